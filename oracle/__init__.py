@@ -1,0 +1,231 @@
+"""ctypes front end of the FP64 CPU oracle (``oracle/ibm_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+CPU-baseline leg of the benchmark.  The GPU library neither imports nor
+links it.  Inputs are widened to float64 before the call, so an FP32 GPU run
+is compared against the oracle fed with exactly the stored FP32 values.
+
+Every function follows §3 of Liu & Stevens (arXiv 2006.03343):
+classes (§3.3 lists), normals (§3.1), the wall model (§3.3,
+eq. bc-bottom-immersed and the tensor rotation), the stress divergence
+(§2.4, eqs. dudx/dudz/dwdz) and the direct forcing (§3.2, eq. u-*-IBM).
+"""
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int, c_long, c_void_p
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("IBM_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
+UV, W = 0, 1
+FLUID, BAND, SOLID = 0, 1, 2
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("nx", c_int), ("ny", c_int), ("nz", c_int),
+                ("dx", c_double), ("dy", c_double), ("dz", c_double)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("band_width", c_double), ("phi_c", c_double), ("kappa", c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"oracle library missing: {LIB_PATH} (run oracle/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = c_void_p
+        L.ora_uv_class.argtypes = [c_double, c_double]
+        L.ora_w_class.argtypes = [c_double, c_double]
+        L.ora_classify.argtypes = [vp, vp, vp, vp, vp]
+        L.ora_normal.argtypes = [vp, vp, c_long, c_long, c_long, vp]
+        L.ora_interp.argtypes = [vp, vp, c_int, vp]
+        L.ora_interp.restype = c_double
+        L.ora_interp_scatter.argtypes = [vp, vp, c_int, vp, c_double]
+        L.ora_local_stress.argtypes = [vp, vp, vp, c_int, c_long, c_long, c_long, vp, vp, vp,
+                                       c_double, vp, vp, vp]
+        L.ora_wall_stress.argtypes = [vp, vp, vp, vp, vp, vp, vp, c_double, vp, vp, vp]
+        L.ora_divergence.argtypes = [vp, vp, vp]
+        L.ora_divergence_transpose.argtypes = [vp, vp, vp]
+        L.ora_forcing.argtypes = [vp, vp, vp, vp, vp, c_double]
+        L.ora_drag.argtypes = [vp, vp, vp, vp, vp]
+        L.ora_counts.argtypes = [vp, vp, vp, vp, vp]
+        L.ora_stage_vjp.argtypes = [vp, vp, vp, vp, vp, vp, vp, c_double, vp, vp, vp, vp, vp,
+                                    vp, vp, vp, vp]
+        L.ora_num_threads.restype = c_int
+        _lib = L
+    return _lib
+
+
+def num_threads():
+    return lib().ora_num_threads()
+
+
+# ------------------------------------------------------------------ helpers
+def _grid(g):
+    return _Grid(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz)
+
+
+def _params(band_width, phi_c, kappa=0.4):
+    return _Params(band_width, phi_c, kappa)
+
+
+def _f64(a, g=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if g is not None and a.shape != (g.nz, g.ny, g.nx):
+        a = np.ascontiguousarray(a.reshape(g.nz, g.ny, g.nx))
+    return a
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data
+
+
+def _parr(arrs):
+    return (c_void_p * len(arrs))(*[_p(a) for a in arrs])
+
+
+# ------------------------------------------------------------------- wrappers
+def uv_class(phi, band_width):
+    return lib().ora_uv_class(float(phi), float(band_width))
+
+
+def w_class(phi, band_width):
+    return lib().ora_w_class(float(phi), float(band_width))
+
+
+def classify(g, band_width, phi_uv, phi_w, phi_c=None):
+    pu, pw = _f64(phi_uv, g), _f64(phi_w, g)
+    mask = np.empty(g.shape, dtype=np.uint8)
+    gr, pr = _grid(g), _params(band_width, phi_c or band_width)
+    lib().ora_classify(ctypes.byref(gr), ctypes.byref(pr), _p(pu), _p(pw), _p(mask))
+    return mask
+
+
+def counts(g, band_width, phi_uv, phi_w):
+    pu, pw = _f64(phi_uv, g), _f64(phi_w, g)
+    out = np.zeros(6, dtype=np.int64)
+    gr, pr = _grid(g), _params(band_width, band_width)
+    lib().ora_counts(ctypes.byref(gr), ctypes.byref(pr), _p(pu), _p(pw), _p(out))
+    return out
+
+
+def normal(g, phi, i, j, k):
+    ph = _f64(phi, g)
+    n = np.zeros(3)
+    gr = _grid(g)
+    lib().ora_normal(ctypes.byref(gr), _p(ph), i, j, k, _p(n))
+    return n
+
+
+def interp(g, f, kind, p):
+    ff = _f64(f, g)
+    pp = np.ascontiguousarray(p, dtype=np.float64)
+    gr = _grid(g)
+    return lib().ora_interp(ctypes.byref(gr), _p(ff), kind, _p(pp))
+
+
+def interp_scatter(g, f, kind, p, value):
+    """Adds value * weights into the float64 array ``f`` in place."""
+    assert f.dtype == np.float64 and f.flags.c_contiguous
+    pp = np.ascontiguousarray(p, dtype=np.float64)
+    gr = _grid(g)
+    lib().ora_interp_scatter(ctypes.byref(gr), _p(f), kind, _p(pp), float(value))
+
+
+def local_stress(g, band_width, phi_c, kappa, phi, kind, i, j, k, u, v, w, ln_ratio):
+    ph, uu, vv, ww = (_f64(a, g) for a in (phi, u, v, w))
+    tau = np.zeros(9)
+    tw = c_double()
+    U = c_double()
+    gr, pr = _grid(g), _params(band_width, phi_c, kappa)
+    lib().ora_local_stress(ctypes.byref(gr), ctypes.byref(pr), _p(ph), kind, i, j, k, _p(uu),
+                           _p(vv), _p(ww), float(ln_ratio), _p(tau), ctypes.byref(tw),
+                           ctypes.byref(U))
+    return tau.reshape(3, 3), tw.value, U.value
+
+
+def wall_stress(g, band_width, phi_c, kappa, phi_uv, phi_w, u, v, w, z0, log_z0, tau):
+    """Returns (tau_out list of 6 arrays, stats[4]); inputs are not modified."""
+    pu, pw, uu, vv, ww = (_f64(a, g) for a in (phi_uv, phi_w, u, v, w))
+    lz = None if log_z0 is None else _f64(log_z0, g)
+    t = [np.array(_f64(a, g), copy=True) for a in tau]
+    stats = np.zeros(4)
+    gr, pr = _grid(g), _params(band_width, phi_c, kappa)
+    lib().ora_wall_stress(ctypes.byref(gr), ctypes.byref(pr), _p(pu), _p(pw), _p(uu), _p(vv),
+                          _p(ww), float(z0), _p(lz), _parr(t), _p(stats))
+    return t, stats
+
+
+def divergence(g, tau):
+    t = [_f64(a, g) for a in tau]
+    div = [np.empty(g.shape) for _ in range(3)]
+    gr = _grid(g)
+    lib().ora_divergence(ctypes.byref(gr), _parr(t), _parr(div))
+    return div
+
+
+def divergence_transpose(g, gdiv):
+    gd = [_f64(a, g) for a in gdiv]
+    gt = [np.zeros(g.shape) for _ in range(6)]
+    gr = _grid(g)
+    lib().ora_divergence_transpose(ctypes.byref(gr), _parr(gd), _parr(gt))
+    return gt
+
+
+def forcing(g, phi_uv, phi_w, ustar, gradp, dt):
+    pu, pw = _f64(phi_uv, g), _f64(phi_w, g)
+    us = [np.array(_f64(a, g), copy=True) for a in ustar]
+    gp = None if gradp is None else [_f64(a, g) for a in gradp]
+    gr = _grid(g)
+    lib().ora_forcing(ctypes.byref(gr), _p(pu), _p(pw), _parr(us),
+                      None if gp is None else _parr(gp), float(dt))
+    return us
+
+
+def drag(g, phi_uv, phi_w, div):
+    pu, pw = _f64(phi_uv, g), _f64(phi_w, g)
+    d = [_f64(a, g) for a in div]
+    out = np.zeros(3)
+    gr = _grid(g)
+    lib().ora_drag(ctypes.byref(gr), _p(pu), _p(pw), _parr(d), _p(out))
+    return out
+
+
+def stage(wl, ustar=None):
+    """One full pass on a ``workloads.configs.Workload``: classes, wall stress,
+    divergence, forcing and drag.  ``ustar`` defaults to (u, v, w)."""
+    g = wl.grid
+    mask = classify(g, wl.band_width, wl.phi_uv, wl.phi_w)
+    cnt = counts(g, wl.band_width, wl.phi_uv, wl.phi_w)
+    tau, stats = wall_stress(g, wl.band_width, wl.phi_c, wl.kappa, wl.phi_uv, wl.phi_w,
+                             wl.u, wl.v, wl.w, wl.z0, wl.log_z0, wl.tau)
+    div = divergence(g, tau)
+    us = forcing(g, wl.phi_uv, wl.phi_w, ustar if ustar is not None else (wl.u, wl.v, wl.w),
+                 wl.gradp, wl.dt)
+    dr = drag(g, wl.phi_uv, wl.phi_w, div)
+    return dict(mask=mask, counts=cnt, tau=tau, stats=stats, div=div, ustar=us, drag=dr)
+
+
+def stage_vjp(wl, g_tau, g_div, g_ustar, g_drag):
+    """Reverse mode of one pass with ustar = u (see ``ora_stage_vjp``)."""
+    g = wl.grid
+    pu, pw, uu, vv, ww = (_f64(a, g) for a in (wl.phi_uv, wl.phi_w, wl.u, wl.v, wl.w))
+    lz = None if wl.log_z0 is None else _f64(wl.log_z0, g)
+    gt = None if g_tau is None else [None if a is None else _f64(a, g) for a in g_tau]
+    gd = [_f64(a, g) for a in g_div]
+    gs = [_f64(a, g) for a in g_ustar]
+    gdr = np.ascontiguousarray(g_drag, dtype=np.float64)
+    gu, gv, gw = (np.empty(g.shape) for _ in range(3))
+    glz = None if lz is None else np.empty(g.shape)
+    gr, pr = _grid(g), _params(wl.band_width, wl.phi_c, wl.kappa)
+    lib().ora_stage_vjp(ctypes.byref(gr), ctypes.byref(pr), _p(pu), _p(pw), _p(uu), _p(vv),
+                        _p(ww), float(wl.z0), _p(lz), None if gt is None else _parr(gt),
+                        _parr(gd), _parr(gs), _p(gdr), _p(gu), _p(gv), _p(gw), _p(glz))
+    return gu, gv, gw, glz
