@@ -1,0 +1,150 @@
+/*
+ * ibm.h -- C ABI of the MI355X (gfx950) wall-modeled immersed boundary stage.
+ *
+ * The stage is the per-time-step part of the simplified wall-modeled IBM of
+ * Liu & Stevens (arXiv 2006.03343, §3): classify the nodes of the staggered
+ * grid by the signed distance phi, model the wall stress in a band of nodes
+ * next to the immersed surface (log law in a local frame), zero the stress
+ * inside the body, take the divergence of the stress and force the
+ * intermediate velocity inside the body.
+ *
+ * Conventions used by every entry point
+ *  - Grid: uniform spacings dx, dy, dz (§2.4, eq. dxdydz); x and y periodic.
+ *  - Fields: contiguous device arrays laid out [nz][ny][nx], x fastest, all of
+ *    the context's storage dtype (float or double), owned by the caller and
+ *    resident on the context's device.  Pointers are plain device addresses.
+ *  - Staggering (§2.4): a "uv" node (i,j,k) sits at (i dx, j dy, (k+1/2) dz),
+ *    a "w" node at (i dx, j dy, k dz).  u, v, tau_xx, tau_yy, tau_zz, tau_xy,
+ *    phi_uv, dp/dx, dp/dy live on uv nodes; w, tau_xz, tau_yz, phi_w, dp/dz on
+ *    w nodes.  Stress component order everywhere: 0 xx, 1 yy, 2 zz, 3 xy,
+ *    4 xz, 5 yz.
+ *  - Streams: ``stream`` is a hipStream_t passed as void* (NULL = the null
+ *    stream).  Per-step calls only enqueue work; they never synchronise.
+ *  - Errors: every function returns 0 (IBM_OK) or a negative IBM_E_* code and
+ *    then leaves a message in ibm_last_error() (thread-local).  Argument
+ *    checks run before anything is enqueued; nothing is thrown across the ABI.
+ *  - Ownership: the library owns the context and everything it allocates
+ *    (masks, band records, run lists, reduction scratch, adjoint maps); no
+ *    call keeps a caller pointer after it returns.
+ */
+#ifndef IBM_H
+#define IBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    IBM_OK = 0,
+    IBM_E_ARG = -1,          /* bad pointer, size, dtype or alignment */
+    IBM_E_STATE = -2,        /* call order: a step before levelset_prepare */
+    IBM_E_HIP = -3,          /* a HIP runtime call failed (message has the HIP error) */
+    IBM_E_NOMEM = -4,        /* device allocation failed */
+    IBM_E_RANGE = -5,        /* parameter out of range, or non-finite phi */
+    IBM_E_UNSUPPORTED = -6   /* e.g. mixed precision with double storage */
+};
+
+enum { IBM_F32 = 0, IBM_F64 = 1 };                 /* storage dtype of every field */
+enum { IBM_PREC_PLAIN = 0, IBM_PREC_MIXED = 1 };   /* mixed: only with IBM_F32 */
+enum { IBM_GRID_UV = 0, IBM_GRID_W = 1 };
+
+typedef struct ibm_ctx ibm_ctx;
+
+typedef struct { int nx, ny, nz; double dx, dy, dz; } ibm_grid;
+
+typedef struct {
+    double band_width;  /* 2 phi_b, a length; §3.3 gives [dz, 1.5 dz) */
+    double phi_c;       /* sample distance from the surface, >= band_width (§3.3); <= 0 -> band_width */
+    double kappa;       /* von Karman constant (§2.2: 0.4) */
+} ibm_params;
+
+/* Create a context for one grid on the current HIP device.
+ * dtype: IBM_F32 or IBM_F64.  precision: IBM_PREC_PLAIN, or IBM_PREC_MIXED
+ * (float storage; double only for small-gradient normal normalisation, the
+ * near-wall log law within one dz of the surface and the drag sums).
+ * Errors: IBM_E_ARG (nx, ny, nz < 1, spacing <= 0 or not finite, or
+ * nx*ny*nz > 2^31 - 1), IBM_E_UNSUPPORTED (mixed with double). */
+int ibm_create(ibm_ctx** out, const ibm_grid* g, int dtype, int precision);
+int ibm_destroy(ibm_ctx* c);
+
+/* §3.1 and §3.3, computed once per geometry (the paper identifies the band
+ * points at initialisation, §5): node classes of both grids, forcing flags
+ * (phi <= 0), normals n = grad phi / |grad phi| at band nodes, and for every
+ * band node the trilinear stencil of its sample point x + (phi_c - phi) n.
+ * phi_uv, phi_w: device fields (context dtype) of the signed distance at the
+ * uv and w nodes (+ fluid, - solid).  Synchronises ``stream``: it reads back
+ * counts.  Errors: IBM_E_RANGE for band_width <= 0, phi_c < band_width,
+ * kappa <= 0 or any non-finite phi. May be called again for a new geometry. */
+int ibm_levelset_prepare(ibm_ctx* c, const void* phi_uv, const void* phi_w,
+                         const ibm_params* p, void* stream);
+
+/* Host copies of what prepare found.  counts: uv fluid, uv band, uv solid,
+ * w fluid, w band, w solid.  band_size: number of band records of a grid.
+ * band_export: ascending linear indices (and, if normals != NULL, 3 doubles
+ * per record: the stored normal).  mask_export: one byte per linear index,
+ * bits 0-1 uv class (0 fluid, 1 band, 2 solid), bits 2-3 w class, bit 4 uv
+ * node forced, bit 5 w node forced. Errors: IBM_E_STATE before prepare. */
+int ibm_counts(const ibm_ctx* c, int64_t out[6]);
+int ibm_band_size(const ibm_ctx* c, int grid, int64_t* n);
+int ibm_band_export(const ibm_ctx* c, int grid, int32_t* idx_host, double* normals_host);
+int ibm_mask_export(const ibm_ctx* c, uint8_t* mask_host);
+
+/* §3.3 wall model, eq. bc-bottom-immersed, in place on tau[6].
+ * On entry tau holds the SGS stress; on return band nodes hold the modeled
+ * wall stress (uv band: xx, yy, zz, xy; w band: xz, yz), solid nodes hold 0
+ * on their grid's components and fluid nodes are untouched.
+ * u, v (uv nodes) and w (w nodes) are sampled at the band nodes' sample
+ * points.  Roughness: the scalar z0 (0 < z0 < phi_c) when log_z0 is NULL,
+ * else the per-node field log_z0 (context dtype) read at the band node.
+ * stats_dev: NULL or 4 device doubles receiving [sum tau_w over uv band
+ * nodes, sum tau_w over w band nodes, max |U_r| over band nodes, number of
+ * band nodes].  Asynchronous on ``stream``.  Errors: IBM_E_STATE, IBM_E_ARG,
+ * IBM_E_RANGE (bad z0). */
+int ibm_wall_stress(ibm_ctx* c, const void* u, const void* v, const void* w, double z0,
+                    const void* log_z0, void* const tau[6], double* stats_dev, void* stream);
+
+/* Stress divergence (§2.4 differences: second-order central in x and y,
+ * periodic; staggered second-order in z, stress outside 0 <= k < nz taken as
+ * 0) and direct forcing (§3.2, eq. u-*-IBM), one dense pass.
+ * div[0], div[1] (uv nodes) and div[2] (w nodes) receive +div(tau); they may
+ * not alias tau.  ustar[3] is updated in place: at nodes with phi <= 0 on the
+ * component's own grid it becomes (3 dt / 2) gradp (gradp == NULL or an
+ * entry NULL: 0); elsewhere it is untouched.  drag_dev: NULL or 3 device
+ * doubles receiving D_c = dx dy dz * sum of div_c over the nodes of the
+ * component's grid with phi > 0.  Asynchronous on ``stream``.
+ * Errors: IBM_E_STATE, IBM_E_ARG. */
+int ibm_apply(ibm_ctx* c, const void* const tau[6], void* const ustar[3],
+              const void* const gradp[3], double dt, void* const div[3], double* drag_dev,
+              void* stream);
+
+/* Reverse mode of one stage pass with respect to u, v, w and log z0, for a
+ * single velocity state that is both sampled by the wall model and forced
+ * (ustar == u).  Cotangents: g_tau[6] (array or entries may be NULL = 0) of
+ * the wall-modeled stress, g_div[3] of the divergence, g_ustar[3] of the
+ * forced velocity, g_drag[3] (host doubles) of the drag.  Outputs gu, gv,
+ * gw (overwritten) and glog_z0 (overwritten; NULL allowed, required NULL
+ * when log_z0 is NULL).  The first call after a prepare builds the transposed
+ * stencil map (synchronous); later calls are asynchronous on ``stream``. */
+int ibm_stage_vjp(ibm_ctx* c, const void* u, const void* v, const void* w, double z0,
+                  const void* log_z0, const void* const g_tau[6], const void* const g_div[3],
+                  const void* const g_ustar[3], const double g_drag[3], void* gu, void* gv,
+                  void* gw, void* glog_z0, void* stream);
+
+/* Tile shape of the dense pass (ibm_apply): a wave owns vx*64 nodes along x,
+ * ty rows and kz planes; wpb waves per block.  vx in {1,2,4} (double: {1,2})
+ * and must divide nx; ty in {1,2,4,8}; kz >= 1; wpb in 1..4.  The shape only
+ * changes speed and the summation order of the drag, never the divergence or
+ * forcing values.  ibm_get_tile reports the shape in use (the default comes
+ * from the grid size).  Errors: IBM_E_ARG for an unsupported shape. */
+int ibm_set_tile(ibm_ctx* c, int vx, int ty, int kz, int wpb);
+int ibm_get_tile(const ibm_ctx* c, int out[4]);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* ibm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,235 @@
+"""MI355X wall-modeled immersed boundary stage (Liu & Stevens, arXiv 2006.03343, §3).
+
+A thin binding over the C ABI of ``libibm.so`` (``include/ibm.h``): argument
+marshalling only.  Torch tensors provide device memory and the current
+stream; every step of the stage runs in the library's HIP kernels.
+
+    ctx = Context(nx, ny, nz, dtype=torch.float32, precision="mixed")
+    ctx.prepare(phi_uv, phi_w, band_width=1.5)          # once per geometry
+    ctx.wall_stress(u, v, w, tau, z0=1e-4)               # each step
+    ctx.apply(tau, ustar, div, gradp=gp, dt=0.01, drag=drag)
+"""
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import (IBM_F32, IBM_F64, IBM_GRID_UV, IBM_GRID_W, IBM_PREC_MIXED, IBM_PREC_PLAIN,
+                   IbmError, IbmGrid, IbmParams, check, ptr_array)
+
+__all__ = ["Context", "IBMStage", "IbmError", "stage_forward"]
+
+_DTYPES = {torch.float32: IBM_F32, torch.float64: IBM_F64}
+_PREC = {"plain": IBM_PREC_PLAIN, "mixed": IBM_PREC_MIXED}
+
+
+class Context:
+    """One grid on one GPU: owns the library context (masks, band records)."""
+
+    def __init__(self, nx, ny, nz, dx=1.0, dy=1.0, dz=1.0, dtype=torch.float32,
+                 precision="plain", device=None):
+        self._lib = _lib.load()
+        if dtype not in _DTYPES:
+            raise TypeError(f"dtype must be float32 or float64, got {dtype}")
+        self.device = torch.device(device if device is not None else "cuda")
+        if self.device.type != "cuda":
+            raise ValueError("the IBM stage runs on a GPU device")
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.shape = (int(nz), int(ny), int(nx))
+        self.n = int(nx) * int(ny) * int(nz)
+        self.dtype = dtype
+        self.precision = precision
+        self.spacing = (float(dx), float(dy), float(dz))
+        self._h = ctypes_void()
+        g = IbmGrid(int(nx), int(ny), int(nz), float(dx), float(dy), float(dz))
+        with torch.cuda.device(self.device):
+            check(self._lib.ibm_create(_byref(self._h), _byref(g), _DTYPES[dtype], _PREC[precision]))
+        self.params = None
+
+    # ------------------------------------------------------------- plumbing
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.ibm_destroy(self._h)
+            self._h = ctypes_void()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self):
+        return torch.cuda.current_stream(self.device).cuda_stream
+
+    def _field(self, t, name, dtype=None):
+        if t is None:
+            return None
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch.Tensor")
+        if t.device != self.device:
+            raise ValueError(f"{name} is on {t.device}, the context is on {self.device}")
+        if t.dtype != (dtype or self.dtype):
+            raise TypeError(f"{name} has dtype {t.dtype}, expected {dtype or self.dtype}")
+        if not t.is_contiguous() or t.numel() != self.n:
+            raise ValueError(f"{name} must be contiguous with {self.n} elements {self.shape}")
+        return t.data_ptr()
+
+    def _fields(self, ts, name, count, optional=False):
+        if ts is None:
+            if optional:
+                return None
+            raise ValueError(f"{name} is required")
+        ts = list(ts)
+        if len(ts) != count:
+            raise ValueError(f"{name} needs {count} fields")
+        return [self._field(t, f"{name}[{i}]") for i, t in enumerate(ts)]
+
+    # --------------------------------------------------------------- set-up
+    def prepare(self, phi_uv, phi_w, band_width, phi_c=None, kappa=0.4):
+        """Classes, normals and band records from the signed distance (once per geometry)."""
+        p = IbmParams(float(band_width), float(phi_c) if phi_c else -1.0, float(kappa))
+        with torch.cuda.device(self.device):
+            check(self._lib.ibm_levelset_prepare(self._h, self._field(phi_uv, "phi_uv"),
+                                                 self._field(phi_w, "phi_w"), _byref(p),
+                                                 self._stream()))
+        self.params = (float(band_width), float(phi_c) if phi_c else float(band_width), float(kappa))
+
+    def counts(self):
+        out = np.zeros(6, dtype=np.int64)
+        check(self._lib.ibm_counts(self._h, out.ctypes.data_as(_lib.POINTER(_lib.c_int64))))
+        return out
+
+    def band_size(self, grid):
+        n = _lib.c_int64(0)
+        check(self._lib.ibm_band_size(self._h, grid, _byref(n)))
+        return int(n.value)
+
+    def band(self, grid):
+        """(ascending linear indices, stored normals as float64 (n, 3)) of a grid's band nodes."""
+        n = self.band_size(grid)
+        idx = np.zeros(n, dtype=np.int32)
+        nrm = np.zeros((n, 3), dtype=np.float64)
+        check(self._lib.ibm_band_export(self._h, grid, idx.ctypes.data, nrm.ctypes.data))
+        return idx, nrm
+
+    def mask(self):
+        m = np.zeros(self.shape, dtype=np.uint8)
+        check(self._lib.ibm_mask_export(self._h, m.ctypes.data))
+        return m
+
+    def set_tile(self, vx, ty, kz, wpb=4):
+        """Tile shape of the dense pass (speed only; see ibm_set_tile)."""
+        check(self._lib.ibm_set_tile(self._h, int(vx), int(ty), int(kz), int(wpb)))
+
+    def get_tile(self):
+        out = np.zeros(4, dtype=np.int32)
+        check(self._lib.ibm_get_tile(self._h, out.ctypes.data))
+        return tuple(int(x) for x in out)
+
+    # ------------------------------------------------------------ each step
+    def wall_stress(self, u, v, w, tau, z0=None, log_z0=None, stats=None):
+        """Wall-modeled stress written in place into ``tau`` (6 fields).
+        ``stats``: optional float64 tensor of 4 on the device."""
+        if (z0 is None) == (log_z0 is None):
+            raise ValueError("give exactly one of z0 and log_z0")
+        taus = self._fields(tau, "tau", 6)
+        sp = None
+        if stats is not None:
+            if stats.dtype != torch.float64 or stats.numel() < 4 or stats.device != self.device:
+                raise ValueError("stats must be a float64 device tensor with 4 elements")
+            sp = stats.data_ptr()
+        with torch.cuda.device(self.device):
+            check(self._lib.ibm_wall_stress(self._h, self._field(u, "u"), self._field(v, "v"),
+                                            self._field(w, "w"), float(z0 or 0.0),
+                                            self._field(log_z0, "log_z0"), ptr_array(taus), sp,
+                                            self._stream()))
+
+    def apply(self, tau, ustar, div, gradp=None, dt=0.01, drag=None):
+        """div = +div(tau); ustar forced in place where phi <= 0; drag (float64[3]) optional."""
+        taus = self._fields(tau, "tau", 6)
+        us = self._fields(ustar, "ustar", 3)
+        dv = self._fields(div, "div", 3)
+        gp = None
+        if gradp is not None:
+            gp = ptr_array([self._field(t, f"gradp[{i}]") for i, t in enumerate(gradp)])
+        dp = None
+        if drag is not None:
+            if drag.dtype != torch.float64 or drag.numel() < 3 or drag.device != self.device:
+                raise ValueError("drag must be a float64 device tensor with 3 elements")
+            dp = drag.data_ptr()
+        with torch.cuda.device(self.device):
+            check(self._lib.ibm_apply(self._h, ptr_array(taus), ptr_array(us), gp, float(dt),
+                                      ptr_array(dv), dp, self._stream()))
+
+    def vjp(self, u, v, w, g_div, g_ustar, g_drag, z0=None, log_z0=None, g_tau=None):
+        """Reverse mode of one pass (ustar == u): returns (gu, gv, gw, glog_z0 or None)."""
+        if (z0 is None) == (log_z0 is None):
+            raise ValueError("give exactly one of z0 and log_z0")
+        gd = self._fields(g_div, "g_div", 3)
+        gs = self._fields(g_ustar, "g_ustar", 3)
+        gt = None
+        if g_tau is not None:
+            gt = ptr_array([self._field(t, f"g_tau[{i}]") if t is not None else None
+                            for i, t in enumerate(g_tau)])
+        gdr = (_lib.c_double * 3)(*[float(x) for x in g_drag])
+        gu, gv, gw = (torch.empty(self.shape, dtype=self.dtype, device=self.device) for _ in range(3))
+        glz = torch.empty_like(gu) if log_z0 is not None else None
+        with torch.cuda.device(self.device):
+            check(self._lib.ibm_stage_vjp(self._h, self._field(u, "u"), self._field(v, "v"),
+                                          self._field(w, "w"), float(z0 or 0.0),
+                                          self._field(log_z0, "log_z0"), gt, ptr_array(gd),
+                                          ptr_array(gs), gdr, gu.data_ptr(), gv.data_ptr(),
+                                          gw.data_ptr(), glz.data_ptr() if glz is not None else None,
+                                          self._stream()))
+        return gu, gv, gw, glz
+
+
+def stage_forward(context, u, v, w, tau_sgs, gradp=None, dt=0.01, z0=None, log_z0=None):
+    """One out-of-place pass: returns (tau (6,...), div (3,...), ustar_ib (3,...), drag (3,))."""
+    tau = torch.stack(list(tau_sgs)).contiguous() if not isinstance(tau_sgs, torch.Tensor) \
+        else tau_sgs.clone()
+    context.wall_stress(u, v, w, list(tau), z0=z0, log_z0=log_z0)
+    ustar = torch.stack([u, v, w]).contiguous()
+    div = torch.empty_like(ustar)
+    drag = torch.zeros(3, dtype=torch.float64, device=context.device)
+    context.apply(list(tau), list(ustar), list(div), gradp=gradp, dt=dt, drag=drag)
+    return tau, div, ustar, drag
+
+
+class IBMStage(torch.autograd.Function):
+    """Differentiable stage pass with respect to u, v, w and a per-node log z0.
+
+    ``IBMStage.apply(context, u, v, w, log_z0, tau_sgs, gradp, dt)`` returns
+    (tau, div, ustar_ib, drag).  The velocity is both sampled by the wall model
+    and forced (ustar = u), out of place.  The backward is the library's
+    hand-written adjoint (ibm_stage_vjp).
+    """
+
+    @staticmethod
+    def forward(ctx, context, u, v, w, log_z0, tau_sgs, gradp, dt):
+        tau, div, ustar, drag = stage_forward(context, u, v, w, tau_sgs, gradp, dt,
+                                              log_z0=log_z0)
+        ctx.context = context
+        ctx.save_for_backward(u, v, w, log_z0)
+        return tau, div, ustar, drag
+
+    @staticmethod
+    def backward(ctx, g_tau, g_div, g_ustar, g_drag):
+        u, v, w, log_z0 = ctx.saved_tensors
+        c = ctx.context
+        z = lambda: torch.zeros(c.shape, dtype=c.dtype, device=c.device)
+        gd = [g_div[i].contiguous() if g_div is not None else z() for i in range(3)]
+        gs = [g_ustar[i].contiguous() if g_ustar is not None else z() for i in range(3)]
+        gt = None if g_tau is None else [g_tau[i].contiguous() for i in range(6)]
+        gdr = [0.0, 0.0, 0.0] if g_drag is None else g_drag.detach().double().cpu().tolist()
+        gu, gv, gw, glz = c.vjp(u, v, w, gd, gs, gdr, log_z0=log_z0, g_tau=gt)
+        return None, gu, gv, gw, glz, None, None, None
+
+
+# small ctypes helpers kept local to avoid importing ctypes names everywhere
+def ctypes_void():
+    return _lib.c_void_p()
+
+
+def _byref(x):
+    return _lib.ctypes.byref(x)

@@ -1,0 +1,317 @@
+// api.hip -- the extern "C" entry points declared in include/ibm.h: argument
+// checks, context lifetime, error reporting and stream plumbing.  All numeric
+// work is in prepare.hip, stage.hip and vjp.hip.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "ibm_impl.h"
+
+namespace ibm {
+
+namespace {
+thread_local char g_err[512] = "";
+}
+
+int fail(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(e == hipErrorOutOfMemory ? IBM_E_NOMEM : IBM_E_HIP, "%s: %s", what,
+                hipGetErrorString(e));
+}
+
+size_t tsize(const ibm_ctx* c) { return c->dtype == IBM_F64 ? 8 : 4; }
+
+namespace {
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+int check_ctx(const ibm_ctx* c, bool need_prepared, const char* fn) {
+    if (!c) return fail(IBM_E_ARG, "%s: context is NULL", fn);
+    if (need_prepared && !c->prepared)
+        return fail(IBM_E_STATE, "%s: call ibm_levelset_prepare first", fn);
+    return IBM_OK;
+}
+
+int check_field(const ibm_ctx* c, const void* p, const char* fn, const char* name,
+                bool vec_aligned = false) {
+    if (!p) return fail(IBM_E_ARG, "%s: %s is NULL", fn, name);
+    const uintptr_t a = (uintptr_t)p;
+    if (a % tsize(c)) return fail(IBM_E_ARG, "%s: %s is not aligned to its element size", fn, name);
+    if (vec_aligned && a % 16)
+        return fail(IBM_E_ARG, "%s: %s must be 16-byte aligned", fn, name);
+    return IBM_OK;
+}
+
+// RAII: make the context's device current for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+}  // namespace ibm
+
+using namespace ibm;
+
+extern "C" {
+
+const char* ibm_last_error(void) { return ibm::g_err; }
+
+int ibm_create(ibm_ctx** out, const ibm_grid* g, int dtype, int precision) {
+    g_err[0] = 0;
+    if (!out || !g) return fail(IBM_E_ARG, "ibm_create: NULL argument");
+    *out = nullptr;
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1)
+        return fail(IBM_E_ARG, "ibm_create: grid sizes must be >= 1 (got %d %d %d)", g->nx, g->ny,
+                    g->nz);
+    if (!finite_pos(g->dx) || !finite_pos(g->dy) || !finite_pos(g->dz))
+        return fail(IBM_E_ARG, "ibm_create: grid spacings must be finite and > 0");
+    const long n = (long)g->nx * g->ny * g->nz;
+    if (n > 2147483647L) return fail(IBM_E_ARG, "ibm_create: nx*ny*nz exceeds 2^31-1");
+    if (dtype != IBM_F32 && dtype != IBM_F64) return fail(IBM_E_ARG, "ibm_create: bad dtype %d", dtype);
+    if (precision != IBM_PREC_PLAIN && precision != IBM_PREC_MIXED)
+        return fail(IBM_E_ARG, "ibm_create: bad precision %d", precision);
+    if (precision == IBM_PREC_MIXED && dtype != IBM_F32)
+        return fail(IBM_E_UNSUPPORTED, "ibm_create: mixed precision needs float storage");
+    ibm_ctx* c = new (std::nothrow) ibm_ctx();
+    if (!c) return fail(IBM_E_NOMEM, "ibm_create: out of host memory");
+    c->g = *g;
+    c->dtype = dtype;
+    c->precision = precision;
+    c->n = n;
+    hipError_t e = hipGetDevice(&c->device);
+    if (e != hipSuccess) {
+        delete c;
+        return hip_fail(e, "hipGetDevice");
+    }
+    e = hipMalloc(&c->counters, 4 * sizeof(unsigned));
+    if (e == hipSuccess) e = hipMemset(c->counters, 0, 4 * sizeof(unsigned));
+    if (e != hipSuccess) {
+        (void)hipFree(c->counters);
+        delete c;
+        return hip_fail(e, "ibm_create: counters");
+    }
+    c->cfg = default_tile(c);
+    *out = c;
+    return IBM_OK;
+}
+
+int ibm_destroy(ibm_ctx* c) {
+    if (!c) return IBM_OK;
+    DeviceGuard dg(c->device);
+    free_prepared(c);
+    (void)hipFree(c->ws_partials);
+    (void)hipFree(c->ap_partials);
+    (void)hipFree(c->counters);
+    delete c;
+    return IBM_OK;
+}
+
+int ibm_levelset_prepare(ibm_ctx* c, const void* phi_uv, const void* phi_w, const ibm_params* p,
+                         void* stream) {
+    g_err[0] = 0;
+    int rc = check_ctx(c, false, "ibm_levelset_prepare");
+    if (rc) return rc;
+    if (!p) return fail(IBM_E_ARG, "ibm_levelset_prepare: params is NULL");
+    if ((rc = check_field(c, phi_uv, "ibm_levelset_prepare", "phi_uv"))) return rc;
+    if ((rc = check_field(c, phi_w, "ibm_levelset_prepare", "phi_w"))) return rc;
+    ibm_params q = *p;
+    if (!(q.phi_c > 0.0)) q.phi_c = q.band_width;
+    if (!finite_pos(q.band_width))
+        return fail(IBM_E_RANGE, "ibm_levelset_prepare: band_width must be finite and > 0");
+    if (!std::isfinite(q.phi_c) || q.phi_c < q.band_width)
+        return fail(IBM_E_RANGE, "ibm_levelset_prepare: phi_c must be >= band_width (phi_c >= 2 phi_b)");
+    if (!finite_pos(q.kappa)) return fail(IBM_E_RANGE, "ibm_levelset_prepare: kappa must be > 0");
+    DeviceGuard dg(c->device);
+    c->p = q;
+    rc = prepare(c, phi_uv, phi_w, (hipStream_t)stream);
+    if (rc) return rc;
+    return size_partials(c);
+}
+
+int ibm_counts(const ibm_ctx* c, int64_t out[6]) {
+    int rc = check_ctx(c, true, "ibm_counts");
+    if (rc) return rc;
+    if (!out) return fail(IBM_E_ARG, "ibm_counts: out is NULL");
+    for (int i = 0; i < 6; ++i) out[i] = c->counts[i];
+    return IBM_OK;
+}
+
+int ibm_band_size(const ibm_ctx* c, int grid, int64_t* n) {
+    int rc = check_ctx(c, true, "ibm_band_size");
+    if (rc) return rc;
+    if ((grid != IBM_GRID_UV && grid != IBM_GRID_W) || !n)
+        return fail(IBM_E_ARG, "ibm_band_size: bad grid or NULL output");
+    *n = c->rec[grid].n;
+    return IBM_OK;
+}
+
+int ibm_band_export(const ibm_ctx* c, int grid, int32_t* idx_host, double* normals_host) {
+    int rc = check_ctx(c, true, "ibm_band_export");
+    if (rc) return rc;
+    if ((grid != IBM_GRID_UV && grid != IBM_GRID_W) || !idx_host)
+        return fail(IBM_E_ARG, "ibm_band_export: bad grid or NULL output");
+    DeviceGuard dg(c->device);
+    const Records& R = c->rec[grid];
+    if (R.n == 0) return IBM_OK;
+    IBM_HIP(hipMemcpy(idx_host, R.q, sizeof(int32_t) * R.n, hipMemcpyDeviceToHost));
+    if (normals_host) {
+        std::vector<char> tmp(tsize(c) * R.n);
+        for (int d = 0; d < 3; ++d) {
+            IBM_HIP(hipMemcpy(tmp.data(), R.nrm[d], tmp.size(), hipMemcpyDeviceToHost));
+            for (long r = 0; r < R.n; ++r)
+                normals_host[3 * r + d] = c->dtype == IBM_F64 ? ((double*)tmp.data())[r]
+                                                               : (double)((float*)tmp.data())[r];
+        }
+    }
+    return IBM_OK;
+}
+
+int ibm_mask_export(const ibm_ctx* c, uint8_t* mask_host) {
+    int rc = check_ctx(c, true, "ibm_mask_export");
+    if (rc) return rc;
+    if (!mask_host) return fail(IBM_E_ARG, "ibm_mask_export: NULL output");
+    DeviceGuard dg(c->device);
+    IBM_HIP(hipMemcpy(mask_host, c->mask, (size_t)c->n, hipMemcpyDeviceToHost));
+    return IBM_OK;
+}
+
+int ibm_wall_stress(ibm_ctx* c, const void* u, const void* v, const void* w, double z0,
+                    const void* log_z0, void* const tau[6], double* stats_dev, void* stream) {
+    g_err[0] = 0;
+    const char* fn = "ibm_wall_stress";
+    int rc = check_ctx(c, true, fn);
+    if (rc) return rc;
+    if ((rc = check_field(c, u, fn, "u")) || (rc = check_field(c, v, fn, "v")) ||
+        (rc = check_field(c, w, fn, "w")))
+        return rc;
+    if (!tau) return fail(IBM_E_ARG, "%s: tau is NULL", fn);
+    for (int i = 0; i < 6; ++i)
+        if ((rc = check_field(c, tau[i], fn, "tau[i]"))) return rc;
+    if (log_z0) {
+        if ((rc = check_field(c, log_z0, fn, "log_z0"))) return rc;
+    } else if (!(z0 > 0.0) || !(z0 < c->p.phi_c)) {
+        return fail(IBM_E_RANGE, "%s: z0 must satisfy 0 < z0 < phi_c (got %g)", fn, z0);
+    }
+    if (stats_dev && ((uintptr_t)stats_dev % 8))
+        return fail(IBM_E_ARG, "%s: stats_dev misaligned", fn);
+    DeviceGuard dg(c->device);
+    return launch_wall_stress(c, u, v, w, z0, log_z0, tau, stats_dev, (hipStream_t)stream);
+}
+
+int ibm_apply(ibm_ctx* c, const void* const tau[6], void* const ustar[3],
+              const void* const gradp[3], double dt, void* const div[3], double* drag_dev,
+              void* stream) {
+    g_err[0] = 0;
+    const char* fn = "ibm_apply";
+    int rc = check_ctx(c, true, fn);
+    if (rc) return rc;
+    if (!tau || !ustar || !div) return fail(IBM_E_ARG, "%s: tau, ustar and div are required", fn);
+    if (!std::isfinite(dt)) return fail(IBM_E_ARG, "%s: dt must be finite", fn);
+    TileCfg cfg = c->cfg;
+    bool vec = cfg.vx > 1;
+    for (int pass = 0; pass < 2; ++pass) {
+        bool ok = true;
+        for (int i = 0; i < 6 && ok; ++i)
+            ok = tau[i] && (uintptr_t)tau[i] % (vec ? 16 : tsize(c)) == 0;
+        for (int i = 0; i < 3 && ok; ++i) ok = div[i] && (uintptr_t)div[i] % (vec ? 16 : tsize(c)) == 0;
+        if (ok) break;
+        if (!vec) break;
+        cfg.vx = 1;   // a misaligned view: fall back to one element per lane
+        vec = false;
+    }
+    for (int i = 0; i < 6; ++i)
+        if ((rc = check_field(c, tau[i], fn, "tau[i]"))) return rc;
+    for (int i = 0; i < 3; ++i) {
+        if ((rc = check_field(c, div[i], fn, "div[i]"))) return rc;
+        if ((rc = check_field(c, ustar[i], fn, "ustar[i]"))) return rc;
+        if (gradp && gradp[i] && (rc = check_field(c, gradp[i], fn, "gradp[i]"))) return rc;
+        for (int j = 0; j < 6; ++j)
+            if (div[i] == tau[j]) return fail(IBM_E_ARG, "%s: div may not alias tau", fn);
+    }
+    if (drag_dev && ((uintptr_t)drag_dev % 8)) return fail(IBM_E_ARG, "%s: drag_dev misaligned", fn);
+    DeviceGuard dg(c->device);
+    return launch_apply(c, cfg, tau, ustar, gradp, dt, div, drag_dev, (hipStream_t)stream);
+}
+
+int ibm_set_tile(ibm_ctx* c, int vx, int ty, int kz, int wpb) {
+    g_err[0] = 0;
+    int rc = check_ctx(c, false, "ibm_set_tile");
+    if (rc) return rc;
+    TileCfg t;
+    t.vx = vx;
+    t.ty = ty;
+    t.kz = kz;
+    t.wpb = wpb;
+    if (!tile_supported(c, t))
+        return fail(IBM_E_ARG, "ibm_set_tile: unsupported shape vx=%d ty=%d kz=%d wpb=%d", vx, ty,
+                    kz, wpb);
+    DeviceGuard dg(c->device);
+    c->cfg = t;
+    return c->prepared ? size_partials(c) : IBM_OK;
+}
+
+int ibm_get_tile(const ibm_ctx* c, int out[4]) {
+    int rc = check_ctx(c, false, "ibm_get_tile");
+    if (rc) return rc;
+    if (!out) return fail(IBM_E_ARG, "ibm_get_tile: NULL output");
+    out[0] = c->cfg.vx;
+    out[1] = c->cfg.ty;
+    out[2] = c->cfg.kz;
+    out[3] = c->cfg.wpb;
+    return IBM_OK;
+}
+
+int ibm_stage_vjp(ibm_ctx* c, const void* u, const void* v, const void* w, double z0,
+                  const void* log_z0, const void* const g_tau[6], const void* const g_div[3],
+                  const void* const g_ustar[3], const double g_drag[3], void* gu, void* gv,
+                  void* gw, void* glog_z0, void* stream) {
+    g_err[0] = 0;
+    const char* fn = "ibm_stage_vjp";
+    int rc = check_ctx(c, true, fn);
+    if (rc) return rc;
+    if ((rc = check_field(c, u, fn, "u")) || (rc = check_field(c, v, fn, "v")) ||
+        (rc = check_field(c, w, fn, "w")) || (rc = check_field(c, gu, fn, "gu")) ||
+        (rc = check_field(c, gv, fn, "gv")) || (rc = check_field(c, gw, fn, "gw")))
+        return rc;
+    if (!g_div || !g_ustar || !g_drag)
+        return fail(IBM_E_ARG, "%s: g_div, g_ustar and g_drag are required", fn);
+    for (int i = 0; i < 3; ++i) {
+        if ((rc = check_field(c, g_div[i], fn, "g_div[i]"))) return rc;
+        if ((rc = check_field(c, g_ustar[i], fn, "g_ustar[i]"))) return rc;
+        if (!std::isfinite(g_drag[i])) return fail(IBM_E_ARG, "%s: g_drag must be finite", fn);
+    }
+    if (g_tau)
+        for (int i = 0; i < 6; ++i)
+            if (g_tau[i] && (rc = check_field(c, g_tau[i], fn, "g_tau[i]"))) return rc;
+    if (log_z0) {
+        if ((rc = check_field(c, log_z0, fn, "log_z0"))) return rc;
+    } else {
+        if (glog_z0) return fail(IBM_E_ARG, "%s: glog_z0 needs a log_z0 field", fn);
+        if (!(z0 > 0.0) || !(z0 < c->p.phi_c))
+            return fail(IBM_E_RANGE, "%s: z0 must satisfy 0 < z0 < phi_c (got %g)", fn, z0);
+    }
+    if (glog_z0 && (rc = check_field(c, glog_z0, fn, "glog_z0"))) return rc;
+    DeviceGuard dg(c->device);
+    return stage_vjp(c, u, v, w, z0, log_z0, g_tau, g_div, g_ustar, g_drag, gu, gv, gw, glog_z0,
+                     (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,151 @@
+// ibm_impl.h -- internal types of the MI355X wall-modeled IBM library.
+//
+// Data kept on the device per context (all owned by the library):
+//  * mask    : one byte per linear index (classes of both grids + forcing flags)
+//  * fmask   : forcing flags packed 2 bits per node (bit 2t: uv forced, bit 2t+1:
+//              w forced) in 32-bit words, rows padded to whole words; the dense
+//              pass reads 1/4 byte per node instead of the whole mask byte
+//  * records : one structure-of-arrays per grid with the band nodes in ascending
+//              linear index: index, unit normal, phi, and the trilinear stencil of
+//              the sample point on the uv and on the w node set
+//  * chunks  : runs of solid nodes along x, split into pieces of at most
+//              kChunk nodes, whose stress components are zeroed each step
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "ibm.h"
+
+namespace ibm {
+
+constexpr int kWave = 64;
+constexpr int kChunk = 1024;
+constexpr int kBandBlock = 256;
+
+// Band records of one grid.  T arrays are the context's storage type.
+struct Records {
+    long n = 0;
+    void* buf = nullptr;
+    int32_t* q = nullptr;     // linear index of the band node
+    int32_t* base = nullptr;  // j0 * nx + i0: lower corner column of the sample stencil
+    int32_t* sx = nullptr;    // x step to the upper corner (1 or 1 - nx across the seam)
+    int32_t* sy = nullptr;    // y step (nx or (1 - ny) * nx)
+    int32_t* ku = nullptr;    // lower vertical index of the uv-grid stencil
+    int32_t* kw = nullptr;    // lower vertical index of the w-grid stencil
+    void* nrm[3] = {nullptr, nullptr, nullptr};
+    void* phi = nullptr;
+    void* fx = nullptr;       // fractions of the stencil
+    void* fy = nullptr;
+    void* fzu = nullptr;
+    void* fzw = nullptr;
+};
+
+template <typename T>
+struct RecView {
+    long n;
+    const int32_t *q, *base, *sx, *sy, *ku, *kw;
+    const T *nx, *ny, *nz, *phi, *fx, *fy, *fzu, *fzw;
+};
+
+template <typename T>
+inline RecView<T> view(const Records& r) {
+    return RecView<T>{r.n, r.q, r.base, r.sx, r.sy, r.ku, r.kw,
+                      (const T*)r.nrm[0], (const T*)r.nrm[1], (const T*)r.nrm[2],
+                      (const T*)r.phi, (const T*)r.fx, (const T*)r.fy,
+                      (const T*)r.fzu, (const T*)r.fzw};
+}
+
+struct Chunk {
+    int32_t q;     // first linear index of the run piece
+    int32_t len;   // number of nodes (<= kChunk)
+    int32_t grid;  // IBM_GRID_UV: zero xx, yy, zz, xy; IBM_GRID_W: zero xz, yz
+    int32_t pad;
+};
+
+// Tile shape of the dense pass: a wave owns 64*vx points along x, ty rows and
+// up to kz planes; wpb waves per block.
+struct TileCfg {
+    int vx = 4, ty = 4, kz = 16, wpb = 4;
+};
+
+// Transposed sample-stencil map for the reverse mode (built on first use).
+struct AdjointMap {
+    bool built = false;
+    long m[2] = {0, 0};          // number of distinct touched nodes (uv grid, w grid)
+    long e[2] = {0, 0};          // number of entries
+    int32_t* node[2] = {nullptr, nullptr};
+    int32_t* off[2] = {nullptr, nullptr};
+    int32_t* rec[2] = {nullptr, nullptr};   // record index in [uv records | w records]
+    int32_t* corner[2] = {nullptr, nullptr};
+    void* rbar = nullptr;        // per-record sample-velocity cotangents, 3 x (nuv + nw)
+};
+
+}  // namespace ibm
+
+struct ibm_ctx {
+    int device = 0;
+    ibm_grid g{};
+    int dtype = IBM_F32;
+    int precision = IBM_PREC_PLAIN;
+    ibm_params p{};
+    bool prepared = false;
+    long n = 0;
+    int wrow = 0;                       // 32-bit fmask words per row
+    uint8_t* mask = nullptr;
+    uint32_t* fmask = nullptr;
+    int64_t counts[6] = {0, 0, 0, 0, 0, 0};
+    ibm::Records rec[2];
+    long nchunks = 0;
+    ibm::Chunk* chunks = nullptr;
+    double* ws_partials = nullptr;      // wall_stress block slots (4 per band block)
+    long ws_cap = 0;                    // in doubles
+    double* ap_partials = nullptr;      // apply wave slots (3 per tile)
+    long ap_cap = 0;                    // in doubles
+    unsigned* counters = nullptr;       // [0] apply, [1] wall_stress, [2..3] spare
+    ibm::TileCfg cfg;
+    ibm::AdjointMap adj;
+};
+
+namespace ibm {
+
+// Thread-local error message and helpers (api.hip).
+int fail(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+size_t tsize(const ibm_ctx* c);
+
+// prepare.hip
+int prepare(ibm_ctx* c, const void* phi_uv, const void* phi_w, hipStream_t s);
+void free_prepared(ibm_ctx* c);
+
+// stage.hip
+int launch_wall_stress(ibm_ctx* c, const void* u, const void* v, const void* w, double z0,
+                       const void* log_z0, void* const tau[6], double* stats, hipStream_t s);
+int launch_apply(ibm_ctx* c, const TileCfg& cfg, const void* const tau[6], void* const ustar[3],
+                 const void* const gradp[3], double dt, void* const div[3], double* drag,
+                 hipStream_t s);
+bool tile_supported(const ibm_ctx* c, const TileCfg& cfg);
+TileCfg default_tile(const ibm_ctx* c);
+long apply_tiles(const ibm_ctx* c, const TileCfg& cfg);
+long band_blocks(const ibm_ctx* c);
+// Size the reduction slots for the current geometry and tile shape.  Called
+// outside launches; waits for the device before freeing a smaller buffer.
+int size_partials(ibm_ctx* c);
+
+// vjp.hip
+int stage_vjp(ibm_ctx* c, const void* u, const void* v, const void* w, double z0,
+              const void* log_z0, const void* const g_tau[6], const void* const g_div[3],
+              const void* const g_ustar[3], const double g_drag[3], void* gu, void* gv, void* gw,
+              void* glog_z0, hipStream_t s);
+void free_adjoint(ibm_ctx* c);
+
+#define IBM_HIP(call)                                              \
+    do {                                                           \
+        hipError_t e_ = (call);                                    \
+        if (e_ != hipSuccess) return ::ibm::hip_fail(e_, #call);   \
+    } while (0)
+
+}  // namespace ibm

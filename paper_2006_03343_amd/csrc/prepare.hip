@@ -1,0 +1,444 @@
+// prepare.hip -- once-per-geometry set-up of the wall-modeled IBM stage.
+//
+// The paper computes phi and n once (§3.1) and identifies the band points at
+// initialisation (§5); this file does that on the GPU:
+//   1. node classes of both staggered grids (§3.3 lists) and forcing flags
+//      (phi <= 0, eq. f-IB), from the stored phi widened to double and compared
+//      against double thresholds, so the result does not depend on the dtype;
+//   2. ordered compaction of the band nodes of each grid (block counts, a host
+//      scan of the block totals, an in-block scan) -- no atomics, so the record
+//      order is the ascending linear index;
+//   3. one record per band node: the unit normal (§3.1; central differences on
+//      the node's own grid), phi, and the trilinear stencil of the sample point
+//      x + (phi_c - phi) n on both node sets (§3.3);
+//   4. runs of solid nodes along x, cut into pieces for the per-step zeroing.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "device.h"
+#include "ibm_impl.h"
+
+namespace ibm {
+namespace {
+
+constexpr int kItems = 8;                    // nodes per thread in the count/compact pass
+constexpr int kCountBlock = 256;
+constexpr int kNodesPerBlock = kItems * kCountBlock;
+
+template <typename T>
+__global__ void k_classify(const T* __restrict__ pu, const T* __restrict__ pw, long n, double b,
+                           double phib, uint8_t* __restrict__ mask, int* __restrict__ bad) {
+    long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const double a = (double)pu[q];
+    const double w = (double)pw[q];
+    if (!isfinite(a) || !isfinite(w)) atomicOr(bad, 1);
+    int uvc = a < 0.0 ? 2 : (a <= b ? 1 : 0);
+    int wc = w < -phib ? 2 : (w <= phib ? 1 : 0);
+    int m = uvc | (wc << 2);
+    if (a <= 0.0) m |= 1 << 4;
+    if (w <= 0.0) m |= 1 << 5;
+    mask[q] = (uint8_t)m;
+}
+
+__global__ void k_fmask(const uint8_t* __restrict__ mask, int nx, long rows, int wrow,
+                        uint32_t* __restrict__ fmask) {
+    long wi = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (wi >= rows * wrow) return;
+    long row = wi / wrow;
+    int x0 = (int)(wi % wrow) * 16;
+    uint32_t bits = 0;
+    for (int t = 0; t < 16; ++t) {
+        int x = x0 + t;
+        if (x < nx) {
+            uint32_t m = mask[row * nx + x];
+            bits |= ((m >> 4) & 1u) << (2 * t);
+            bits |= ((m >> 5) & 1u) << (2 * t + 1);
+        }
+    }
+    fmask[wi] = bits;
+}
+
+__device__ inline int block_exclusive_scan(int x, int* lds, int* total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int inc = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int y = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += y;
+    }
+    if (lane == 63) lds[w] = inc;
+    __syncthreads();
+    int pre = 0, tot = 0;
+    for (int i = 0; i < nw; ++i) {
+        if (i < w) pre += lds[i];
+        tot += lds[i];
+    }
+    __syncthreads();
+    *total = tot;
+    return pre + inc - x;
+}
+
+// Per block of kNodesPerBlock nodes: [uv band, w band, 6 class counts].
+__global__ void k_block_counts(const uint8_t* __restrict__ mask, long n, int* __restrict__ bc) {
+    __shared__ int lds[8][kCountBlock / 64];
+    long q0 = (long)blockIdx.x * kNodesPerBlock + (long)threadIdx.x * kItems;
+    int c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int t = 0; t < kItems; ++t) {
+        long q = q0 + t;
+        if (q < n) {
+            int m = mask[q];
+            int uvc = m & 3, wc = (m >> 2) & 3;
+            c[0] += uvc == 1;
+            c[1] += wc == 1;
+            c[2 + uvc] += 1;
+            c[5 + wc] += 1;
+        }
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int i = 0; i < 8; ++i) {
+        int x = c[i];
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+        if (lane == 0) lds[i][w] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 8) {
+        int s = 0;
+        for (int i = 0; i < kCountBlock / 64; ++i) s += lds[threadIdx.x][i];
+        bc[(long)blockIdx.x * 8 + threadIdx.x] = s;
+    }
+}
+
+__global__ void k_compact(const uint8_t* __restrict__ mask, long n, const long* __restrict__ off_uv,
+                          const long* __restrict__ off_w, int32_t* __restrict__ q_uv,
+                          int32_t* __restrict__ q_w) {
+    __shared__ int lds[kCountBlock / 64];
+    long q0 = (long)blockIdx.x * kNodesPerBlock + (long)threadIdx.x * kItems;
+    int fu = 0, fw = 0;
+    uint8_t m[kItems];
+    for (int t = 0; t < kItems; ++t) {
+        long q = q0 + t;
+        m[t] = q < n ? mask[q] : 0;
+        fu += (m[t] & 3) == 1;
+        fw += ((m[t] >> 2) & 3) == 1;
+    }
+    int tot;
+    int pu = block_exclusive_scan(fu, lds, &tot);
+    int pw = block_exclusive_scan(fw, lds, &tot);
+    long ou = off_uv[blockIdx.x] + pu;
+    long ow = off_w[blockIdx.x] + pw;
+    for (int t = 0; t < kItems; ++t) {
+        if ((m[t] & 3) == 1) q_uv[ou++] = (int32_t)(q0 + t);
+        if (((m[t] >> 2) & 3) == 1) q_w[ow++] = (int32_t)(q0 + t);
+    }
+}
+
+// Solid runs along x, one thread per (k, j) row.  With out == nullptr only
+// counts the pieces of each row.
+__global__ void k_row_chunks(const uint8_t* __restrict__ mask, int nx, long rows,
+                             const long* __restrict__ row_off, Chunk* __restrict__ out,
+                             int* __restrict__ row_cnt) {
+    long row = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= rows) return;
+    const uint8_t* m = mask + row * nx;
+    long o = out ? row_off[row] : 0;
+    int cnt = 0;
+    for (int grid = 0; grid < 2; ++grid) {
+        int x = 0;
+        while (x < nx) {
+            if (((m[x] >> (2 * grid)) & 3) != 2) {
+                ++x;
+                continue;
+            }
+            int s = x;
+            while (x < nx && ((m[x] >> (2 * grid)) & 3) == 2) ++x;
+            for (int c0 = s; c0 < x; c0 += kChunk) {
+                if (out) {
+                    Chunk ch;
+                    ch.q = (int32_t)(row * nx + c0);
+                    ch.len = min(kChunk, x - c0);
+                    ch.grid = grid;
+                    ch.pad = 0;
+                    out[o + cnt] = ch;
+                }
+                ++cnt;
+            }
+        }
+    }
+    if (row_cnt) row_cnt[row] = cnt;
+}
+
+struct RecOut {
+    int32_t *q, *base, *sx, *sy, *ku, *kw;
+    void *nx, *ny, *nz, *phi, *fx, *fy, *fzu, *fzw;
+};
+
+struct GeomArgs {
+    int nx, ny, nz;
+    double dx, dy, dz;
+    double phi_c;
+};
+
+// Lower stencil index and fraction of the vertical index coordinate k + t,
+// clamped to [0, nz-1].  Splitting the small offset t keeps the fraction
+// exact to the precision of t even on tall grids.
+template <typename T>
+__device__ inline void vsplit(int k, T t, int nz, int32_t* k0, T* f) {
+    T fl = floor(t);
+    int kk = k + (int)fl;
+    T fr = t - fl;
+    if (kk >= nz - 1) {
+        kk = nz - 1;
+        fr = T(0);
+    }
+    if (kk < 0) {
+        kk = 0;
+        fr = T(0);
+    }
+    *k0 = kk;
+    *f = fr;
+}
+
+template <typename T>
+__device__ inline void hsplit(int i, T t, int n, int32_t* i0, T* f) {
+    T fl = floor(t);
+    long ii = (long)i + (long)fl;
+    *f = t - fl;
+    *i0 = (int32_t)pmodl(ii, n);
+}
+
+template <typename T, bool MIXED>
+__global__ void k_records(const T* __restrict__ phi, int kind, long nrec, RecOut o, GeomArgs ga) {
+    long r = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrec) return;
+    const int nx = ga.nx, ny = ga.ny, nz = ga.nz;
+    const long plane = (long)nx * ny;
+    const long q = o.q[r];
+    const int i = (int)(q % nx);
+    const int j = (int)((q / nx) % ny);
+    const int k = (int)(q / plane);
+    const long row = q - i;
+    const long col = q - (long)j * nx;
+    // neighbours on the node's own grid: periodic in x and y
+    const T pxp = phi[row + pmodl(i + 1, nx)], pxm = phi[row + pmodl(i - 1, nx)];
+    const T pyp = phi[col + pmodl(j + 1, ny) * nx], pym = phi[col + pmodl(j - 1, ny) * nx];
+    T pzp = phi[q], pzm = phi[q];
+    T hz = T(2);
+    if (nz == 1) {
+        hz = T(1);
+    } else if (k == 0) {
+        pzp = phi[q + plane];
+        hz = T(1);
+    } else if (k == nz - 1) {
+        pzm = phi[q - plane];
+        hz = T(1);
+    } else {
+        pzp = phi[q + plane];
+        pzm = phi[q - plane];
+    }
+    T gx = (pxp - pxm) / (T(2) * T(ga.dx));
+    T gy = (pyp - pym) / (T(2) * T(ga.dy));
+    T gz = (pzp - pzm) / (hz * T(ga.dz));
+    T m2 = gx * gx + gy * gy + gz * gz;
+    T n0, n1, n2;
+    if (MIXED && m2 < T(0.25)) {
+        // small |grad phi|: difference and normalise in double (the float
+        // differences of float values are exact in double)
+        double dgx = ((double)pxp - (double)pxm) / (2.0 * ga.dx);
+        double dgy = ((double)pyp - (double)pym) / (2.0 * ga.dy);
+        double dgz = ((double)pzp - (double)pzm) / ((double)hz * ga.dz);
+        double mag = sqrt(dgx * dgx + dgy * dgy + dgz * dgz);
+        if (mag == 0.0) {
+            n0 = T(0); n1 = T(0); n2 = T(1);
+        } else {
+            n0 = (T)(dgx / mag); n1 = (T)(dgy / mag); n2 = (T)(dgz / mag);
+        }
+    } else if (m2 == T(0)) {
+        n0 = T(0); n1 = T(0); n2 = T(1);
+    } else {
+        T mag = sqrt(m2);
+        n0 = gx / mag; n1 = gy / mag; n2 = gz / mag;
+    }
+    // sample point offset from the node, in cells
+    const T shift = T(ga.phi_c) - phi[q];
+    const T tx = shift * n0 / T(ga.dx);
+    const T ty = shift * n1 / T(ga.dy);
+    const T tz = shift * n2 / T(ga.dz);
+    int32_t i0, j0, ku, kw;
+    T fx, fy, fzu, fzw;
+    hsplit<T>(i, tx, nx, &i0, &fx);
+    hsplit<T>(j, ty, ny, &j0, &fy);
+    // node heights in index units: uv node k+1/2, w node k; uv index = z/dz - 1/2
+    const T tu = kind == IBM_GRID_UV ? tz : tz - T(0.5);
+    const T tw = kind == IBM_GRID_UV ? tz + T(0.5) : tz;
+    vsplit<T>(k, tu, nz, &ku, &fzu);
+    vsplit<T>(k, tw, nz, &kw, &fzw);
+    o.base[r] = j0 * nx + i0;
+    o.sx[r] = (i0 + 1 == nx) ? 1 - nx : 1;
+    o.sy[r] = (j0 + 1 == ny) ? (1 - ny) * nx : nx;
+    o.ku[r] = ku;
+    o.kw[r] = kw;
+    ((T*)o.nx)[r] = n0;
+    ((T*)o.ny)[r] = n1;
+    ((T*)o.nz)[r] = n2;
+    ((T*)o.phi)[r] = phi[q];
+    ((T*)o.fx)[r] = fx;
+    ((T*)o.fy)[r] = fy;
+    ((T*)o.fzu)[r] = fzu;
+    ((T*)o.fzw)[r] = fzw;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+int alloc_records(Records& R, long n, size_t ts) {
+    R.n = n;
+    size_t ib = align256(sizeof(int32_t) * (size_t)std::max<long>(n, 1));
+    size_t tb = align256(ts * (size_t)std::max<long>(n, 1));
+    size_t total = 6 * ib + 8 * tb;
+    IBM_HIP(hipMalloc(&R.buf, total));
+    char* p = (char*)R.buf;
+    int32_t** ints[6] = {&R.q, &R.base, &R.sx, &R.sy, &R.ku, &R.kw};
+    for (int i = 0; i < 6; ++i) {
+        *ints[i] = (int32_t*)p;
+        p += ib;
+    }
+    void** ts_[8] = {&R.nrm[0], &R.nrm[1], &R.nrm[2], &R.phi, &R.fx, &R.fy, &R.fzu, &R.fzw};
+    for (int i = 0; i < 8; ++i) {
+        *ts_[i] = p;
+        p += tb;
+    }
+    return IBM_OK;
+}
+
+inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+template <typename T>
+int prepare_t(ibm_ctx* c, const T* pu, const T* pw, hipStream_t s) {
+    const long n = c->n;
+    const int nx = c->g.nx, ny = c->g.ny, nz = c->g.nz;
+    const long rows = (long)ny * nz;
+    const double b = c->p.band_width;
+    IBM_HIP(hipMalloc(&c->mask, (size_t)n));
+    c->wrow = (nx + 15) / 16;
+    IBM_HIP(hipMalloc(&c->fmask, sizeof(uint32_t) * (size_t)rows * c->wrow));
+    int* bad = nullptr;
+    IBM_HIP(hipMalloc(&bad, sizeof(int)));
+    IBM_HIP(hipMemsetAsync(bad, 0, sizeof(int), s));
+    hipLaunchKernelGGL(k_classify<T>, dim3(nblk(n, 256)), dim3(256), 0, s, pu, pw, n, b, 0.5 * b,
+                       c->mask, bad);
+    hipLaunchKernelGGL(k_fmask, dim3(nblk(rows * c->wrow, 256)), dim3(256), 0, s, c->mask, nx,
+                       rows, c->wrow, c->fmask);
+    const long nb = (n + kNodesPerBlock - 1) / kNodesPerBlock;
+    int* bc = nullptr;
+    IBM_HIP(hipMalloc(&bc, sizeof(int) * 8 * (size_t)nb));
+    hipLaunchKernelGGL(k_block_counts, dim3((unsigned)nb), dim3(kCountBlock), 0, s, c->mask, n, bc);
+    IBM_HIP(hipGetLastError());
+    std::vector<int> hbc(8 * (size_t)nb);
+    int hbad = 0;
+    IBM_HIP(hipMemcpyAsync(hbc.data(), bc, sizeof(int) * 8 * (size_t)nb, hipMemcpyDeviceToHost, s));
+    IBM_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    IBM_HIP(hipStreamSynchronize(s));
+    (void)hipFree(bad);
+    if (hbad) {
+        (void)hipFree(bc);
+        return fail(IBM_E_RANGE, "levelset_prepare: phi_uv or phi_w holds a non-finite value");
+    }
+    std::vector<long> off_uv(nb), off_w(nb);
+    long tu = 0, tw = 0;
+    for (int i = 0; i < 6; ++i) c->counts[i] = 0;
+    for (long b_ = 0; b_ < nb; ++b_) {
+        off_uv[b_] = tu;
+        off_w[b_] = tw;
+        tu += hbc[8 * b_ + 0];
+        tw += hbc[8 * b_ + 1];
+        for (int i = 0; i < 6; ++i) c->counts[i] += hbc[8 * b_ + 2 + i];
+    }
+    int rc = alloc_records(c->rec[0], tu, sizeof(T));
+    if (rc) return rc;
+    rc = alloc_records(c->rec[1], tw, sizeof(T));
+    if (rc) return rc;
+    long* doff = nullptr;
+    IBM_HIP(hipMalloc(&doff, sizeof(long) * 2 * (size_t)nb));
+    IBM_HIP(hipMemcpyAsync(doff, off_uv.data(), sizeof(long) * nb, hipMemcpyHostToDevice, s));
+    IBM_HIP(hipMemcpyAsync(doff + nb, off_w.data(), sizeof(long) * nb, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)nb), dim3(kCountBlock), 0, s, c->mask, n, doff,
+                       doff + nb, c->rec[0].q, c->rec[1].q);
+    GeomArgs ga{nx, ny, nz, c->g.dx, c->g.dy, c->g.dz, c->p.phi_c};
+    const bool mixed = c->precision == IBM_PREC_MIXED;
+    for (int kind = 0; kind < 2; ++kind) {
+        Records& R = c->rec[kind];
+        if (R.n == 0) continue;
+        RecOut o{R.q, R.base, R.sx, R.sy, R.ku, R.kw, R.nrm[0], R.nrm[1], R.nrm[2], R.phi,
+                 R.fx, R.fy, R.fzu, R.fzw};
+        const T* ph = kind == 0 ? pu : pw;
+        if (mixed)
+            hipLaunchKernelGGL((k_records<T, true>), dim3(nblk(R.n, 256)), dim3(256), 0, s, ph,
+                               kind, R.n, o, ga);
+        else
+            hipLaunchKernelGGL((k_records<T, false>), dim3(nblk(R.n, 256)), dim3(256), 0, s, ph,
+                               kind, R.n, o, ga);
+    }
+    // solid runs
+    int* rcnt = nullptr;
+    IBM_HIP(hipMalloc(&rcnt, sizeof(int) * (size_t)rows));
+    hipLaunchKernelGGL(k_row_chunks, dim3(nblk(rows, 256)), dim3(256), 0, s, c->mask, nx, rows,
+                       (const long*)nullptr, (Chunk*)nullptr, rcnt);
+    std::vector<int> hr(rows);
+    IBM_HIP(hipMemcpyAsync(hr.data(), rcnt, sizeof(int) * rows, hipMemcpyDeviceToHost, s));
+    IBM_HIP(hipStreamSynchronize(s));
+    std::vector<long> roff(rows);
+    long tot = 0;
+    for (long r = 0; r < rows; ++r) {
+        roff[r] = tot;
+        tot += hr[r];
+    }
+    c->nchunks = tot;
+    IBM_HIP(hipMalloc(&c->chunks, sizeof(Chunk) * (size_t)std::max<long>(tot, 1)));
+    long* droff = nullptr;
+    IBM_HIP(hipMalloc(&droff, sizeof(long) * (size_t)rows));
+    IBM_HIP(hipMemcpyAsync(droff, roff.data(), sizeof(long) * rows, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_row_chunks, dim3(nblk(rows, 256)), dim3(256), 0, s, c->mask, nx, rows,
+                       (const long*)droff, c->chunks, (int*)nullptr);
+    IBM_HIP(hipGetLastError());
+    IBM_HIP(hipStreamSynchronize(s));
+    (void)hipFree(droff);
+    (void)hipFree(rcnt);
+    (void)hipFree(doff);
+    (void)hipFree(bc);
+    return IBM_OK;
+}
+
+}  // namespace
+
+void free_prepared(ibm_ctx* c) {
+    (void)hipFree(c->mask);
+    c->mask = nullptr;
+    (void)hipFree(c->fmask);
+    c->fmask = nullptr;
+    for (int k = 0; k < 2; ++k) {
+        (void)hipFree(c->rec[k].buf);
+        c->rec[k] = Records();
+    }
+    (void)hipFree(c->chunks);
+    c->chunks = nullptr;
+    c->nchunks = 0;
+    free_adjoint(c);
+    c->prepared = false;
+}
+
+int prepare(ibm_ctx* c, const void* phi_uv, const void* phi_w, hipStream_t s) {
+    free_prepared(c);
+    int rc = c->dtype == IBM_F64 ? prepare_t<double>(c, (const double*)phi_uv, (const double*)phi_w, s)
+                                 : prepare_t<float>(c, (const float*)phi_uv, (const float*)phi_w, s);
+    if (rc != IBM_OK) {
+        free_prepared(c);
+        return rc;
+    }
+    c->prepared = true;
+    return IBM_OK;
+}
+
+}  // namespace ibm

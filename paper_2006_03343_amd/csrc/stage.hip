@@ -1,0 +1,588 @@
+// stage.hip -- the per-time-step kernels of the wall-modeled IBM stage.
+//
+// k_wall_stress (§3.3): one thread per band record.  It gathers u, v on the uv
+// grid and w on the w grid at the record's sample point (trilinear, 24 loads
+// that mostly hit L2), takes the tangential part U_r = u - (u.n) n, and writes
+// tau = -c |U_r| (U_r n^T + n U_r^T) with c = (kappa / ln(phi_c / z0))^2.  That
+// is the rotation tau_ij = a_im a_jn tau'_mn of the local tensor whose only
+// non-zero entries are tau'_13 = tau'_31 = tau_w = -c |U_r|^2 (eq.
+// bc-bottom-immersed), written without forming the frame.  uv records store
+// xx, yy, zz, xy and w records xz, yz (§3.3).  Extra blocks zero the stress on
+// runs of solid nodes (§3.3: stress inside the body set to zero).
+//
+// k_apply: the dense pass, one read of the six stress fields and one write of
+// the three divergence components per node (HBM bound, no matrix cores).  A
+// wave owns a tile of 64*VX nodes along x, TY rows and up to KZ planes and
+// marches upward in z:
+//   * x neighbours come from the adjacent lanes (cross-lane shuffles), plus
+//     two scalar loads at the tile edges (periodic wrap);
+//   * y neighbours come from a three-row window held in registers while the
+//     wave walks its rows, plus two halo rows per plane;
+//   * z neighbours stay in registers from one plane to the next: tau_zz of the
+//     plane below and tau_xz, tau_yz of the plane above (loaded one plane
+//     ahead);
+//   * no LDS and no barriers; every wave is independent.
+// The same pass forces u* at nodes with phi <= 0 (eq. u-*-IBM), reading the
+// 2-bit forcing flags, and accumulates the drag; each wave leaves a partial in
+// a fixed slot and the last wave to finish (atomic ticket) adds the slots in
+// slot order, so the result is deterministic.
+#include <algorithm>
+#include <cmath>
+
+#include "device.h"
+#include "ibm_impl.h"
+
+namespace ibm {
+namespace {
+
+// ----------------------------------------------------------------- wall stress
+template <typename T>
+struct WSArgs {
+    RecView<T> rec[2];
+    const T *u, *v, *w, *log_z0;
+    T* tau[6];
+    const Chunk* chunks;
+    int nx, ny, nz;
+    long plane;
+    int nb_uv, nb_band;            // blocks of uv records, of all records (>= 1)
+    double ln_scalar;              // ln(phi_c / z0) for a scalar z0
+    double ln_phic;                // ln(phi_c) for a per-node log z0
+    double kappa;
+    double dz;
+    double* partials;              // 4 per band block
+    unsigned* counter;
+    double* stats;                 // nullable
+};
+
+template <typename T>
+__device__ inline T trilerp(const T* __restrict__ f, long c00, long c10, long c01, long c11,
+                            long z0, long z1, T fx, T fy, T fz) {
+    const T gx = T(1) - fx, gy = T(1) - fy, gz = T(1) - fz;
+    T a0 = f[z0 + c00] * gx + f[z0 + c10] * fx;
+    T b0 = f[z0 + c01] * gx + f[z0 + c11] * fx;
+    T a1 = f[z1 + c00] * gx + f[z1 + c10] * fx;
+    T b1 = f[z1 + c01] * gx + f[z1 + c11] * fx;
+    T lo = a0 * gy + b0 * fy;
+    T hi = a1 * gy + b1 * fy;
+    return lo * gz + hi * fz;
+}
+
+template <typename T, bool MIXED, bool HAS_LZ>
+__global__ void __launch_bounds__(kBandBlock) k_wall_stress(WSArgs<T> a) {
+    const int b = blockIdx.x;
+    if (b >= a.nb_band) {
+        // zero the stress components of one piece of a solid run
+        const Chunk ch = a.chunks[b - a.nb_band];
+        if (ch.grid == IBM_GRID_UV) {
+            for (int t = threadIdx.x; t < ch.len; t += blockDim.x) {
+                const long q = (long)ch.q + t;
+                a.tau[0][q] = T(0);
+                a.tau[1][q] = T(0);
+                a.tau[2][q] = T(0);
+                a.tau[3][q] = T(0);
+            }
+        } else {
+            for (int t = threadIdx.x; t < ch.len; t += blockDim.x) {
+                const long q = (long)ch.q + t;
+                a.tau[4][q] = T(0);
+                a.tau[5][q] = T(0);
+            }
+        }
+        return;
+    }
+    const int kind = b < a.nb_uv ? IBM_GRID_UV : IBM_GRID_W;
+    const RecView<T>& R = a.rec[kind];
+    const long r = (long)(kind == IBM_GRID_UV ? b : b - a.nb_uv) * kBandBlock + threadIdx.x;
+    double tw_acc = 0.0, umax = 0.0, cnt = 0.0;
+    if (r < R.n) {
+        const long q = R.q[r];
+        const T n0 = R.nx[r], n1 = R.ny[r], n2 = R.nz[r];
+        const long base = R.base[r];
+        const long c00 = base, c10 = base + R.sx[r], c01 = base + R.sy[r];
+        const long c11 = c10 + R.sy[r];
+        const T fx = R.fx[r], fy = R.fy[r];
+        const int ku = R.ku[r], kw = R.kw[r];
+        const long zu0 = ku * a.plane, zu1 = min(ku + 1, a.nz - 1) * a.plane;
+        const long zw0 = kw * a.plane, zw1 = min(kw + 1, a.nz - 1) * a.plane;
+        const T fzu = R.fzu[r], fzw = R.fzw[r];
+        const T us = trilerp<T>(a.u, c00, c10, c01, c11, zu0, zu1, fx, fy, fzu);
+        const T vs = trilerp<T>(a.v, c00, c10, c01, c11, zu0, zu1, fx, fy, fzu);
+        const T ws = trilerp<T>(a.w, c00, c10, c01, c11, zw0, zw1, fx, fy, fzw);
+        const T un = us * n0 + vs * n1 + ws * n2;
+        const T ur0 = us - un * n0, ur1 = vs - un * n1, ur2 = ws - un * n2;
+        const T U = sqrt(ur0 * ur0 + ur1 * ur1 + ur2 * ur2);
+        // c |U_r|, with c = (kappa / ln(phi_c / z0))^2
+        T cU;
+        if (MIXED && fabs((double)R.phi[r]) <= a.dz) {
+            const double lnr = HAS_LZ ? a.ln_phic - (double)a.log_z0[q] : a.ln_scalar;
+            const double k_l = a.kappa / lnr;
+            cU = (T)(k_l * k_l * (double)U);
+        } else {
+            const T lnr = HAS_LZ ? T(a.ln_phic) - a.log_z0[q] : T(a.ln_scalar);
+            const T k_l = T(a.kappa) / lnr;
+            cU = k_l * k_l * U;
+        }
+        if (kind == IBM_GRID_UV) {
+            a.tau[0][q] = -cU * (T(2) * ur0 * n0);
+            a.tau[1][q] = -cU * (T(2) * ur1 * n1);
+            a.tau[2][q] = -cU * (T(2) * ur2 * n2);
+            a.tau[3][q] = -cU * (ur0 * n1 + n0 * ur1);
+        } else {
+            a.tau[4][q] = -cU * (ur0 * n2 + n0 * ur2);
+            a.tau[5][q] = -cU * (ur1 * n2 + n1 * ur2);
+        }
+        tw_acc = -(double)cU * (double)U;
+        umax = (double)U;
+        cnt = 1.0;
+    }
+    if (!a.stats) return;
+    // block partial: [sum tau_w uv, sum tau_w w, max |U_r|, count]
+    __shared__ double red[4][kBandBlock / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const double s = wave_sum(tw_acc), m = wave_max(umax), c = wave_sum(cnt);
+    if (lane == 0) {
+        red[0][wv] = s;
+        red[1][wv] = m;
+        red[2][wv] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double ss = 0.0, mm = 0.0, cc = 0.0;
+        for (int i = 0; i < kBandBlock / 64; ++i) {
+            ss += red[0][i];
+            mm = fmax(mm, red[1][i]);
+            cc += red[2][i];
+        }
+        double* p = a.partials + 4 * (long)b;
+        p[0] = kind == IBM_GRID_UV ? ss : 0.0;
+        p[1] = kind == IBM_GRID_W ? ss : 0.0;
+        p[2] = mm;
+        p[3] = cc;
+        __threadfence();
+        const unsigned t = ticket(a.counter);
+        red[3][0] = (t == (unsigned)a.nb_band - 1) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    if (red[3][0] == 0.0 || wv != 0) return;
+    // last block: fixed-order reduction of the block slots
+    __threadfence();
+    double s0 = 0.0, s1 = 0.0, mx = 0.0, ct = 0.0;
+    for (long i = lane; i < a.nb_band; i += 64) {
+        s0 += load_acquire(a.partials + 4 * i + 0);
+        s1 += load_acquire(a.partials + 4 * i + 1);
+        mx = fmax(mx, load_acquire(a.partials + 4 * i + 2));
+        ct += load_acquire(a.partials + 4 * i + 3);
+    }
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    mx = wave_max(mx);
+    ct = wave_sum(ct);
+    if (lane == 0) {
+        a.stats[0] = s0;
+        a.stats[1] = s1;
+        a.stats[2] = mx;
+        a.stats[3] = ct;
+        __hip_atomic_store(a.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// ----------------------------------------------------------------- dense pass
+template <typename T>
+struct ApplyArgs {
+    const T* tau[6];
+    T* ustar[3];
+    const T* gradp[3];
+    T* div[3];
+    const uint32_t* fmask;
+    int nx, ny, nz, wrow;
+    long plane;
+    T cx, cy, cz;            // 1/(2 dx), 1/(2 dy), 1/dz
+    T fdt;                   // 3 dt / 2
+    int nxs, njt, kz;        // x segments, row tiles, planes per tile
+    long ntiles;
+    int nblocks;             // blocks that own tiles (the grid is padded to a multiple of 8)
+    int per_xcd;             // logical blocks per XCD
+    double* partials;        // 3 per tile
+    unsigned* counter;
+    double* drag;            // nullable
+    double dv;
+};
+
+// One row of the dense pass at plane k: load helpers with periodic rows.
+template <typename T, int VX>
+__device__ inline Vec<T, VX> ldrow(const T* __restrict__ f, int off, bool act) {
+    return act ? vload<T, VX>(f + off) : vzero<T, VX>();
+}
+
+// Central difference along x of a lane-distributed row: (f[x+1] - f[x-1]).
+template <typename T, int VX>
+__device__ inline Vec<T, VX> xdiff(const Vec<T, VX>& r, const T* __restrict__ f, int rowbase,
+                                   int lane, bool last, int xleft, int xright) {
+    T lft = __shfl_up(r.v[VX - 1], 1, 64);
+    T rgt = __shfl_down(r.v[0], 1, 64);
+    if (lane == 0) lft = f[rowbase + xleft];
+    if (last) rgt = f[rowbase + xright];
+    Vec<T, VX> d;
+#pragma unroll
+    for (int e = 0; e < VX; ++e) {
+        const T hi = (e == VX - 1) ? rgt : r.v[e + 1];
+        const T lo = (e == 0) ? lft : r.v[e - 1];
+        d.v[e] = hi - lo;
+    }
+    return d;
+}
+
+template <typename T, typename Acc, int VX, int TY>
+__global__ void __launch_bounds__(256) k_apply(ApplyArgs<T> a) {
+    const int lane = threadIdx.x & 63;
+    // wave-uniform tile coordinates live in scalar registers
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wpb = blockDim.x >> 6;
+    const int lb = (blockIdx.x & 7) * a.per_xcd + (blockIdx.x >> 3);   // XCD-aware order
+    const long tile = (long)lb * wpb + wv;
+    const bool live = lb < a.nblocks && tile < a.ntiles;
+    Acc s0 = Acc(0), s1 = Acc(0), s2 = Acc(0);
+    if (live) {
+        const int xs = (int)(tile % a.nxs);
+        const int t2 = (int)(tile / a.nxs);
+        const int jt = t2 % a.njt;
+        const int kc = t2 / a.njt;
+        const int nx = a.nx, ny = a.ny, nz = a.nz;
+        const int plane = (int)a.plane;
+        const int x0 = xs * 64 * VX;
+        const int xl = x0 + lane * VX;
+        const bool act = xl < nx;
+        const int seg_end = min(nx, x0 + 64 * VX);
+        const bool last = act && (xl + VX == seg_end);
+        const int xleft = (x0 == 0) ? nx - 1 : x0 - 1;
+        const int xright = (seg_end == nx) ? 0 : seg_end;
+        const int j0 = jt * TY;
+        const int kb = kc * a.kz;
+        const int ke = min(kb + a.kz, nz);
+        int roff[TY + 2];   // offset of row j0-1+r (r = 0..TY+1), periodic in y
+#pragma unroll
+        for (int r = 0; r < TY + 2; ++r) {
+            int jj = (j0 - 1 + r) % ny;
+            if (jj < 0) jj += ny;
+            roff[r] = jj * nx;
+        }
+        const T *txx = a.tau[0], *tyy = a.tau[1], *tzz = a.tau[2], *txy = a.tau[3],
+                *txz = a.tau[4], *tyz = a.tau[5];
+        Vec<T, VX> zz_prev[TY], xz_cur[TY], yz_cur[TY];
+        {
+            const int pk = kb * plane;
+#pragma unroll
+            for (int r = 0; r < TY; ++r) {
+                xz_cur[r] = ldrow<T, VX>(txz, pk + roff[r + 1] + xl, act);
+                yz_cur[r] = ldrow<T, VX>(tyz, pk + roff[r + 1] + xl, act);
+                zz_prev[r] = (kb > 0) ? ldrow<T, VX>(tzz, pk - plane + roff[r + 1] + xl, act)
+                                      : vzero<T, VX>();
+            }
+        }
+        const uint32_t mbits = (1u << (2 * VX)) - 1u;
+        for (int k = kb; k < ke; ++k) {
+            const int pk = k * plane;
+            const bool has_up = k + 1 < nz;
+            const int pu = pk + plane;
+            // y window: rows r-1, r, r+1 of xy and yy; yz halo rows
+            Vec<T, VX> xy_m = ldrow<T, VX>(txy, pk + roff[0] + xl, act);
+            Vec<T, VX> yy_m = ldrow<T, VX>(tyy, pk + roff[0] + xl, act);
+            const Vec<T, VX> yz_lo = ldrow<T, VX>(tyz, pk + roff[0] + xl, act);
+            Vec<T, VX> xy_c = ldrow<T, VX>(txy, pk + roff[1] + xl, act);
+            Vec<T, VX> yy_c = ldrow<T, VX>(tyy, pk + roff[1] + xl, act);
+            Vec<T, VX> yz_pend;
+#pragma unroll
+            for (int r = 0; r < TY; ++r) {
+                const int rb = pk + roff[r + 1];
+                const Vec<T, VX> xy_p = ldrow<T, VX>(txy, pk + roff[r + 2] + xl, act);
+                const Vec<T, VX> yy_p = ldrow<T, VX>(tyy, pk + roff[r + 2] + xl, act);
+                const Vec<T, VX> yz_up = (r + 1 < TY) ? yz_cur[r + 1]
+                                                      : ldrow<T, VX>(tyz, pk + roff[r + 2] + xl, act);
+                const Vec<T, VX> yz_dn = (r == 0) ? yz_lo : yz_cur[r - 1];
+                const Vec<T, VX> xx_c = ldrow<T, VX>(txx, rb + xl, act);
+                const Vec<T, VX> zz_c = ldrow<T, VX>(tzz, rb + xl, act);
+                const Vec<T, VX> xz_n = has_up ? ldrow<T, VX>(txz, pu + roff[r + 1] + xl, act)
+                                               : vzero<T, VX>();
+                const Vec<T, VX> yz_n = has_up ? ldrow<T, VX>(tyz, pu + roff[r + 1] + xl, act)
+                                               : vzero<T, VX>();
+                const Vec<T, VX> dxx = xdiff<T, VX>(xx_c, txx, rb, lane, last, xleft, xright);
+                const Vec<T, VX> dxy = xdiff<T, VX>(xy_c, txy, rb, lane, last, xleft, xright);
+                const Vec<T, VX> dxz = xdiff<T, VX>(xz_cur[r], txz, rb, lane, last, xleft, xright);
+                if (act && j0 + r < ny) {
+                    Vec<T, VX> dvx, dvy, dvz;
+#pragma unroll
+                    for (int e = 0; e < VX; ++e) {
+                        dvx.v[e] = dxx.v[e] * a.cx + (xy_p.v[e] - xy_m.v[e]) * a.cy +
+                                   (xz_n.v[e] - xz_cur[r].v[e]) * a.cz;
+                        dvy.v[e] = dxy.v[e] * a.cx + (yy_p.v[e] - yy_m.v[e]) * a.cy +
+                                   (yz_n.v[e] - yz_cur[r].v[e]) * a.cz;
+                        dvz.v[e] = dxz.v[e] * a.cx + (yz_up.v[e] - yz_dn.v[e]) * a.cy +
+                                   (zz_c.v[e] - zz_prev[r].v[e]) * a.cz;
+                    }
+                    const int o = rb + xl;
+                    vstore_nt<T, VX>(a.div[0] + o, dvx);
+                    vstore_nt<T, VX>(a.div[1] + o, dvy);
+                    vstore_nt<T, VX>(a.div[2] + o, dvz);
+                    const int wi = (k * ny + (j0 + r)) * a.wrow + (xl >> 4);
+                    const uint32_t fb = (a.fmask[wi] >> (2 * (xl & 15))) & mbits;
+                    if (fb) {
+#pragma unroll
+                        for (int e = 0; e < VX; ++e) {
+                            if ((fb >> (2 * e)) & 1u) {
+                                a.ustar[0][o + e] = a.gradp[0] ? a.fdt * a.gradp[0][o + e] : T(0);
+                                a.ustar[1][o + e] = a.gradp[1] ? a.fdt * a.gradp[1][o + e] : T(0);
+                            }
+                            if ((fb >> (2 * e + 1)) & 1u)
+                                a.ustar[2][o + e] = a.gradp[2] ? a.fdt * a.gradp[2][o + e] : T(0);
+                        }
+                    }
+#pragma unroll
+                    for (int e = 0; e < VX; ++e) {
+                        if (!((fb >> (2 * e)) & 1u)) {
+                            s0 += (Acc)dvx.v[e];
+                            s1 += (Acc)dvy.v[e];
+                        }
+                        if (!((fb >> (2 * e + 1)) & 1u)) s2 += (Acc)dvz.v[e];
+                    }
+                }
+                // advance the registers: this row's plane-k values are no longer needed
+                zz_prev[r] = zz_c;
+                xz_cur[r] = xz_n;
+                if (r > 0) yz_cur[r - 1] = yz_pend;
+                yz_pend = yz_n;
+                xy_m = xy_c;
+                xy_c = xy_p;
+                yy_m = yy_c;
+                yy_c = yy_p;
+            }
+            yz_cur[TY - 1] = yz_pend;
+        }
+    }
+    if (!a.drag) return;
+    const double d0 = wave_sum((double)s0), d1 = wave_sum((double)s1), d2 = wave_sum((double)s2);
+    unsigned t = 0;
+    if (live && lane == 0) {
+        a.partials[3 * tile + 0] = d0;
+        a.partials[3 * tile + 1] = d1;
+        a.partials[3 * tile + 2] = d2;
+        __threadfence();
+        t = ticket(a.counter);
+    }
+    t = __shfl(t, 0, 64);
+    if (!live || t != (unsigned)(a.ntiles - 1)) return;
+    __threadfence();
+    double r0 = 0.0, r1 = 0.0, r2 = 0.0;
+    for (long i = lane; i < a.ntiles; i += 64) {
+        r0 += load_acquire(a.partials + 3 * i + 0);
+        r1 += load_acquire(a.partials + 3 * i + 1);
+        r2 += load_acquire(a.partials + 3 * i + 2);
+    }
+    r0 = wave_sum(r0);
+    r1 = wave_sum(r1);
+    r2 = wave_sum(r2);
+    if (lane == 0) {
+        a.drag[0] = a.dv * r0;
+        a.drag[1] = a.dv * r1;
+        a.drag[2] = a.dv * r2;
+        __hip_atomic_store(a.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+template <typename T>
+int wall_stress_t(ibm_ctx* c, const T* u, const T* v, const T* w, double z0, const T* log_z0,
+                  void* const tau[6], double* stats, hipStream_t s) {
+    WSArgs<T> a;
+    a.rec[0] = view<T>(c->rec[0]);
+    a.rec[1] = view<T>(c->rec[1]);
+    a.u = u;
+    a.v = v;
+    a.w = w;
+    a.log_z0 = log_z0;
+    for (int i = 0; i < 6; ++i) a.tau[i] = (T*)tau[i];
+    a.chunks = c->chunks;
+    a.nx = c->g.nx;
+    a.ny = c->g.ny;
+    a.nz = c->g.nz;
+    a.plane = (long)c->g.nx * c->g.ny;
+    a.nb_uv = (int)nblk(c->rec[0].n, kBandBlock);
+    a.nb_band = (int)band_blocks(c);
+    a.ln_scalar = log_z0 ? 0.0 : std::log(c->p.phi_c / z0);
+    a.ln_phic = std::log(c->p.phi_c);
+    a.kappa = c->p.kappa;
+    a.dz = c->g.dz;
+    if (c->ws_cap < 4L * a.nb_band) return fail(IBM_E_STATE, "wall_stress: reduction slots not sized");
+    a.partials = c->ws_partials;
+    a.counter = c->counters + 1;
+    a.stats = stats;
+    const unsigned grid = (unsigned)(a.nb_band + c->nchunks);
+    const bool mixed = c->precision == IBM_PREC_MIXED;
+    if (mixed && log_z0)
+        hipLaunchKernelGGL((k_wall_stress<T, true, true>), dim3(grid), dim3(kBandBlock), 0, s, a);
+    else if (mixed)
+        hipLaunchKernelGGL((k_wall_stress<T, true, false>), dim3(grid), dim3(kBandBlock), 0, s, a);
+    else if (log_z0)
+        hipLaunchKernelGGL((k_wall_stress<T, false, true>), dim3(grid), dim3(kBandBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_wall_stress<T, false, false>), dim3(grid), dim3(kBandBlock), 0, s, a);
+    IBM_HIP(hipGetLastError());
+    return IBM_OK;
+}
+
+template <typename T, typename Acc, int VX, int TY>
+void launch_apply_k(const ApplyArgs<T>& a, unsigned grid, unsigned block, hipStream_t s) {
+    hipLaunchKernelGGL((k_apply<T, Acc, VX, TY>), dim3(grid), dim3(block), 0, s, a);
+}
+
+template <typename T, typename Acc, int VX>
+bool dispatch_ty(const ApplyArgs<T>& a, int ty, unsigned grid, unsigned block, hipStream_t s) {
+    switch (ty) {
+        case 1: launch_apply_k<T, Acc, VX, 1>(a, grid, block, s); return true;
+        case 2: launch_apply_k<T, Acc, VX, 2>(a, grid, block, s); return true;
+        case 4: launch_apply_k<T, Acc, VX, 4>(a, grid, block, s); return true;
+        case 8: launch_apply_k<T, Acc, VX, 8>(a, grid, block, s); return true;
+        default: return false;
+    }
+}
+
+template <typename T, typename Acc>
+bool dispatch_vx(const ApplyArgs<T>& a, int vx, int ty, unsigned grid, unsigned block,
+                 hipStream_t s) {
+    switch (vx) {
+        case 1: return dispatch_ty<T, Acc, 1>(a, ty, grid, block, s);
+        case 2: return dispatch_ty<T, Acc, 2>(a, ty, grid, block, s);
+        case 4:
+            if constexpr (sizeof(T) == 4) return dispatch_ty<T, Acc, 4>(a, ty, grid, block, s);
+            return false;
+        default: return false;
+    }
+}
+
+template <typename T>
+int apply_t(ibm_ctx* c, const TileCfg& cfg, const void* const tau[6], void* const ustar[3],
+            const void* const gradp[3], double dt, void* const div[3], double* drag,
+            hipStream_t s) {
+    ApplyArgs<T> a;
+    for (int i = 0; i < 6; ++i) a.tau[i] = (const T*)tau[i];
+    for (int i = 0; i < 3; ++i) {
+        a.ustar[i] = (T*)ustar[i];
+        a.gradp[i] = gradp ? (const T*)gradp[i] : nullptr;
+        a.div[i] = (T*)div[i];
+    }
+    a.fmask = c->fmask;
+    a.nx = c->g.nx;
+    a.ny = c->g.ny;
+    a.nz = c->g.nz;
+    a.wrow = c->wrow;
+    a.plane = (long)c->g.nx * c->g.ny;
+    a.cx = (T)(1.0 / (2.0 * c->g.dx));
+    a.cy = (T)(1.0 / (2.0 * c->g.dy));
+    a.cz = (T)(1.0 / c->g.dz);
+    a.fdt = (T)(1.5 * dt);
+    a.nxs = (c->g.nx + 64 * cfg.vx - 1) / (64 * cfg.vx);
+    a.njt = (c->g.ny + cfg.ty - 1) / cfg.ty;
+    a.kz = cfg.kz;
+    const long nkc = (c->g.nz + cfg.kz - 1) / cfg.kz;
+    a.ntiles = (long)a.nxs * a.njt * nkc;
+    a.nblocks = (int)((a.ntiles + cfg.wpb - 1) / cfg.wpb);
+    a.per_xcd = (a.nblocks + 7) / 8;
+    if (c->ap_cap < 3 * a.ntiles) return fail(IBM_E_STATE, "apply: reduction slots not sized");
+    a.partials = c->ap_partials;
+    a.counter = c->counters;
+    a.drag = drag;
+    a.dv = c->g.dx * c->g.dy * c->g.dz;
+    const unsigned grid = (unsigned)(8 * a.per_xcd);
+    const unsigned block = (unsigned)(64 * cfg.wpb);
+    bool ok;
+    if (c->precision == IBM_PREC_MIXED || sizeof(T) == 8)
+        ok = dispatch_vx<T, double>(a, cfg.vx, cfg.ty, grid, block, s);
+    else
+        ok = dispatch_vx<T, float>(a, cfg.vx, cfg.ty, grid, block, s);
+    if (!ok) return fail(IBM_E_ARG, "apply: unsupported tile shape vx=%d ty=%d", cfg.vx, cfg.ty);
+    IBM_HIP(hipGetLastError());
+    return IBM_OK;
+}
+
+}  // namespace
+
+long apply_tiles(const ibm_ctx* c, const TileCfg& cfg) {
+    const long nxs = (c->g.nx + 64 * cfg.vx - 1) / (64 * cfg.vx);
+    const long njt = (c->g.ny + cfg.ty - 1) / cfg.ty;
+    const long nkc = (c->g.nz + cfg.kz - 1) / cfg.kz;
+    return nxs * njt * nkc;
+}
+
+long band_blocks(const ibm_ctx* c) {
+    return std::max<long>(1, (long)nblk(c->rec[0].n, kBandBlock) + (long)nblk(c->rec[1].n, kBandBlock));
+}
+
+int size_partials(ibm_ctx* c) {
+    // the dense pass may fall back to one element per lane for misaligned
+    // views, so size its slots for vx = 1 at the current ty and kz
+    TileCfg one = c->cfg;
+    one.vx = 1;
+    const long need_ap = 3 * std::max(apply_tiles(c, c->cfg), apply_tiles(c, one));
+    const long need_ws = 4 * band_blocks(c);
+    if (need_ap <= c->ap_cap && need_ws <= c->ws_cap) return IBM_OK;
+    IBM_HIP(hipDeviceSynchronize());
+    if (need_ap > c->ap_cap) {
+        (void)hipFree(c->ap_partials);
+        c->ap_partials = nullptr;
+        c->ap_cap = 0;
+        IBM_HIP(hipMalloc(&c->ap_partials, sizeof(double) * (size_t)need_ap));
+        c->ap_cap = need_ap;
+    }
+    if (need_ws > c->ws_cap) {
+        (void)hipFree(c->ws_partials);
+        c->ws_partials = nullptr;
+        c->ws_cap = 0;
+        IBM_HIP(hipMalloc(&c->ws_partials, sizeof(double) * (size_t)need_ws));
+        c->ws_cap = need_ws;
+    }
+    return IBM_OK;
+}
+
+bool tile_supported(const ibm_ctx* c, const TileCfg& cfg) {
+    const int ts = c->dtype == IBM_F64 ? 8 : 4;
+    if (cfg.vx != 1 && cfg.vx != 2 && cfg.vx != 4) return false;
+    if (cfg.vx * ts > 16) return false;
+    if (c->g.nx % cfg.vx) return false;
+    if (cfg.ty != 1 && cfg.ty != 2 && cfg.ty != 4 && cfg.ty != 8) return false;
+    if (cfg.kz < 1 || cfg.wpb < 1 || cfg.wpb > 4) return false;
+    return true;
+}
+
+TileCfg default_tile(const ibm_ctx* c) {
+    TileCfg t;
+    const int ts = c->dtype == IBM_F64 ? 8 : 4;
+    const int nx = c->g.nx;
+    t.vx = 1;
+    for (int vx = 16 / ts; vx >= 2; vx /= 2)
+        if (nx % vx == 0 && nx >= 64 * vx) {
+            t.vx = vx;
+            break;
+        }
+    t.ty = 4;
+    t.kz = 16;
+    t.wpb = 4;
+    return t;
+}
+
+int launch_wall_stress(ibm_ctx* c, const void* u, const void* v, const void* w, double z0,
+                       const void* log_z0, void* const tau[6], double* stats, hipStream_t s) {
+    if (c->dtype == IBM_F64)
+        return wall_stress_t<double>(c, (const double*)u, (const double*)v, (const double*)w, z0,
+                                     (const double*)log_z0, tau, stats, s);
+    return wall_stress_t<float>(c, (const float*)u, (const float*)v, (const float*)w, z0,
+                                (const float*)log_z0, tau, stats, s);
+}
+
+int launch_apply(ibm_ctx* c, const TileCfg& cfg, const void* const tau[6], void* const ustar[3],
+                 const void* const gradp[3], double dt, void* const div[3], double* drag,
+                 hipStream_t s) {
+    if (c->dtype == IBM_F64) return apply_t<double>(c, cfg, tau, ustar, gradp, dt, div, drag, s);
+    return apply_t<float>(c, cfg, tau, ustar, gradp, dt, div, drag, s);
+}
+
+}  // namespace ibm

@@ -1,0 +1,380 @@
+// vjp.hip -- hand-written reverse mode of one stage pass.
+//
+// Forward (one velocity state u = u* that is sampled and forced):
+//   tau_out = wall model at band nodes (depends on u through the sample and on
+//             log z0), 0 at solid nodes, tau_sgs elsewhere;
+//   div     = D tau_out;  drag_c = dV sum_{phi > 0} div_c;
+//   ustar   = u where phi > 0, (3 dt / 2) grad p elsewhere.
+// Reverse:
+//   1. dense pass:  gu = g_ustar [phi_uv > 0] (and v, w alike); glog_z0 = 0;
+//   2. band pass:   per band record, the stress cotangent at its node,
+//                   g_tau + (D^T gbar)(q) with gbar = g_div + dV g_drag [phi > 0],
+//                   evaluated from the transposed stencil at that node only;
+//                   then back through tau = -c |U_r| (U_r n^T + n U_r^T):
+//                   U_r cotangent, projection (I - n n^T), and the log z0
+//                   cotangent dc/dlog z0 = 2 kappa^2 / ln(phi_c / z0)^3;
+//   3. gather pass: each velocity node touched by a sample stencil adds the
+//                   weighted record cotangents, reading a transposed map sorted
+//                   by node (built once per geometry) -- no atomics, so the
+//                   result is deterministic.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <numeric>
+#include <vector>
+
+#include "device.h"
+#include "ibm_impl.h"
+
+namespace ibm {
+namespace {
+
+inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+template <typename T>
+__global__ void k_vjp_dense(const T* __restrict__ g0, const T* __restrict__ g1,
+                            const T* __restrict__ g2, const uint32_t* __restrict__ fmask, int nx,
+                            long rows, int wrow, T* __restrict__ gu, T* __restrict__ gv,
+                            T* __restrict__ gw, T* __restrict__ glz) {
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= rows * nx) return;
+    const long row = q / nx;
+    const int x = (int)(q - row * nx);
+    const uint32_t fb = fmask[row * wrow + (x >> 4)] >> (2 * (x & 15));
+    gu[q] = (fb & 1u) ? T(0) : g0[q];
+    gv[q] = (fb & 1u) ? T(0) : g1[q];
+    gw[q] = (fb & 2u) ? T(0) : g2[q];
+    if (glz) glz[q] = T(0);
+}
+
+template <typename T>
+struct BandArgs {
+    RecView<T> rec;
+    int kind;
+    long roff;                 // index of this kind's first record in the concatenated list
+    const T *u, *v, *w, *log_z0;
+    const T* g_tau[6];
+    const T* g_div[3];
+    const uint32_t* fmask;
+    int nx, ny, nz, wrow;
+    long plane;
+    double gdrag[3];
+    double dv;
+    T cx, cy, cz;
+    double ln_scalar, ln_phic, kappa, dz;
+    int mixed;
+    T* rbar;                   // 3 x ntot
+    long ntot;
+    T* glz;                    // nullable
+};
+
+// Cotangent of div_c at node (i, j, k), including the drag term; zero outside 0 <= k < nz.
+template <typename T>
+__device__ inline T gbar(const BandArgs<T>& a, int c, long i, long j, long k) {
+    if (k < 0 || k >= a.nz) return T(0);
+    const long ii = pmodl(i, a.nx), jj = pmodl(j, a.ny);
+    const long q = (k * a.ny + jj) * a.nx + ii;
+    const uint32_t fb = a.fmask[(k * a.ny + jj) * a.wrow + (ii >> 4)] >> (2 * (ii & 15));
+    const bool forced = (c < 2) ? (fb & 1u) : (fb & 2u);
+    T g = a.g_div[c][q];
+    if (!forced) g += (T)(a.dv * a.gdrag[c]);
+    return g;
+}
+
+template <typename T>
+__device__ inline T trilerp(const T* __restrict__ f, long c00, long c10, long c01, long c11,
+                            long z0, long z1, T fx, T fy, T fz) {
+    const T gx = T(1) - fx, gy = T(1) - fy, gz = T(1) - fz;
+    T a0 = f[z0 + c00] * gx + f[z0 + c10] * fx;
+    T b0 = f[z0 + c01] * gx + f[z0 + c11] * fx;
+    T a1 = f[z1 + c00] * gx + f[z1 + c10] * fx;
+    T b1 = f[z1 + c01] * gx + f[z1 + c11] * fx;
+    return (a0 * gy + b0 * fy) * gz + (a1 * gy + b1 * fy) * fz;
+}
+
+template <typename T, bool HAS_LZ>
+__global__ void k_vjp_band(BandArgs<T> a) {
+    const long r = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const RecView<T>& R = a.rec;
+    if (r >= R.n) return;
+    const long q = R.q[r];
+    const long i = q % a.nx, j = (q / a.nx) % a.ny, k = q / a.plane;
+    const T n0 = R.nx[r], n1 = R.ny[r], n2 = R.nz[r];
+    const long base = R.base[r];
+    const long c00 = base, c10 = base + R.sx[r], c01 = base + R.sy[r], c11 = c10 + R.sy[r];
+    const T fx = R.fx[r], fy = R.fy[r];
+    const int ku = R.ku[r], kw = R.kw[r];
+    const long zu0 = ku * a.plane, zu1 = min(ku + 1, a.nz - 1) * a.plane;
+    const long zw0 = kw * a.plane, zw1 = min(kw + 1, a.nz - 1) * a.plane;
+    const T us = trilerp<T>(a.u, c00, c10, c01, c11, zu0, zu1, fx, fy, R.fzu[r]);
+    const T vs = trilerp<T>(a.v, c00, c10, c01, c11, zu0, zu1, fx, fy, R.fzu[r]);
+    const T ws = trilerp<T>(a.w, c00, c10, c01, c11, zw0, zw1, fx, fy, R.fzw[r]);
+    const T un = us * n0 + vs * n1 + ws * n2;
+    const T ur0 = us - un * n0, ur1 = vs - un * n1, ur2 = ws - un * n2;
+    const T U = sqrt(ur0 * ur0 + ur1 * ur1 + ur2 * ur2);
+    double lnr;
+    if (HAS_LZ)
+        lnr = a.ln_phic - (double)a.log_z0[q];
+    else
+        lnr = a.ln_scalar;
+    T c;
+    if (a.mixed && fabs((double)R.phi[r]) <= a.dz) {
+        const double kl = a.kappa / lnr;
+        c = (T)(kl * kl);
+    } else {
+        const T kl = T(a.kappa) / (HAS_LZ ? T(a.ln_phic) - a.log_z0[q] : T(a.ln_scalar));
+        c = kl * kl;
+    }
+    // stress cotangent at this node for the components the record stores
+    T S, P0, P1, P2;
+    if (a.kind == IBM_GRID_UV) {
+        const T txx = (a.g_tau[0] ? a.g_tau[0][q] : T(0)) -
+                      (gbar(a, 0, i + 1, j, k) - gbar(a, 0, i - 1, j, k)) * a.cx;
+        const T tyy = (a.g_tau[1] ? a.g_tau[1][q] : T(0)) -
+                      (gbar(a, 1, i, j + 1, k) - gbar(a, 1, i, j - 1, k)) * a.cy;
+        const T tzz = (a.g_tau[2] ? a.g_tau[2][q] : T(0)) +
+                      (gbar(a, 2, i, j, k) - gbar(a, 2, i, j, k + 1)) * a.cz;
+        const T txy = (a.g_tau[3] ? a.g_tau[3][q] : T(0)) -
+                      (gbar(a, 0, i, j + 1, k) - gbar(a, 0, i, j - 1, k)) * a.cy -
+                      (gbar(a, 1, i + 1, j, k) - gbar(a, 1, i - 1, j, k)) * a.cx;
+        S = txx * (T(2) * ur0 * n0) + tyy * (T(2) * ur1 * n1) + tzz * (T(2) * ur2 * n2) +
+            txy * (ur0 * n1 + n0 * ur1);
+        P0 = txx * (T(2) * n0) + txy * n1;
+        P1 = tyy * (T(2) * n1) + txy * n0;
+        P2 = tzz * (T(2) * n2);
+    } else {
+        const T txz = (a.g_tau[4] ? a.g_tau[4][q] : T(0)) -
+                      (gbar(a, 2, i + 1, j, k) - gbar(a, 2, i - 1, j, k)) * a.cx +
+                      (gbar(a, 0, i, j, k - 1) - gbar(a, 0, i, j, k)) * a.cz;
+        const T tyz = (a.g_tau[5] ? a.g_tau[5][q] : T(0)) -
+                      (gbar(a, 2, i, j + 1, k) - gbar(a, 2, i, j - 1, k)) * a.cy +
+                      (gbar(a, 1, i, j, k - 1) - gbar(a, 1, i, j, k)) * a.cz;
+        S = txz * (ur0 * n2 + n0 * ur2) + tyz * (ur1 * n2 + n1 * ur2);
+        P0 = txz * n2;
+        P1 = tyz * n2;
+        P2 = txz * n0 + tyz * n1;
+    }
+    // tau = -c U M, M = U_r n^T + n U_r^T:  dtau/dU_r,j = -c (U_r,j / U M + U dM/dU_r,j)
+    T b0 = T(0), b1 = T(0), b2 = T(0);
+    if (U > T(0)) {
+        const T sU = S / U;
+        b0 = -c * (ur0 * sU + U * P0);
+        b1 = -c * (ur1 * sU + U * P1);
+        b2 = -c * (ur2 * sU + U * P2);
+        if (HAS_LZ && a.glz) {
+            const double cbar = -(double)U * (double)S;
+            a.glz[q] += (T)(cbar * 2.0 * a.kappa * a.kappa / (lnr * lnr * lnr));
+        }
+    }
+    // through U_r = (I - n n^T) u_s
+    const T bn = b0 * n0 + b1 * n1 + b2 * n2;
+    const long rr = a.roff + r;
+    a.rbar[rr] = b0 - bn * n0;
+    a.rbar[a.ntot + rr] = b1 - bn * n1;
+    a.rbar[2 * a.ntot + rr] = b2 - bn * n2;
+}
+
+template <typename T>
+struct GatherArgs {
+    RecView<T> rec[2];
+    long nuv, ntot;
+    const int32_t *node, *off, *erec, *corner;
+    long m;
+    int zgrid;                 // 0: weights use fzu (u, v), 1: fzw (w)
+    const T* rbar;
+    T* out0;                   // gu (zgrid 0) or gw (zgrid 1)
+    T* out1;                   // gv (zgrid 0) or nullptr
+};
+
+template <typename T>
+__global__ void k_vjp_gather(GatherArgs<T> a) {
+    const long m = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= a.m) return;
+    T s0 = T(0), s1 = T(0);
+    for (int e = a.off[m]; e < a.off[m + 1]; ++e) {
+        const long rr = a.erec[e];
+        const int cn = a.corner[e];
+        const bool isw = rr >= a.nuv;
+        const RecView<T>& R = a.rec[isw];
+        const long r = isw ? rr - a.nuv : rr;
+        const T fx = R.fx[r], fy = R.fy[r], fz = a.zgrid ? R.fzw[r] : R.fzu[r];
+        const T wgt = ((cn & 1) ? fx : T(1) - fx) * ((cn & 2) ? fy : T(1) - fy) *
+                      ((cn & 4) ? fz : T(1) - fz);
+        if (a.zgrid == 0) {
+            s0 += wgt * a.rbar[rr];
+            s1 += wgt * a.rbar[a.ntot + rr];
+        } else {
+            s0 += wgt * a.rbar[2 * a.ntot + rr];
+        }
+    }
+    const long node = a.node[m];
+    a.out0[node] += s0;
+    if (a.out1) a.out1[node] += s1;
+}
+
+// Transposed stencil map: for each node set, the (record, corner) pairs that
+// touch each node, sorted by node, then record, then corner.
+template <typename T>
+int build_map(ibm_ctx* c) {
+    AdjointMap& A = c->adj;
+    const long nuv = c->rec[0].n, nw = c->rec[1].n, ntot = nuv + nw;
+    const long plane = (long)c->g.nx * c->g.ny;
+    const int nz = c->g.nz;
+    std::vector<int32_t> base(ntot), sx(ntot), sy(ntot), ku(ntot), kw(ntot);
+    for (int kind = 0; kind < 2; ++kind) {
+        const Records& R = c->rec[kind];
+        if (R.n == 0) continue;
+        const long o = kind ? nuv : 0;
+        IBM_HIP(hipMemcpy(base.data() + o, R.base, 4 * R.n, hipMemcpyDeviceToHost));
+        IBM_HIP(hipMemcpy(sx.data() + o, R.sx, 4 * R.n, hipMemcpyDeviceToHost));
+        IBM_HIP(hipMemcpy(sy.data() + o, R.sy, 4 * R.n, hipMemcpyDeviceToHost));
+        IBM_HIP(hipMemcpy(ku.data() + o, R.ku, 4 * R.n, hipMemcpyDeviceToHost));
+        IBM_HIP(hipMemcpy(kw.data() + o, R.kw, 4 * R.n, hipMemcpyDeviceToHost));
+    }
+    for (int zg = 0; zg < 2; ++zg) {
+        std::vector<uint64_t> key((size_t)ntot * 8);
+        for (long rr = 0; rr < ntot; ++rr) {
+            const int k0 = zg ? kw[rr] : ku[rr];
+            const int k1 = std::min(k0 + 1, nz - 1);
+            for (int cn = 0; cn < 8; ++cn) {
+                const long node = (long)base[rr] + ((cn & 1) ? sx[rr] : 0) +
+                                  ((cn & 2) ? sy[rr] : 0) + (long)((cn & 4) ? k1 : k0) * plane;
+                key[(size_t)rr * 8 + cn] = ((uint64_t)node << 32) | ((uint64_t)rr << 3) | (uint64_t)cn;
+            }
+        }
+        std::sort(key.begin(), key.end());
+        std::vector<int32_t> node, off, erec(key.size()), corner(key.size());
+        for (size_t e = 0; e < key.size(); ++e) {
+            const int32_t nd = (int32_t)(key[e] >> 32);
+            if (node.empty() || node.back() != nd) {
+                node.push_back(nd);
+                off.push_back((int32_t)e);
+            }
+            erec[e] = (int32_t)((key[e] & 0xffffffffu) >> 3);
+            corner[e] = (int32_t)(key[e] & 7u);
+        }
+        off.push_back((int32_t)key.size());
+        A.m[zg] = (long)node.size();
+        A.e[zg] = (long)key.size();
+        const size_t nb = std::max<size_t>(node.size(), 1), eb = std::max<size_t>(key.size(), 1);
+        IBM_HIP(hipMalloc(&A.node[zg], 4 * nb));
+        IBM_HIP(hipMalloc(&A.off[zg], 4 * (nb + 1)));
+        IBM_HIP(hipMalloc(&A.rec[zg], 4 * eb));
+        IBM_HIP(hipMalloc(&A.corner[zg], 4 * eb));
+        if (!node.empty()) {
+            IBM_HIP(hipMemcpy(A.node[zg], node.data(), 4 * node.size(), hipMemcpyHostToDevice));
+            IBM_HIP(hipMemcpy(A.off[zg], off.data(), 4 * off.size(), hipMemcpyHostToDevice));
+            IBM_HIP(hipMemcpy(A.rec[zg], erec.data(), 4 * erec.size(), hipMemcpyHostToDevice));
+            IBM_HIP(hipMemcpy(A.corner[zg], corner.data(), 4 * corner.size(), hipMemcpyHostToDevice));
+        }
+    }
+    IBM_HIP(hipMalloc(&A.rbar, sizeof(T) * 3 * (size_t)std::max<long>(ntot, 1)));
+    A.built = true;
+    return IBM_OK;
+}
+
+template <typename T>
+int vjp_t(ibm_ctx* c, const T* u, const T* v, const T* w, double z0, const T* log_z0,
+          const void* const g_tau[6], const void* const g_div[3], const void* const g_ustar[3],
+          const double g_drag[3], T* gu, T* gv, T* gw, T* glz, hipStream_t s) {
+    if (!c->adj.built) {
+        IBM_HIP(hipStreamSynchronize(s));
+        int rc = build_map<T>(c);
+        if (rc) {
+            free_adjoint(c);
+            return rc;
+        }
+    }
+    const long rows = (long)c->g.ny * c->g.nz;
+    hipLaunchKernelGGL(k_vjp_dense<T>, dim3(nblk(c->n, 256)), dim3(256), 0, s,
+                       (const T*)g_ustar[0], (const T*)g_ustar[1], (const T*)g_ustar[2], c->fmask,
+                       c->g.nx, rows, c->wrow, gu, gv, gw, glz);
+    const long nuv = c->rec[0].n, ntot = nuv + c->rec[1].n;
+    BandArgs<T> a;
+    a.u = u;
+    a.v = v;
+    a.w = w;
+    a.log_z0 = log_z0;
+    for (int i = 0; i < 6; ++i) a.g_tau[i] = g_tau ? (const T*)g_tau[i] : nullptr;
+    for (int i = 0; i < 3; ++i) {
+        a.g_div[i] = (const T*)g_div[i];
+        a.gdrag[i] = g_drag[i];
+    }
+    a.fmask = c->fmask;
+    a.nx = c->g.nx;
+    a.ny = c->g.ny;
+    a.nz = c->g.nz;
+    a.wrow = c->wrow;
+    a.plane = (long)c->g.nx * c->g.ny;
+    a.dv = c->g.dx * c->g.dy * c->g.dz;
+    a.cx = (T)(1.0 / (2.0 * c->g.dx));
+    a.cy = (T)(1.0 / (2.0 * c->g.dy));
+    a.cz = (T)(1.0 / c->g.dz);
+    a.ln_scalar = log_z0 ? 0.0 : std::log(c->p.phi_c / z0);
+    a.ln_phic = std::log(c->p.phi_c);
+    a.kappa = c->p.kappa;
+    a.dz = c->g.dz;
+    a.mixed = c->precision == IBM_PREC_MIXED;
+    a.rbar = (T*)c->adj.rbar;
+    a.ntot = ntot;
+    a.glz = glz;
+    for (int kind = 0; kind < 2; ++kind) {   // uv first, then w: log z0 adds in a fixed order
+        a.rec = view<T>(c->rec[kind]);
+        a.kind = kind;
+        a.roff = kind ? nuv : 0;
+        if (a.rec.n == 0) continue;
+        if (log_z0)
+            hipLaunchKernelGGL((k_vjp_band<T, true>), dim3(nblk(a.rec.n, 256)), dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_vjp_band<T, false>), dim3(nblk(a.rec.n, 256)), dim3(256), 0, s, a);
+    }
+    GatherArgs<T> ga;
+    ga.rec[0] = view<T>(c->rec[0]);
+    ga.rec[1] = view<T>(c->rec[1]);
+    ga.nuv = nuv;
+    ga.ntot = ntot;
+    ga.rbar = (const T*)c->adj.rbar;
+    for (int zg = 0; zg < 2; ++zg) {
+        ga.node = c->adj.node[zg];
+        ga.off = c->adj.off[zg];
+        ga.erec = c->adj.rec[zg];
+        ga.corner = c->adj.corner[zg];
+        ga.m = c->adj.m[zg];
+        ga.zgrid = zg;
+        ga.out0 = zg ? gw : gu;
+        ga.out1 = zg ? nullptr : gv;
+        if (ga.m == 0) continue;
+        hipLaunchKernelGGL(k_vjp_gather<T>, dim3(nblk(ga.m, 256)), dim3(256), 0, s, ga);
+    }
+    IBM_HIP(hipGetLastError());
+    return IBM_OK;
+}
+
+}  // namespace
+
+void free_adjoint(ibm_ctx* c) {
+    AdjointMap& A = c->adj;
+    for (int zg = 0; zg < 2; ++zg) {
+        (void)hipFree(A.node[zg]);
+        (void)hipFree(A.off[zg]);
+        (void)hipFree(A.rec[zg]);
+        (void)hipFree(A.corner[zg]);
+    }
+    (void)hipFree(A.rbar);
+    A = AdjointMap();
+}
+
+int stage_vjp(ibm_ctx* c, const void* u, const void* v, const void* w, double z0,
+              const void* log_z0, const void* const g_tau[6], const void* const g_div[3],
+              const void* const g_ustar[3], const double g_drag[3], void* gu, void* gv, void* gw,
+              void* glog_z0, hipStream_t s) {
+    if (c->dtype == IBM_F64)
+        return vjp_t<double>(c, (const double*)u, (const double*)v, (const double*)w, z0,
+                             (const double*)log_z0, g_tau, g_div, g_ustar, g_drag, (double*)gu,
+                             (double*)gv, (double*)gw, (double*)glog_z0, s);
+    return vjp_t<float>(c, (const float*)u, (const float*)v, (const float*)w, z0,
+                        (const float*)log_z0, g_tau, g_div, g_ustar, g_drag, (float*)gu,
+                        (float*)gv, (float*)gw, (float*)glog_z0, s);
+}
+
+}  // namespace ibm

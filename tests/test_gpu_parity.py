@@ -1,0 +1,197 @@
+"""GPU parity: the HIP library against the FP64 oracle, element by element.
+
+Bars (normwise per output: max |gpu - oracle| / max |oracle|): 1e-12 for
+float64 storage, 2e-5 for float32 (plain and mixed); masks, band lists and
+class counts identical; stress values off the band identical (copied or
+zeroed); drag within tol * dV * sum |div|.  The oracle is always fed the
+exact stored values the GPU sees (float32 inputs widened to float64).
+"""
+import numpy as np
+import pytest
+
+from _gpu import TOL, compare, normwise, run_gpu, torch_dev
+from workloads import Grid, configs, terrain
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _ref(ora, wl):
+    return ora.stage(wl)
+
+
+def test_cube_f64_full_parity(ora):
+    wl = configs.cube()
+    _say("cube 64x32x32 f64 plain")
+    out, ctx = run_gpu(wl, "f64")
+    ref = _ref(ora, wl)
+    errs = compare(out, ref, wl, TOL["f64"])
+    _say(f"errors {errs}")
+    # ordered band lists and stored normals
+    for grid, cls_shift, phi, kind in ((0, 0, wl.phi_uv, 0), (1, 2, wl.phi_w, 1)):
+        idx, nrm = ctx.band(grid)
+        expect = np.flatnonzero(((ref["mask"].ravel() >> cls_shift) & 3) == 1)
+        assert (idx == expect).all()
+        g = wl.grid
+        for r in range(0, len(idx), max(1, len(idx) // 200)):
+            k, j, i = np.unravel_index(idx[r], g.shape)
+            assert np.abs(nrm[r] - ora.normal(g, phi, i, j, k)).max() < 1e-14
+
+
+TILES_F64 = [(1, 1, 1, 1), (1, 2, 3, 2), (2, 4, 16, 4), (2, 8, 7, 3), (1, 8, 64, 4), (2, 1, 5, 1)]
+
+
+def test_tile_shapes_bitwise_identical(ora):
+    wl = configs.cube()
+    _say("cube f64 tile shapes")
+    base, _ = run_gpu(wl, "f64", tile=TILES_F64[0])
+    ref = _ref(ora, wl)
+    compare(base, ref, wl, TOL["f64"])
+    for t in TILES_F64[1:]:
+        _say(f"tile {t}")
+        out, _ = run_gpu(wl, "f64", tile=t)
+        assert (out["div"] == base["div"]).all(), t
+        assert (out["ustar"] == base["ustar"]).all(), t
+        assert (out["tau"] == base["tau"]).all(), t
+        compare(out, ref, wl, TOL["f64"])
+
+
+@pytest.mark.parametrize("dtype,prec,tile", [
+    ("f64", "plain", (2, 4, 16, 4)), ("f64", "plain", (1, 8, 5, 2)),
+    ("f32", "plain", (4, 4, 16, 4)), ("f32", "mixed", (4, 2, 9, 4)), ("f32", "mixed", (1, 8, 3, 1)),
+    ("f32", "plain", (2, 1, 40, 3))])
+def test_ragged_ridge(ora, dtype, prec, tile):
+    # 100 x 36 x 40: no tile dimension divides the grid
+    wl = configs.ridge(100, 36, 40, H=8.0, L=20.0, x0=30.0)
+    if dtype == "f32":
+        wl = wl.cast(np.float32)
+    _say(f"ridge 100x36x40 {dtype} {prec} tile {tile}")
+    out, _ = run_gpu(wl, dtype, prec, tile=tile)
+    errs = compare(out, _ref(ora, wl), wl, TOL[dtype])
+    _say(f"errors {errs}")
+
+
+@pytest.mark.parametrize("dtype,prec", [("f64", "plain"), ("f32", "plain"), ("f32", "mixed")])
+def test_small_hill(ora, dtype, prec):
+    wl = configs.hill(128, 64, 64, H=16.0, L=40.0, x0=40.0, y0=32.0)
+    if dtype == "f32":
+        wl = wl.cast(np.float32)
+    _say(f"hill 128x64x64 {dtype} {prec}")
+    out, _ = run_gpu(wl, dtype, prec)
+    errs = compare(out, _ref(ora, wl), wl, TOL[dtype])
+    _say(f"errors {errs}")
+
+
+@pytest.mark.parametrize("dtype,prec", [("f64", "plain"), ("f32", "mixed")])
+def test_per_node_log_z0(ora, dtype, prec):
+    wl = configs.fractal(64, 48, 40, rms=4.0)
+    if dtype == "f32":
+        wl = wl.cast(np.float32)
+    _say(f"fractal 64x48x40 log z0 field {dtype} {prec}")
+    out, _ = run_gpu(wl, dtype, prec)
+    errs = compare(out, _ref(ora, wl), wl, TOL[dtype])
+    _say(f"errors {errs}")
+
+
+def _degenerate_cases():
+    out = []
+    # single column, single row, single plane and anisotropic spacing
+    for shape, sp in (((1, 1, 12), (1.0, 1.0, 1.0)), ((7, 1, 9), (1.0, 1.0, 1.0)),
+                      ((1, 6, 9), (0.5, 1.0, 1.0)), ((33, 5, 1), (1.0, 1.0, 1.0)),
+                      ((20, 12, 10), (0.7, 1.3, 0.9))):
+        g = Grid(*shape, *sp)
+        wl = configs.flat(g, 1.25 * sp[2], theta=0.4, z0=1e-3, noise=0.1, tau_std=0.01,
+                          gp_std=0.1, seed=shape[0])
+        wl.band_width = 1.5 * sp[2]
+        wl.phi_c = 1.5 * sp[2]
+        out.append((f"flat{shape}", wl))
+    # no surface at all (every node fluid) and every node solid
+    g = Grid(16, 8, 6)
+    wl = configs.flat(g, -10.0, noise=0.1, tau_std=0.01, gp_std=0.1)
+    out.append(("all-fluid", wl))
+    wl = configs.flat(g, 50.0, noise=0.1, tau_std=0.01, gp_std=0.1)
+    out.append(("all-solid", wl))
+    # a sphere floating in the fluid (closed surface, normals in every direction)
+    g = Grid(24, 20, 18)
+    pu, pw = terrain.sphere(g, (11.3, 9.7, 8.6), 5.2)
+    wl = configs.flat(g, 1.0, noise=0.3, tau_std=0.01, gp_std=0.1)
+    wl.phi_uv, wl.phi_w = pu, pw
+    out.append(("sphere", wl))
+    return out
+
+
+@pytest.mark.parametrize("name,wl", _degenerate_cases(), ids=lambda x: x if isinstance(x, str) else "")
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_degenerate_and_edge_cases(ora, name, wl, dtype):
+    if dtype == "f32":
+        wl = wl.cast(np.float32)
+    _say(f"{name} {wl.grid} {dtype}")
+    out, _ = run_gpu(wl, dtype)
+    compare(out, _ref(ora, wl), wl, TOL[dtype])
+
+
+def test_gradp_null_forces_zero(ora):
+    wl = configs.cube(32, 16, 16)
+    wl.gradp = None
+    _say("cube 32x16x16 f64, gradp NULL")
+    out, _ = run_gpu(wl, "f64")
+    ref = _ref(ora, wl)
+    compare(out, ref, wl, TOL["f64"])
+    f_uv = (ref["mask"] >> 4) & 1 == 1
+    assert (out["ustar"][0][f_uv] == 0).all() and (out["ustar"][1][f_uv] == 0).all()
+
+
+def test_repeat_calls_are_deterministic(ora):
+    wl = configs.cube().cast(np.float32)
+    _say("cube f32 mixed, repeated calls")
+    a, _ = run_gpu(wl, "f32", "mixed")
+    b, _ = run_gpu(wl, "f32", "mixed")
+    for k in ("tau", "div", "ustar", "drag", "stats"):
+        assert (a[k] == b[k]).all(), k
+
+
+def test_errors_are_reported():
+    import torch
+    import paper_2006_03343_amd as ibm
+    from paper_2006_03343_amd import _lib
+    _, dev = torch_dev()
+    _say("error paths")
+    with pytest.raises(ibm.IbmError) as e:
+        ibm.Context(8, 8, 8, dtype=torch.float64, precision="mixed", device=dev)
+    assert e.value.code == _lib.IBM_E_UNSUPPORTED
+    ctx = ibm.Context(8, 8, 8, dtype=torch.float64, device=dev)
+    z = torch.zeros((8, 8, 8), dtype=torch.float64, device=dev)
+    with pytest.raises(ibm.IbmError) as e:
+        ctx.wall_stress(z, z, z, [z] * 6, z0=1e-3)
+    assert e.value.code == _lib.IBM_E_STATE
+    bad = z.clone()
+    bad[3, 3, 3] = float("nan")
+    with pytest.raises(ibm.IbmError) as e:
+        ctx.prepare(bad, z, 1.5)
+    assert e.value.code == _lib.IBM_E_RANGE
+    with pytest.raises(ibm.IbmError) as e:
+        ctx.prepare(z, z, 1.5, phi_c=1.0)
+    assert e.value.code == _lib.IBM_E_RANGE
+    ctx.prepare(z + 5.0, z + 5.0, 1.5)
+    with pytest.raises(ibm.IbmError) as e:
+        ctx.wall_stress(z, z, z, [z.clone() for _ in range(6)], z0=2.0)
+    assert e.value.code == _lib.IBM_E_RANGE
+    with pytest.raises(ibm.IbmError) as e:
+        ctx.set_tile(3, 4, 16, 4)
+    assert e.value.code == _lib.IBM_E_ARG
+    with pytest.raises(TypeError):
+        ctx.wall_stress(z.float(), z, z, [z] * 6, z0=1e-3)
+    assert ctx.counts()[0] == 512
+
+
+def test_hill_full_size_mixed(ora):
+    """The 512 x 256 x 256 hill in the benchmark's configuration, every node compared."""
+    wl = configs.hill().cast(np.float32)
+    _say("hill 512x256x256 f32 mixed (benchmark shape)")
+    out, ctx = run_gpu(wl, "f32", "mixed")
+    _say(f"tile {ctx.get_tile()}")
+    errs = compare(out, _ref(ora, wl), wl, TOL["f32"])
+    _say(f"errors {errs}")
