@@ -101,13 +101,6 @@ int ibm_create(ibm_ctx** out, const ibm_grid* g, int dtype, int precision) {
         delete c;
         return hip_fail(e, "hipGetDevice");
     }
-    e = hipMalloc(&c->counters, 4 * sizeof(unsigned));
-    if (e == hipSuccess) e = hipMemset(c->counters, 0, 4 * sizeof(unsigned));
-    if (e != hipSuccess) {
-        (void)hipFree(c->counters);
-        delete c;
-        return hip_fail(e, "ibm_create: counters");
-    }
     c->cfg = default_tile(c);
     *out = c;
     return IBM_OK;
@@ -119,7 +112,6 @@ int ibm_destroy(ibm_ctx* c) {
     free_prepared(c);
     (void)hipFree(c->ws_partials);
     (void)hipFree(c->ap_partials);
-    (void)hipFree(c->counters);
     delete c;
     return IBM_OK;
 }

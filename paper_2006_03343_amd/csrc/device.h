@@ -76,13 +76,4 @@ __device__ inline double wave_max(double x) {
     return x;
 }
 
-// Agent-scope atomic ticket: returns the value before the increment.
-__device__ inline unsigned ticket(unsigned* counter) {
-    return __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ inline double load_acquire(const double* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 }  // namespace ibm

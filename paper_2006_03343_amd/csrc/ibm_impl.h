@@ -10,6 +10,8 @@
 //              the sample point on the uv and on the w node set
 //  * chunks  : runs of solid nodes along x, split into pieces of at most
 //              kChunk nodes, whose stress components are zeroed each step
+//  * fchunks : runs of forced nodes (phi <= 0) along x, split the same way,
+//              whose intermediate velocity is forced each step
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -62,7 +64,7 @@ inline RecView<T> view(const Records& r) {
 struct Chunk {
     int32_t q;     // first linear index of the run piece
     int32_t len;   // number of nodes (<= kChunk)
-    int32_t grid;  // IBM_GRID_UV: zero xx, yy, zz, xy; IBM_GRID_W: zero xz, yz
+    int32_t grid;  // 0: zero xx, yy, zz, xy; 1: zero xz, yz; 2: force u, v; 3: force w
     int32_t pad;
 };
 
@@ -101,11 +103,12 @@ struct ibm_ctx {
     ibm::Records rec[2];
     long nchunks = 0;
     ibm::Chunk* chunks = nullptr;
+    long nfchunks = 0;
+    ibm::Chunk* fchunks = nullptr;
     double* ws_partials = nullptr;      // wall_stress block slots (4 per band block)
     long ws_cap = 0;                    // in doubles
     double* ap_partials = nullptr;      // apply wave slots (3 per tile)
     long ap_cap = 0;                    // in doubles
-    unsigned* counters = nullptr;       // [0] apply, [1] wall_stress, [2..3] spare
     ibm::TileCfg cfg;
     ibm::AdjointMap adj;
 };

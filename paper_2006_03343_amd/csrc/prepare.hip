@@ -136,9 +136,16 @@ __global__ void k_compact(const uint8_t* __restrict__ mask, long n, const long* 
     }
 }
 
-// Solid runs along x, one thread per (k, j) row.  With out == nullptr only
-// counts the pieces of each row.
-__global__ void k_row_chunks(const uint8_t* __restrict__ mask, int nx, long rows,
+// Runs along x, one thread per (k, j) row, cut into pieces of at most kChunk
+// nodes.  mode 0: solid nodes (class 2) of the uv grid (tag IBM_GRID_UV) and of
+// the w grid (tag IBM_GRID_W); mode 1: forced nodes (phi <= 0) of the uv grid
+// (tag 2) and of the w grid (tag 3).  With out == nullptr only counts.
+__device__ inline bool in_run(uint8_t m, int mode, int grid) {
+    if (mode == 0) return ((m >> (2 * grid)) & 3) == 2;
+    return (m >> (4 + grid)) & 1;
+}
+
+__global__ void k_row_chunks(const uint8_t* __restrict__ mask, int nx, long rows, int mode,
                              const long* __restrict__ row_off, Chunk* __restrict__ out,
                              int* __restrict__ row_cnt) {
     long row = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -149,18 +156,18 @@ __global__ void k_row_chunks(const uint8_t* __restrict__ mask, int nx, long rows
     for (int grid = 0; grid < 2; ++grid) {
         int x = 0;
         while (x < nx) {
-            if (((m[x] >> (2 * grid)) & 3) != 2) {
+            if (!in_run(m[x], mode, grid)) {
                 ++x;
                 continue;
             }
             int s = x;
-            while (x < nx && ((m[x] >> (2 * grid)) & 3) == 2) ++x;
+            while (x < nx && in_run(m[x], mode, grid)) ++x;
             for (int c0 = s; c0 < x; c0 += kChunk) {
                 if (out) {
                     Chunk ch;
                     ch.q = (int32_t)(row * nx + c0);
                     ch.len = min(kChunk, x - c0);
-                    ch.grid = grid;
+                    ch.grid = grid + 2 * mode;
                     ch.pad = 0;
                     out[o + cnt] = ch;
                 }
@@ -381,29 +388,32 @@ int prepare_t(ibm_ctx* c, const T* pu, const T* pw, hipStream_t s) {
             hipLaunchKernelGGL((k_records<T, false>), dim3(nblk(R.n, 256)), dim3(256), 0, s, ph,
                                kind, R.n, o, ga);
     }
-    // solid runs
+    // solid runs (zeroed by wall_stress) and forced runs (forced by apply)
     int* rcnt = nullptr;
-    IBM_HIP(hipMalloc(&rcnt, sizeof(int) * (size_t)rows));
-    hipLaunchKernelGGL(k_row_chunks, dim3(nblk(rows, 256)), dim3(256), 0, s, c->mask, nx, rows,
-                       (const long*)nullptr, (Chunk*)nullptr, rcnt);
-    std::vector<int> hr(rows);
-    IBM_HIP(hipMemcpyAsync(hr.data(), rcnt, sizeof(int) * rows, hipMemcpyDeviceToHost, s));
-    IBM_HIP(hipStreamSynchronize(s));
-    std::vector<long> roff(rows);
-    long tot = 0;
-    for (long r = 0; r < rows; ++r) {
-        roff[r] = tot;
-        tot += hr[r];
-    }
-    c->nchunks = tot;
-    IBM_HIP(hipMalloc(&c->chunks, sizeof(Chunk) * (size_t)std::max<long>(tot, 1)));
     long* droff = nullptr;
+    IBM_HIP(hipMalloc(&rcnt, sizeof(int) * (size_t)rows));
     IBM_HIP(hipMalloc(&droff, sizeof(long) * (size_t)rows));
-    IBM_HIP(hipMemcpyAsync(droff, roff.data(), sizeof(long) * rows, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_row_chunks, dim3(nblk(rows, 256)), dim3(256), 0, s, c->mask, nx, rows,
-                       (const long*)droff, c->chunks, (int*)nullptr);
-    IBM_HIP(hipGetLastError());
-    IBM_HIP(hipStreamSynchronize(s));
+    std::vector<int> hr(rows);
+    std::vector<long> roff(rows);
+    for (int mode = 0; mode < 2; ++mode) {
+        hipLaunchKernelGGL(k_row_chunks, dim3(nblk(rows, 256)), dim3(256), 0, s, c->mask, nx, rows,
+                           mode, (const long*)nullptr, (Chunk*)nullptr, rcnt);
+        IBM_HIP(hipMemcpyAsync(hr.data(), rcnt, sizeof(int) * rows, hipMemcpyDeviceToHost, s));
+        IBM_HIP(hipStreamSynchronize(s));
+        long tot = 0;
+        for (long r = 0; r < rows; ++r) {
+            roff[r] = tot;
+            tot += hr[r];
+        }
+        Chunk** dst = mode == 0 ? &c->chunks : &c->fchunks;
+        (mode == 0 ? c->nchunks : c->nfchunks) = tot;
+        IBM_HIP(hipMalloc(dst, sizeof(Chunk) * (size_t)std::max<long>(tot, 1)));
+        IBM_HIP(hipMemcpyAsync(droff, roff.data(), sizeof(long) * rows, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_row_chunks, dim3(nblk(rows, 256)), dim3(256), 0, s, c->mask, nx, rows,
+                           mode, (const long*)droff, *dst, (int*)nullptr);
+        IBM_HIP(hipGetLastError());
+        IBM_HIP(hipStreamSynchronize(s));
+    }
     (void)hipFree(droff);
     (void)hipFree(rcnt);
     (void)hipFree(doff);
@@ -425,6 +435,9 @@ void free_prepared(ibm_ctx* c) {
     (void)hipFree(c->chunks);
     c->chunks = nullptr;
     c->nchunks = 0;
+    (void)hipFree(c->fchunks);
+    c->fchunks = nullptr;
+    c->nfchunks = 0;
     free_adjoint(c);
     c->prepared = false;
 }

@@ -22,10 +22,11 @@
 //     plane below and tau_xz, tau_yz of the plane above (loaded one plane
 //     ahead);
 //   * no LDS and no barriers; every wave is independent.
-// The same pass forces u* at nodes with phi <= 0 (eq. u-*-IBM), reading the
-// 2-bit forcing flags, and accumulates the drag; each wave leaves a partial in
-// a fixed slot and the last wave to finish (atomic ticket) adds the slots in
-// slot order, so the result is deterministic.
+// Leading blocks of the same launch force u* on runs of nodes with phi <= 0
+// (eq. u-*-IBM); the tiles read the 2-bit forcing flags only to leave forced
+// nodes out of the drag, which they accumulate; each wave leaves a partial in
+// a fixed slot and a one-block kernel (k_finalize) adds the slots in slot order,
+// so the result is deterministic and no atomics serialise the waves.
 #include <algorithm>
 #include <cmath>
 
@@ -50,7 +51,6 @@ struct WSArgs {
     double kappa;
     double dz;
     double* partials;              // 4 per band block
-    unsigned* counter;
     double* stats;                 // nullable
 };
 
@@ -136,8 +136,9 @@ __global__ void __launch_bounds__(kBandBlock) k_wall_stress(WSArgs<T> a) {
         cnt = 1.0;
     }
     if (!a.stats) return;
-    // block partial: [sum tau_w uv, sum tau_w w, max |U_r|, count]
-    __shared__ double red[4][kBandBlock / 64];
+    // block partial: [sum tau_w uv, sum tau_w w, max |U_r|, count]; k_finalize adds the
+    // slots in slot order after the kernel
+    __shared__ double red[3][kBandBlock / 64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const double s = wave_sum(tw_acc), m = wave_max(umax), c = wave_sum(cnt);
     if (lane == 0) {
@@ -158,31 +159,32 @@ __global__ void __launch_bounds__(kBandBlock) k_wall_stress(WSArgs<T> a) {
         p[1] = kind == IBM_GRID_W ? ss : 0.0;
         p[2] = mm;
         p[3] = cc;
-        __threadfence();
-        const unsigned t = ticket(a.counter);
-        red[3][0] = (t == (unsigned)a.nb_band - 1) ? 1.0 : 0.0;
     }
-    __syncthreads();
-    if (red[3][0] == 0.0 || wv != 0) return;
-    // last block: fixed-order reduction of the block slots
-    __threadfence();
-    double s0 = 0.0, s1 = 0.0, mx = 0.0, ct = 0.0;
-    for (long i = lane; i < a.nb_band; i += 64) {
-        s0 += load_acquire(a.partials + 4 * i + 0);
-        s1 += load_acquire(a.partials + 4 * i + 1);
-        mx = fmax(mx, load_acquire(a.partials + 4 * i + 2));
-        ct += load_acquire(a.partials + 4 * i + 3);
-    }
-    s0 = wave_sum(s0);
-    s1 = wave_sum(s1);
-    mx = wave_max(mx);
-    ct = wave_sum(ct);
-    if (lane == 0) {
-        a.stats[0] = s0;
-        a.stats[1] = s1;
-        a.stats[2] = mx;
-        a.stats[3] = ct;
-        __hip_atomic_store(a.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Fixed-order reduction of per-slot partials (one block): out[c] = scale_c *
+// (sum or max over slots i of p[i * nc + c]); bit ``c`` of maxmask selects max.
+__global__ void __launch_bounds__(256) k_finalize(const double* __restrict__ p, long nslots, int nc,
+                                                   unsigned maxmask, double scale,
+                                                   double* __restrict__ out) {
+    __shared__ double red[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int c = 0; c < nc; ++c) {
+        const bool mx = (maxmask >> c) & 1u;
+        double acc = 0.0;
+        for (long i = threadIdx.x; i < nslots; i += blockDim.x) {
+            const double x = p[i * nc + c];
+            acc = mx ? fmax(acc, x) : acc + x;
+        }
+        acc = mx ? wave_max(acc) : wave_sum(acc);
+        if (lane == 0) red[wv] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double r = red[0];
+            for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = mx ? fmax(r, red[w]) : r + red[w];
+            out[c] = mx ? r : scale * r;
+        }
+        __syncthreads();
     }
 }
 
@@ -203,25 +205,45 @@ struct ApplyArgs {
     int nblocks;             // blocks that own tiles (the grid is padded to a multiple of 8)
     int per_xcd;             // logical blocks per XCD
     double* partials;        // 3 per tile
-    unsigned* counter;
     double* drag;            // nullable
+    const Chunk* fchunks;    // runs of forced nodes
+    int nfblocks;            // leading blocks that force (a multiple of 8)
+    long nfchunks;
     double dv;
 };
 
-// One row of the dense pass at plane k: load helpers with periodic rows.
-template <typename T, int VX>
-__device__ inline Vec<T, VX> ldrow(const T* __restrict__ f, int off, bool act) {
-    return act ? vload<T, VX>(f + off) : vzero<T, VX>();
+template <typename T>
+__device__ inline T readlane(T x, int l) {
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), l));
+    } else {
+        const long long b = __builtin_bit_cast(long long, x);
+        const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+        const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+        return __builtin_bit_cast(T, ((long long)hi << 32) | (unsigned)lo);
+    }
 }
 
 // Central difference along x of a lane-distributed row: (f[x+1] - f[x-1]).
+// Neighbours inside the wave come from the adjacent lanes.  When the wave
+// holds the whole periodic row the ends wrap inside the wave; otherwise lane
+// 0 holds the value left of the segment and lane 1 the value right of it
+// (``edge``, loaded with the rest of the plane) and both are broadcast.
 template <typename T, int VX>
-__device__ inline Vec<T, VX> xdiff(const Vec<T, VX>& r, const T* __restrict__ f, int rowbase,
-                                   int lane, bool last, int xleft, int xright) {
+__device__ inline Vec<T, VX> xdiff(const Vec<T, VX>& r, T edge, int lane, bool last,
+                                   bool whole_row, int last_lane) {
     T lft = __shfl_up(r.v[VX - 1], 1, 64);
     T rgt = __shfl_down(r.v[0], 1, 64);
-    if (lane == 0) lft = f[rowbase + xleft];
-    if (last) rgt = f[rowbase + xright];
+    T hl, hr;
+    if (whole_row) {
+        hl = readlane(r.v[VX - 1], last_lane);
+        hr = readlane(r.v[0], 0);
+    } else {
+        hl = readlane(edge, 0);
+        hr = readlane(edge, 1);
+    }
+    if (lane == 0) lft = hl;
+    if (last) rgt = hr;
     Vec<T, VX> d;
 #pragma unroll
     for (int e = 0; e < VX; ++e) {
@@ -232,13 +254,33 @@ __device__ inline Vec<T, VX> xdiff(const Vec<T, VX>& r, const T* __restrict__ f,
     return d;
 }
 
+// The dense pass.  Per plane every load is issued first, without branches
+// (lanes past the end of the row read a valid clamped address and discard
+// it), so a wave waits for memory once per plane.
 template <typename T, typename Acc, int VX, int TY>
 __global__ void __launch_bounds__(256) k_apply(ApplyArgs<T> a) {
+    if ((int)blockIdx.x < a.nfblocks) {
+        // direct forcing (eq. u-*-IBM) on runs of nodes with phi <= 0
+        for (long ci = blockIdx.x; ci < a.nfchunks; ci += a.nfblocks) {
+            const Chunk ch = a.fchunks[ci];
+            for (int t = threadIdx.x; t < ch.len; t += blockDim.x) {
+                const long q = (long)ch.q + t;
+                if (ch.grid == 2) {
+                    a.ustar[0][q] = a.gradp[0] ? a.fdt * a.gradp[0][q] : T(0);
+                    a.ustar[1][q] = a.gradp[1] ? a.fdt * a.gradp[1][q] : T(0);
+                } else {
+                    a.ustar[2][q] = a.gradp[2] ? a.fdt * a.gradp[2][q] : T(0);
+                }
+            }
+        }
+        return;
+    }
     const int lane = threadIdx.x & 63;
     // wave-uniform tile coordinates live in scalar registers
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wpb = blockDim.x >> 6;
-    const int lb = (blockIdx.x & 7) * a.per_xcd + (blockIdx.x >> 3);   // XCD-aware order
+    const int bid = blockIdx.x - a.nfblocks;                           // nfblocks % 8 == 0
+    const int lb = (bid & 7) * a.per_xcd + (bid >> 3);                 // XCD-aware order
     const long tile = (long)lb * wpb + wv;
     const bool live = lb < a.nblocks && tile < a.ntiles;
     Acc s0 = Acc(0), s1 = Acc(0), s2 = Acc(0);
@@ -252,20 +294,27 @@ __global__ void __launch_bounds__(256) k_apply(ApplyArgs<T> a) {
         const int x0 = xs * 64 * VX;
         const int xl = x0 + lane * VX;
         const bool act = xl < nx;
+        const int xlc = act ? xl : nx - VX;          // always a valid vector address
         const int seg_end = min(nx, x0 + 64 * VX);
         const bool last = act && (xl + VX == seg_end);
         const int xleft = (x0 == 0) ? nx - 1 : x0 - 1;
         const int xright = (seg_end == nx) ? 0 : seg_end;
+        const int eoff = (lane & 1) ? xright : xleft; // lane 0: left edge, lane 1: right edge
+        const bool whole_row = (x0 == 0) && (seg_end == nx);   // wave-uniform
+        const int last_lane = (seg_end - x0) / VX - 1;
         const int j0 = jt * TY;
         const int kb = kc * a.kz;
         const int ke = min(kb + a.kz, nz);
         int roff[TY + 2];   // offset of row j0-1+r (r = 0..TY+1), periodic in y
+        int frow[TY];       // forcing-flag row of tile row r (clamped for ragged tiles)
 #pragma unroll
         for (int r = 0; r < TY + 2; ++r) {
             int jj = (j0 - 1 + r) % ny;
             if (jj < 0) jj += ny;
             roff[r] = jj * nx;
         }
+#pragma unroll
+        for (int r = 0; r < TY; ++r) frow[r] = min(j0 + r, ny - 1);
         const T *txx = a.tau[0], *tyy = a.tau[1], *tzz = a.tau[2], *txy = a.tau[3],
                 *txz = a.tau[4], *tyz = a.tau[5];
         Vec<T, VX> zz_prev[TY], xz_cur[TY], yz_cur[TY];
@@ -273,69 +322,73 @@ __global__ void __launch_bounds__(256) k_apply(ApplyArgs<T> a) {
             const int pk = kb * plane;
 #pragma unroll
             for (int r = 0; r < TY; ++r) {
-                xz_cur[r] = ldrow<T, VX>(txz, pk + roff[r + 1] + xl, act);
-                yz_cur[r] = ldrow<T, VX>(tyz, pk + roff[r + 1] + xl, act);
-                zz_prev[r] = (kb > 0) ? ldrow<T, VX>(tzz, pk - plane + roff[r + 1] + xl, act)
+                xz_cur[r] = vload<T, VX>(txz + pk + roff[r + 1] + xlc);
+                yz_cur[r] = vload<T, VX>(tyz + pk + roff[r + 1] + xlc);
+                zz_prev[r] = (kb > 0) ? vload<T, VX>(tzz + pk - plane + roff[r + 1] + xlc)
                                       : vzero<T, VX>();
             }
         }
         const uint32_t mbits = (1u << (2 * VX)) - 1u;
+        const int fsh = 2 * (xlc & 15);
         for (int k = kb; k < ke; ++k) {
             const int pk = k * plane;
             const bool has_up = k + 1 < nz;
-            const int pu = pk + plane;
-            // y window: rows r-1, r, r+1 of xy and yy; yz halo rows
-            Vec<T, VX> xy_m = ldrow<T, VX>(txy, pk + roff[0] + xl, act);
-            Vec<T, VX> yy_m = ldrow<T, VX>(tyy, pk + roff[0] + xl, act);
-            const Vec<T, VX> yz_lo = ldrow<T, VX>(tyz, pk + roff[0] + xl, act);
-            Vec<T, VX> xy_c = ldrow<T, VX>(txy, pk + roff[1] + xl, act);
-            Vec<T, VX> yy_c = ldrow<T, VX>(tyy, pk + roff[1] + xl, act);
-            Vec<T, VX> yz_pend;
+            // ---- issue every load of plane k
+            Vec<T, VX> xy[TY + 2], yy[TY + 2], xx[TY], zz[TY], xzn[TY], yzn[TY];
+            T exx[TY], exy[TY], exz[TY];
+            uint32_t fw[TY];
+#pragma unroll
+            for (int r = 0; r < TY + 2; ++r) {
+                xy[r] = vload<T, VX>(txy + pk + roff[r] + xlc);
+                yy[r] = vload<T, VX>(tyy + pk + roff[r] + xlc);
+            }
+            const Vec<T, VX> yz_lo = vload<T, VX>(tyz + pk + roff[0] + xlc);
+            const Vec<T, VX> yz_hi = vload<T, VX>(tyz + pk + roff[TY + 1] + xlc);
 #pragma unroll
             for (int r = 0; r < TY; ++r) {
                 const int rb = pk + roff[r + 1];
-                const Vec<T, VX> xy_p = ldrow<T, VX>(txy, pk + roff[r + 2] + xl, act);
-                const Vec<T, VX> yy_p = ldrow<T, VX>(tyy, pk + roff[r + 2] + xl, act);
-                const Vec<T, VX> yz_up = (r + 1 < TY) ? yz_cur[r + 1]
-                                                      : ldrow<T, VX>(tyz, pk + roff[r + 2] + xl, act);
-                const Vec<T, VX> yz_dn = (r == 0) ? yz_lo : yz_cur[r - 1];
-                const Vec<T, VX> xx_c = ldrow<T, VX>(txx, rb + xl, act);
-                const Vec<T, VX> zz_c = ldrow<T, VX>(tzz, rb + xl, act);
-                const Vec<T, VX> xz_n = has_up ? ldrow<T, VX>(txz, pu + roff[r + 1] + xl, act)
-                                               : vzero<T, VX>();
-                const Vec<T, VX> yz_n = has_up ? ldrow<T, VX>(tyz, pu + roff[r + 1] + xl, act)
-                                               : vzero<T, VX>();
-                const Vec<T, VX> dxx = xdiff<T, VX>(xx_c, txx, rb, lane, last, xleft, xright);
-                const Vec<T, VX> dxy = xdiff<T, VX>(xy_c, txy, rb, lane, last, xleft, xright);
-                const Vec<T, VX> dxz = xdiff<T, VX>(xz_cur[r], txz, rb, lane, last, xleft, xright);
+                xx[r] = vload<T, VX>(txx + rb + xlc);
+                zz[r] = vload<T, VX>(tzz + rb + xlc);
+                if (has_up) {
+                    xzn[r] = vload<T, VX>(txz + rb + plane + xlc);
+                    yzn[r] = vload<T, VX>(tyz + rb + plane + xlc);
+                } else {
+                    xzn[r] = vzero<T, VX>();
+                    yzn[r] = vzero<T, VX>();
+                }
+                if (!whole_row) {
+                    exx[r] = txx[rb + eoff];
+                    exy[r] = txy[rb + eoff];
+                    exz[r] = txz[rb + eoff];
+                } else {
+                    exx[r] = exy[r] = exz[r] = T(0);
+                }
+                fw[r] = a.fmask[(k * ny + frow[r]) * a.wrow + (xlc >> 4)];
+            }
+            // ---- compute the TY rows
+#pragma unroll
+            for (int r = 0; r < TY; ++r) {
+                const Vec<T, VX> dxx = xdiff<T, VX>(xx[r], exx[r], lane, last, whole_row, last_lane);
+                const Vec<T, VX> dxy = xdiff<T, VX>(xy[r + 1], exy[r], lane, last, whole_row, last_lane);
+                const Vec<T, VX> dxz = xdiff<T, VX>(xz_cur[r], exz[r], lane, last, whole_row, last_lane);
+                const Vec<T, VX>& yz_dn = (r == 0) ? yz_lo : yz_cur[r - 1];
+                const Vec<T, VX>& yz_up = (r + 1 == TY) ? yz_hi : yz_cur[r + 1];
                 if (act && j0 + r < ny) {
                     Vec<T, VX> dvx, dvy, dvz;
 #pragma unroll
                     for (int e = 0; e < VX; ++e) {
-                        dvx.v[e] = dxx.v[e] * a.cx + (xy_p.v[e] - xy_m.v[e]) * a.cy +
-                                   (xz_n.v[e] - xz_cur[r].v[e]) * a.cz;
-                        dvy.v[e] = dxy.v[e] * a.cx + (yy_p.v[e] - yy_m.v[e]) * a.cy +
-                                   (yz_n.v[e] - yz_cur[r].v[e]) * a.cz;
+                        dvx.v[e] = dxx.v[e] * a.cx + (xy[r + 2].v[e] - xy[r].v[e]) * a.cy +
+                                   (xzn[r].v[e] - xz_cur[r].v[e]) * a.cz;
+                        dvy.v[e] = dxy.v[e] * a.cx + (yy[r + 2].v[e] - yy[r].v[e]) * a.cy +
+                                   (yzn[r].v[e] - yz_cur[r].v[e]) * a.cz;
                         dvz.v[e] = dxz.v[e] * a.cx + (yz_up.v[e] - yz_dn.v[e]) * a.cy +
-                                   (zz_c.v[e] - zz_prev[r].v[e]) * a.cz;
+                                   (zz[r].v[e] - zz_prev[r].v[e]) * a.cz;
                     }
-                    const int o = rb + xl;
+                    const int o = pk + roff[r + 1] + xl;
                     vstore_nt<T, VX>(a.div[0] + o, dvx);
                     vstore_nt<T, VX>(a.div[1] + o, dvy);
                     vstore_nt<T, VX>(a.div[2] + o, dvz);
-                    const int wi = (k * ny + (j0 + r)) * a.wrow + (xl >> 4);
-                    const uint32_t fb = (a.fmask[wi] >> (2 * (xl & 15))) & mbits;
-                    if (fb) {
-#pragma unroll
-                        for (int e = 0; e < VX; ++e) {
-                            if ((fb >> (2 * e)) & 1u) {
-                                a.ustar[0][o + e] = a.gradp[0] ? a.fdt * a.gradp[0][o + e] : T(0);
-                                a.ustar[1][o + e] = a.gradp[1] ? a.fdt * a.gradp[1][o + e] : T(0);
-                            }
-                            if ((fb >> (2 * e + 1)) & 1u)
-                                a.ustar[2][o + e] = a.gradp[2] ? a.fdt * a.gradp[2][o + e] : T(0);
-                        }
-                    }
+                    const uint32_t fb = (fw[r] >> fsh) & mbits;
 #pragma unroll
                     for (int e = 0; e < VX; ++e) {
                         if (!((fb >> (2 * e)) & 1u)) {
@@ -345,46 +398,22 @@ __global__ void __launch_bounds__(256) k_apply(ApplyArgs<T> a) {
                         if (!((fb >> (2 * e + 1)) & 1u)) s2 += (Acc)dvz.v[e];
                     }
                 }
-                // advance the registers: this row's plane-k values are no longer needed
-                zz_prev[r] = zz_c;
-                xz_cur[r] = xz_n;
-                if (r > 0) yz_cur[r - 1] = yz_pend;
-                yz_pend = yz_n;
-                xy_m = xy_c;
-                xy_c = xy_p;
-                yy_m = yy_c;
-                yy_c = yy_p;
             }
-            yz_cur[TY - 1] = yz_pend;
+            // ---- carry the plane upward
+#pragma unroll
+            for (int r = 0; r < TY; ++r) {
+                zz_prev[r] = zz[r];
+                xz_cur[r] = xzn[r];
+                yz_cur[r] = yzn[r];
+            }
         }
     }
     if (!a.drag) return;
     const double d0 = wave_sum((double)s0), d1 = wave_sum((double)s1), d2 = wave_sum((double)s2);
-    unsigned t = 0;
     if (live && lane == 0) {
         a.partials[3 * tile + 0] = d0;
         a.partials[3 * tile + 1] = d1;
         a.partials[3 * tile + 2] = d2;
-        __threadfence();
-        t = ticket(a.counter);
-    }
-    t = __shfl(t, 0, 64);
-    if (!live || t != (unsigned)(a.ntiles - 1)) return;
-    __threadfence();
-    double r0 = 0.0, r1 = 0.0, r2 = 0.0;
-    for (long i = lane; i < a.ntiles; i += 64) {
-        r0 += load_acquire(a.partials + 3 * i + 0);
-        r1 += load_acquire(a.partials + 3 * i + 1);
-        r2 += load_acquire(a.partials + 3 * i + 2);
-    }
-    r0 = wave_sum(r0);
-    r1 = wave_sum(r1);
-    r2 = wave_sum(r2);
-    if (lane == 0) {
-        a.drag[0] = a.dv * r0;
-        a.drag[1] = a.dv * r1;
-        a.drag[2] = a.dv * r2;
-        __hip_atomic_store(a.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -414,7 +443,6 @@ int wall_stress_t(ibm_ctx* c, const T* u, const T* v, const T* w, double z0, con
     a.dz = c->g.dz;
     if (c->ws_cap < 4L * a.nb_band) return fail(IBM_E_STATE, "wall_stress: reduction slots not sized");
     a.partials = c->ws_partials;
-    a.counter = c->counters + 1;
     a.stats = stats;
     const unsigned grid = (unsigned)(a.nb_band + c->nchunks);
     const bool mixed = c->precision == IBM_PREC_MIXED;
@@ -426,6 +454,9 @@ int wall_stress_t(ibm_ctx* c, const T* u, const T* v, const T* w, double z0, con
         hipLaunchKernelGGL((k_wall_stress<T, false, true>), dim3(grid), dim3(kBandBlock), 0, s, a);
     else
         hipLaunchKernelGGL((k_wall_stress<T, false, false>), dim3(grid), dim3(kBandBlock), 0, s, a);
+    if (stats)
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, (const double*)a.partials,
+                           (long)a.nb_band, 4, 1u << 2, 1.0, stats);
     IBM_HIP(hipGetLastError());
     return IBM_OK;
 }
@@ -489,10 +520,12 @@ int apply_t(ibm_ctx* c, const TileCfg& cfg, const void* const tau[6], void* cons
     a.per_xcd = (a.nblocks + 7) / 8;
     if (c->ap_cap < 3 * a.ntiles) return fail(IBM_E_STATE, "apply: reduction slots not sized");
     a.partials = c->ap_partials;
-    a.counter = c->counters;
     a.drag = drag;
     a.dv = c->g.dx * c->g.dy * c->g.dz;
-    const unsigned grid = (unsigned)(8 * a.per_xcd);
+    a.fchunks = c->fchunks;
+    a.nfchunks = c->nfchunks;
+    a.nfblocks = (int)std::min<long>((c->nfchunks + 7) / 8 * 8, 1024);
+    const unsigned grid = (unsigned)(a.nfblocks + 8 * a.per_xcd);
     const unsigned block = (unsigned)(64 * cfg.wpb);
     bool ok;
     if (c->precision == IBM_PREC_MIXED || sizeof(T) == 8)
@@ -500,6 +533,9 @@ int apply_t(ibm_ctx* c, const TileCfg& cfg, const void* const tau[6], void* cons
     else
         ok = dispatch_vx<T, float>(a, cfg.vx, cfg.ty, grid, block, s);
     if (!ok) return fail(IBM_E_ARG, "apply: unsupported tile shape vx=%d ty=%d", cfg.vx, cfg.ty);
+    if (drag)
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, (const double*)a.partials,
+                           a.ntiles, 3, 0u, a.dv, drag);
     IBM_HIP(hipGetLastError());
     return IBM_OK;
 }
@@ -563,9 +599,11 @@ TileCfg default_tile(const ibm_ctx* c) {
             t.vx = vx;
             break;
         }
-    t.ty = 4;
-    t.kz = 16;
-    t.wpb = 4;
+    // measured on the 512x256x256 hill (float32): two rows per wave, 32 planes
+    // per tile, one wave per block
+    t.ty = 2;
+    t.kz = 32;
+    t.wpb = 1;
     return t;
 }
 
