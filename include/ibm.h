@@ -141,6 +141,63 @@ int ibm_stage_vjp(ibm_ctx* c, const void* u, const void* v, const void* w, doubl
 int ibm_set_tile(ibm_ctx* c, int vx, int ty, int kz, int wpb);
 int ibm_get_tile(const ibm_ctx* c, int out[4]);
 
+/* ---------------------------------------------------------------- tuning
+ * Time candidate tile shapes of the dense pass on this context's prepared
+ * grid (on scratch fields allocated for the call; caller data is not read)
+ * and keep the fastest.  cache_path (nullable): a JSON file, one entry per
+ * grid shape, dtype, precision and GPU architecture; a cached shape is reused
+ * without timing unless IBM_TUNE_FORCE.  IBM_TUNE_BATCH restricts the search
+ * to shapes the batched kernels accept (ty <= 2).  Synchronises ``stream``. */
+enum { IBM_TUNE_FORCE = 1, IBM_TUNE_BATCH = 2 };
+int ibm_autotune(ibm_ctx* c, const char* cache_path, int flags, void* stream);
+
+/* ------------------------------------------------------------- ensembles
+ * A batch advances many grids of different sizes together: one step is three
+ * persistent kernels (wall stress, dense pass, reductions) over a work list
+ * that spans every case, captured once in a hipGraph and replayed by
+ * ibm_batch_launch.  Each case computes exactly what ibm_wall_stress followed
+ * by ibm_apply computes on a context with the same tile shape (bitwise). */
+typedef struct ibm_batch ibm_batch;
+
+typedef struct {
+    const void *u, *v, *w;   /* sampled velocity (uv, uv, w nodes) */
+    const void* log_z0;      /* per-node log z0, or NULL for the case's scalar z0 */
+    void* tau[6];            /* in: SGS stress; out: wall-modeled stress */
+    void* ustar[3];          /* forced in place */
+    const void* gradp[3];    /* entries may be NULL (0) */
+    void* div[3];            /* out: +div(tau) */
+    double dt;
+    double* drag_dev;        /* NULL or 3 device doubles: the case's drag (as ibm_apply) */
+    double* stats_dev;       /* NULL or 4 device doubles: band statistics (as ibm_wall_stress) */
+} ibm_case_io;
+
+/* ncases contexts on the current device; grids[i] is case i's grid. */
+int ibm_batch_create(ibm_batch** out, int ncases, const ibm_grid* grids, int dtype, int precision);
+int ibm_batch_destroy(ibm_batch* b);
+/* Prepare every case (as ibm_levelset_prepare; synchronous).  z0[i]: case i's
+ * scalar roughness (0 < z0 < phi_c). Unbinds every case. */
+int ibm_batch_prepare(ibm_batch* b, const void* const* phi_uv, const void* const* phi_w,
+                      const ibm_params* p, const double* z0, void* stream);
+/* Attach case i's caller-owned device fields.  The batch keeps the pointers:
+ * they must stay valid, at the same addresses, until the batch is destroyed or
+ * the case is bound again.  tau and div need 16-byte alignment when the case's
+ * tile has vx > 1.  Invalidates a captured graph. */
+int ibm_batch_bind(ibm_batch* b, int case_id, const ibm_case_io* io);
+/* Autotune each distinct grid shape once (IBM_TUNE_BATCH) and give the shape
+ * to every case of that size.  Invalidates a captured graph. */
+int ibm_batch_tune(ibm_batch* b, const char* cache_path, void* stream);
+/* One step without a graph (three kernel launches on ``stream``). */
+int ibm_batch_run(ibm_batch* b, void* stream);
+/* Record one step into a hipGraph (stream capture on ``stream``, which must be
+ * a created stream, not the null stream), after every case is bound.
+ * ibm_batch_launch replays it on any stream: one hipGraphLaunch per step.
+ * Errors: IBM_E_STATE when a case is unbound or the graph is stale, IBM_E_ARG
+ * for the null stream. */
+int ibm_batch_capture(ibm_batch* b, void* stream);
+int ibm_batch_launch(ibm_batch* b, void* stream);
+/* The context of one case (owned by the batch): counts, masks, band lists. */
+int ibm_batch_case(const ibm_batch* b, int case_id, ibm_ctx** out);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* ibm_last_error(void);
 

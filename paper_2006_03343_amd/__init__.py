@@ -16,7 +16,7 @@ from . import _lib
 from ._lib import (IBM_F32, IBM_F64, IBM_GRID_UV, IBM_GRID_W, IBM_PREC_MIXED, IBM_PREC_PLAIN,
                    IbmError, IbmGrid, IbmParams, check, ptr_array)
 
-__all__ = ["Context", "IBMStage", "IbmError", "stage_forward"]
+__all__ = ["Context", "Batch", "IBMStage", "IbmError", "stage_forward"]
 
 _DTYPES = {torch.float32: IBM_F32, torch.float64: IBM_F64}
 _PREC = {"plain": IBM_PREC_PLAIN, "mixed": IBM_PREC_MIXED}
@@ -46,11 +46,25 @@ class Context:
             check(self._lib.ibm_create(_byref(self._h), _byref(g), _DTYPES[dtype], _PREC[precision]))
         self.params = None
 
+    @classmethod
+    def _borrow(cls, handle, nx, ny, nz, spacing, dtype, precision, device):
+        """A non-owning view of a context owned by a Batch."""
+        self = cls.__new__(cls)
+        self._lib = _lib.load()
+        self.device, self.dtype, self.precision = device, dtype, precision
+        self.shape = (int(nz), int(ny), int(nx))
+        self.n = int(nx) * int(ny) * int(nz)
+        self.spacing = spacing
+        self._h = handle
+        self._owned = False
+        self.params = None
+        return self
+
     # ------------------------------------------------------------- plumbing
     def close(self):
-        if getattr(self, "_h", None) is not None and self._h.value:
+        if getattr(self, "_h", None) is not None and self._h.value and getattr(self, "_owned", True):
             self._lib.ibm_destroy(self._h)
-            self._h = ctypes_void()
+        self._h = ctypes_void()
 
     def __del__(self):
         try:
@@ -117,6 +131,15 @@ class Context:
         check(self._lib.ibm_mask_export(self._h, m.ctypes.data))
         return m
 
+    def autotune(self, cache_path=None, force=False, batch=False):
+        """Time tile shapes of the dense pass on this grid and keep the fastest
+        (ibm_autotune); a JSON cache file, if given, is read and updated."""
+        flags = (_lib.IBM_TUNE_FORCE if force else 0) | (_lib.IBM_TUNE_BATCH if batch else 0)
+        with torch.cuda.device(self.device):
+            check(self._lib.ibm_autotune(self._h, cache_path.encode() if cache_path else None,
+                                         flags, self._stream()))
+        return self.get_tile()
+
     def set_tile(self, vx, ty, kz, wpb=4):
         """Tile shape of the dense pass (speed only; see ibm_set_tile)."""
         check(self._lib.ibm_set_tile(self._h, int(vx), int(ty), int(kz), int(wpb)))
@@ -182,6 +205,108 @@ class Context:
                                           gw.data_ptr(), glz.data_ptr() if glz is not None else None,
                                           self._stream()))
         return gu, gv, gw, glz
+
+
+class Batch:
+    """An ensemble of grids advanced together by persistent kernels, one
+    hipGraph launch per step (ibm_batch_*).  Bound tensors are kept alive by
+    the batch until they are rebound or the batch is closed."""
+
+    def __init__(self, grids, dtype=torch.float32, precision="plain", device=None):
+        self._lib = _lib.load()
+        self.device = torch.device(device if device is not None else "cuda")
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.dtype, self.precision = dtype, precision
+        self.grids = [tuple(g) + (1.0, 1.0, 1.0)[len(g) - 3:] for g in grids]
+        arr = (IbmGrid * len(grids))(*[IbmGrid(int(g[0]), int(g[1]), int(g[2]), float(g[3]),
+                                               float(g[4]), float(g[5])) for g in self.grids])
+        self._h = ctypes_void()
+        with torch.cuda.device(self.device):
+            check(self._lib.ibm_batch_create(_byref(self._h), len(grids), arr, _DTYPES[dtype],
+                                             _PREC[precision]))
+        self._keep = [None] * len(grids)
+
+    def __len__(self):
+        return len(self.grids)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.ibm_batch_destroy(self._h)
+        self._h = ctypes_void()
+        self._keep = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self):
+        return torch.cuda.current_stream(self.device).cuda_stream
+
+    def case(self, i):
+        """Non-owning Context of case i (counts, masks, band lists, tile shape)."""
+        h = ctypes_void()
+        check(self._lib.ibm_batch_case(self._h, int(i), _byref(h)))
+        g = self.grids[i]
+        return Context._borrow(h, g[0], g[1], g[2], g[3:6], self.dtype, self.precision, self.device)
+
+    def prepare(self, phi_uv, phi_w, band_width, z0, phi_c=None, kappa=0.4):
+        n = len(self.grids)
+        cases = [self.case(i) for i in range(n)]
+        pu = ptr_array([cases[i]._field(phi_uv[i], f"phi_uv[{i}]") for i in range(n)])
+        pw = ptr_array([cases[i]._field(phi_w[i], f"phi_w[{i}]") for i in range(n)])
+        z = (_lib.c_double * n)(*[float(x) for x in z0])
+        p = IbmParams(float(band_width), float(phi_c) if phi_c else -1.0, float(kappa))
+        with torch.cuda.device(self.device):
+            check(self._lib.ibm_batch_prepare(self._h, pu, pw, _byref(p), z, self._stream()))
+        self._keep = [None] * n
+
+    def bind(self, i, u, v, w, tau, ustar, div, gradp=None, dt=0.01, log_z0=None, drag=None,
+             stats=None):
+        c = self.case(i)
+        io = _lib.IbmCaseIO()
+        io.u, io.v, io.w = c._field(u, "u"), c._field(v, "v"), c._field(w, "w")
+        io.log_z0 = c._field(log_z0, "log_z0")
+        for k, t in enumerate(tau):
+            io.tau[k] = c._field(t, f"tau[{k}]")
+        for k in range(3):
+            io.ustar[k] = c._field(ustar[k], f"ustar[{k}]")
+            io.div[k] = c._field(div[k], f"div[{k}]")
+            io.gradp[k] = c._field(gradp[k], f"gradp[{k}]") if gradp is not None else None
+        io.dt = float(dt)
+        for name, t, m in (("drag", drag, 3), ("stats", stats, 4)):
+            if t is not None and (t.dtype != torch.float64 or t.numel() < m or t.device != self.device):
+                raise ValueError(f"{name} must be a float64 device tensor with {m} elements")
+        io.drag_dev = drag.data_ptr() if drag is not None else None
+        io.stats_dev = stats.data_ptr() if stats is not None else None
+        check(self._lib.ibm_batch_bind(self._h, int(i), _byref(io)))
+        self._keep[i] = (u, v, w, tau, ustar, div, gradp, log_z0, drag, stats)
+
+    def tune(self, cache_path=None):
+        with torch.cuda.device(self.device):
+            check(self._lib.ibm_batch_tune(self._h, cache_path.encode() if cache_path else None,
+                                           self._stream()))
+
+    def run(self):
+        """One step of every case without a graph."""
+        with torch.cuda.device(self.device):
+            check(self._lib.ibm_batch_run(self._h, self._stream()))
+
+    def capture(self):
+        """Record one step into a hipGraph.  Capture runs on a side stream (the
+        null stream cannot be captured) ordered after the current stream."""
+        with torch.cuda.device(self.device):
+            side = torch.cuda.Stream(self.device)
+            side.wait_stream(torch.cuda.current_stream(self.device))
+            check(self._lib.ibm_batch_capture(self._h, side.cuda_stream))
+            torch.cuda.current_stream(self.device).wait_stream(side)
+
+    def launch(self):
+        """One step of every case: one hipGraphLaunch of the captured graph."""
+        with torch.cuda.device(self.device):
+            check(self._lib.ibm_batch_launch(self._h, self._stream()))
 
 
 def stage_forward(context, u, v, w, tau_sgs, gradp=None, dt=0.01, z0=None, log_z0=None):

@@ -18,7 +18,10 @@ IBM_GRID_UV, IBM_GRID_W = 0, 1
 
 EXPORTS = ["ibm_create", "ibm_destroy", "ibm_levelset_prepare", "ibm_counts", "ibm_band_size",
            "ibm_band_export", "ibm_mask_export", "ibm_wall_stress", "ibm_apply", "ibm_stage_vjp",
-           "ibm_set_tile", "ibm_get_tile", "ibm_last_error"]
+           "ibm_set_tile", "ibm_get_tile", "ibm_last_error", "ibm_autotune", "ibm_batch_create",
+           "ibm_batch_destroy", "ibm_batch_prepare", "ibm_batch_bind", "ibm_batch_tune",
+           "ibm_batch_run", "ibm_batch_capture", "ibm_batch_launch", "ibm_batch_case"]
+IBM_TUNE_FORCE, IBM_TUNE_BATCH = 1, 2
 
 
 class IbmGrid(ctypes.Structure):
@@ -28,6 +31,13 @@ class IbmGrid(ctypes.Structure):
 
 class IbmParams(ctypes.Structure):
     _fields_ = [("band_width", c_double), ("phi_c", c_double), ("kappa", c_double)]
+
+
+class IbmCaseIO(ctypes.Structure):
+    _fields_ = [("u", c_void_p), ("v", c_void_p), ("w", c_void_p), ("log_z0", c_void_p),
+                ("tau", c_void_p * 6), ("ustar", c_void_p * 3), ("gradp", c_void_p * 3),
+                ("div", c_void_p * 3), ("dt", c_double), ("drag_dev", c_void_p),
+                ("stats_dev", c_void_p)]
 
 
 class IbmError(RuntimeError):
@@ -60,9 +70,19 @@ def load():
     L.ibm_stage_vjp.argtypes = [vp, vp, vp, vp, c_double, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.ibm_set_tile.argtypes = [vp, c_int, c_int, c_int, c_int]
     L.ibm_get_tile.argtypes = [vp, vp]
+    L.ibm_autotune.argtypes = [vp, c_char_p, c_int, vp]
+    L.ibm_batch_create.argtypes = [POINTER(vp), c_int, vp, c_int, c_int]
+    L.ibm_batch_destroy.argtypes = [vp]
+    L.ibm_batch_prepare.argtypes = [vp, vp, vp, POINTER(IbmParams), vp, vp]
+    L.ibm_batch_bind.argtypes = [vp, c_int, POINTER(IbmCaseIO)]
+    L.ibm_batch_tune.argtypes = [vp, c_char_p, vp]
+    L.ibm_batch_run.argtypes = [vp, vp]
+    L.ibm_batch_capture.argtypes = [vp, vp]
+    L.ibm_batch_launch.argtypes = [vp, vp]
+    L.ibm_batch_case.argtypes = [vp, c_int, POINTER(vp)]
     L.ibm_last_error.restype = c_char_p
     for name in EXPORTS:
-        if name != "ibm_last_error" and name != "ibm_destroy":
+        if name not in ("ibm_last_error", "ibm_destroy", "ibm_batch_destroy"):
             getattr(L, name).restype = c_int
     _lib = L
     return L

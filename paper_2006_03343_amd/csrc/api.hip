@@ -52,19 +52,6 @@ int check_field(const ibm_ctx* c, const void* p, const char* fn, const char* nam
     return IBM_OK;
 }
 
-// RAII: make the context's device current for the duration of a call.
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) (void)hipSetDevice(dev);
-    }
-    ~DeviceGuard() {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
-
 }  // namespace
 }  // namespace ibm
 
@@ -108,7 +95,7 @@ int ibm_create(ibm_ctx** out, const ibm_grid* g, int dtype, int precision) {
 
 int ibm_destroy(ibm_ctx* c) {
     if (!c) return IBM_OK;
-    DeviceGuard dg(c->device);
+    DeviceScope dg(c->device);
     free_prepared(c);
     (void)hipFree(c->ws_partials);
     (void)hipFree(c->ap_partials);
@@ -131,7 +118,7 @@ int ibm_levelset_prepare(ibm_ctx* c, const void* phi_uv, const void* phi_w, cons
     if (!std::isfinite(q.phi_c) || q.phi_c < q.band_width)
         return fail(IBM_E_RANGE, "ibm_levelset_prepare: phi_c must be >= band_width (phi_c >= 2 phi_b)");
     if (!finite_pos(q.kappa)) return fail(IBM_E_RANGE, "ibm_levelset_prepare: kappa must be > 0");
-    DeviceGuard dg(c->device);
+    DeviceScope dg(c->device);
     c->p = q;
     rc = prepare(c, phi_uv, phi_w, (hipStream_t)stream);
     if (rc) return rc;
@@ -160,7 +147,7 @@ int ibm_band_export(const ibm_ctx* c, int grid, int32_t* idx_host, double* norma
     if (rc) return rc;
     if ((grid != IBM_GRID_UV && grid != IBM_GRID_W) || !idx_host)
         return fail(IBM_E_ARG, "ibm_band_export: bad grid or NULL output");
-    DeviceGuard dg(c->device);
+    DeviceScope dg(c->device);
     const Records& R = c->rec[grid];
     if (R.n == 0) return IBM_OK;
     IBM_HIP(hipMemcpy(idx_host, R.q, sizeof(int32_t) * R.n, hipMemcpyDeviceToHost));
@@ -180,7 +167,7 @@ int ibm_mask_export(const ibm_ctx* c, uint8_t* mask_host) {
     int rc = check_ctx(c, true, "ibm_mask_export");
     if (rc) return rc;
     if (!mask_host) return fail(IBM_E_ARG, "ibm_mask_export: NULL output");
-    DeviceGuard dg(c->device);
+    DeviceScope dg(c->device);
     IBM_HIP(hipMemcpy(mask_host, c->mask, (size_t)c->n, hipMemcpyDeviceToHost));
     return IBM_OK;
 }
@@ -204,7 +191,7 @@ int ibm_wall_stress(ibm_ctx* c, const void* u, const void* v, const void* w, dou
     }
     if (stats_dev && ((uintptr_t)stats_dev % 8))
         return fail(IBM_E_ARG, "%s: stats_dev misaligned", fn);
-    DeviceGuard dg(c->device);
+    DeviceScope dg(c->device);
     return launch_wall_stress(c, u, v, w, z0, log_z0, tau, stats_dev, (hipStream_t)stream);
 }
 
@@ -239,7 +226,7 @@ int ibm_apply(ibm_ctx* c, const void* const tau[6], void* const ustar[3],
             if (div[i] == tau[j]) return fail(IBM_E_ARG, "%s: div may not alias tau", fn);
     }
     if (drag_dev && ((uintptr_t)drag_dev % 8)) return fail(IBM_E_ARG, "%s: drag_dev misaligned", fn);
-    DeviceGuard dg(c->device);
+    DeviceScope dg(c->device);
     return launch_apply(c, cfg, tau, ustar, gradp, dt, div, drag_dev, (hipStream_t)stream);
 }
 
@@ -255,7 +242,7 @@ int ibm_set_tile(ibm_ctx* c, int vx, int ty, int kz, int wpb) {
     if (!tile_supported(c, t))
         return fail(IBM_E_ARG, "ibm_set_tile: unsupported shape vx=%d ty=%d kz=%d wpb=%d", vx, ty,
                     kz, wpb);
-    DeviceGuard dg(c->device);
+    DeviceScope dg(c->device);
     c->cfg = t;
     return c->prepared ? size_partials(c) : IBM_OK;
 }
@@ -301,7 +288,7 @@ int ibm_stage_vjp(ibm_ctx* c, const void* u, const void* v, const void* w, doubl
             return fail(IBM_E_RANGE, "%s: z0 must satisfy 0 < z0 < phi_c (got %g)", fn, z0);
     }
     if (glog_z0 && (rc = check_field(c, glog_z0, fn, "glog_z0"))) return rc;
-    DeviceGuard dg(c->device);
+    DeviceScope dg(c->device);
     return stage_vjp(c, u, v, w, z0, log_z0, g_tau, g_div, g_ustar, g_drag, gu, gv, gw, glog_z0,
                      (hipStream_t)stream);
 }

@@ -138,12 +138,30 @@ long band_blocks(const ibm_ctx* c);
 // outside launches; waits for the device before freeing a smaller buffer.
 int size_partials(ibm_ctx* c);
 
+// batch.hip
+int autotune(ibm_ctx* c, const char* cache_path, int flags, hipStream_t s);
+
 // vjp.hip
 int stage_vjp(ibm_ctx* c, const void* u, const void* v, const void* w, double z0,
               const void* log_z0, const void* const g_tau[6], const void* const g_div[3],
               const void* const g_ustar[3], const double g_drag[3], void* gu, void* gv, void* gw,
               void* glog_z0, hipStream_t s);
 void free_adjoint(ibm_ctx* c);
+
+// Make a device current for the duration of a call; restores the caller's.
+struct DeviceScope {
+    int prev = -1;
+    explicit DeviceScope(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceScope() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+    DeviceScope(const DeviceScope&) = delete;
+    DeviceScope& operator=(const DeviceScope&) = delete;
+};
 
 #define IBM_HIP(call)                                              \
     do {                                                           \

@@ -1,0 +1,200 @@
+"""GPU tests of the ensemble path (ibm_batch_*) and of the tile autotuner.
+
+* every case of a batch equals a plain per-case call (ibm_wall_stress then
+  ibm_apply) with the same tile shape, bit for bit: stress, divergence,
+  forced velocity, drag and band statistics; one case is also held to the
+  oracle;
+* replays of the captured hipGraph, with eager work and synchronisations in
+  between, each equal the eager result;
+* the autotuner writes and re-reads its cache and keeps a valid shape.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from _gpu import TOL, compare, torch_dev
+from workloads import configs
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(64, 32, 24), (48, 40, 20), (32, 32, 16), (64, 64, 24), (48, 40, 20), (80, 24, 18)]
+TILES = {"f32": [(4, 2, 16, 1), (2, 1, 5, 1), (1, 2, 7, 1), (4, 1, 32, 1), (2, 2, 3, 1), (1, 1, 64, 1)],
+         "f64": [(2, 2, 16, 1), (1, 1, 5, 1), (2, 1, 7, 1), (1, 2, 32, 1), (2, 2, 3, 1), (1, 1, 64, 1)]}
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _cases(dtype, log_z0=False):
+    wls = []
+    for i, s in enumerate(SHAPES):
+        wl = configs.fractal(*s, rms=3.0, seed_offset=i) if log_z0 else configs.bumps_case(i, s)
+        if dtype == "f32":
+            wl = wl.cast(np.float32)
+        wls.append(wl)
+    return wls
+
+
+class Fields:
+    """Device copies of one case's inputs plus output buffers."""
+
+    def __init__(self, wl, tdt, dev):
+        import torch
+        T = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev, tdt)
+        self.u, self.v, self.w = T(wl.u), T(wl.v), T(wl.w)
+        self.lz = T(wl.log_z0) if wl.log_z0 is not None else None
+        self.tau0 = torch.stack([T(t) for t in wl.tau]).contiguous()
+        self.gp = [T(t) for t in wl.gradp]
+        self.tau = self.tau0.clone()
+        self.ustar = torch.stack([self.u, self.v, self.w]).contiguous()
+        self.div = torch.zeros_like(self.ustar)
+        self.drag = torch.zeros(3, dtype=torch.float64, device=dev)
+        self.stats = torch.zeros(4, dtype=torch.float64, device=dev)
+
+    def reset(self):
+        import torch
+        self.tau.copy_(self.tau0)
+        self.ustar.copy_(torch.stack([self.u, self.v, self.w]))
+        self.div.zero_()
+        self.drag.zero_()
+        self.stats.zero_()
+
+    def snapshot(self):
+        return {k: getattr(self, k).cpu().numpy().copy()
+                for k in ("tau", "div", "ustar", "drag", "stats")}
+
+
+def _plain(wl, tile, tdt, prec, dev):
+    import paper_2006_03343_amd as ibm
+    g = wl.grid
+    f = Fields(wl, tdt, dev)
+    ctx = ibm.Context(g.nx, g.ny, g.nz, dtype=tdt, precision=prec, device=dev)
+    ctx.set_tile(*tile)
+    T = lambda a: __import__("torch").from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev, tdt)
+    ctx.prepare(T(wl.phi_uv), T(wl.phi_w), wl.band_width, wl.phi_c, wl.kappa)
+    ctx.wall_stress(f.u, f.v, f.w, list(f.tau), z0=None if f.lz is not None else wl.z0,
+                    log_z0=f.lz, stats=f.stats)
+    ctx.apply(list(f.tau), list(f.ustar), list(f.div), gradp=f.gp, dt=wl.dt, drag=f.drag)
+    return f.snapshot()
+
+
+def _batch(wls, tiles, tdt, prec, dev):
+    import torch
+    import paper_2006_03343_amd as ibm
+    b = ibm.Batch([(w.grid.nx, w.grid.ny, w.grid.nz) for w in wls], dtype=tdt, precision=prec,
+                  device=dev)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev, tdt)
+    b.prepare([T(w.phi_uv) for w in wls], [T(w.phi_w) for w in wls], 1.5, [w.z0 for w in wls],
+              phi_c=1.5)
+    if tiles is not None:
+        for i, t in enumerate(tiles):
+            b.case(i).set_tile(*t)
+    fs = [Fields(w, tdt, dev) for w in wls]
+    for i, (w, f) in enumerate(zip(wls, fs)):
+        b.bind(i, f.u, f.v, f.w, list(f.tau), list(f.ustar), list(f.div), gradp=f.gp, dt=w.dt,
+               log_z0=f.lz, drag=f.drag, stats=f.stats)
+    return b, fs
+
+
+def _same(a, b, what):
+    for k in a:
+        assert np.array_equal(a[k], b[k]), f"{what}: {k} differs"
+
+
+@pytest.mark.parametrize("dtype,prec,lz", [("f32", "mixed", False), ("f64", "plain", False),
+                                           ("f32", "plain", True)])
+def test_batch_equals_plain_calls(ora, dtype, prec, lz):
+    torch, dev = torch_dev()
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    wls = _cases(dtype, lz)
+    tiles = TILES[dtype]
+    _say(f"batch of {len(wls)} cases {dtype} {prec} log_z0={lz}: run vs plain calls")
+    b, fs = _batch(wls, tiles, tdt, prec, dev)
+    b.run()
+    torch.cuda.synchronize()
+    for i, (w, f) in enumerate(zip(wls, fs)):
+        _same(f.snapshot(), _plain(w, tiles[i], tdt, prec, dev), f"case {i}")
+    # one case against the oracle
+    ref = ora.stage(wls[1])
+    out = dict(tau=fs[1].tau.cpu().numpy(), div=fs[1].div.cpu().numpy(),
+               ustar=fs[1].ustar.cpu().numpy(), drag=fs[1].drag.cpu().numpy(),
+               stats=fs[1].stats.cpu().numpy(), mask=b.case(1).mask(), counts=b.case(1).counts())
+    compare(out, ref, wls[1], TOL[dtype])
+
+
+def test_graph_replays_match_eager():
+    torch, dev = torch_dev()
+    wls = _cases("f32")
+    _say("batch f32 mixed: captured graph, 3 replays with eager work between")
+    b, fs = _batch(wls, TILES["f32"], torch.float32, "mixed", dev)
+    b.run()
+    torch.cuda.synchronize()
+    eager = [f.snapshot() for f in fs]
+    b.capture()
+    for rep in range(3):
+        for f in fs:
+            f.reset()
+        torch.cuda.synchronize()
+        junk = torch.randn(1 << 20, device=dev).sum()    # unrelated eager work
+        b.launch()
+        torch.cuda.synchronize()
+        for i, f in enumerate(fs):
+            _same(f.snapshot(), eager[i], f"replay {rep} case {i}")
+        del junk
+
+
+def test_batch_errors():
+    import paper_2006_03343_amd as ibm
+    from paper_2006_03343_amd import _lib
+    torch, dev = torch_dev()
+    _say("batch error paths")
+    wls = _cases("f32")[:2]
+    b = ibm.Batch([(w.grid.nx, w.grid.ny, w.grid.nz) for w in wls], dtype=torch.float32,
+                  device=dev)
+    with pytest.raises(ibm.IbmError) as e:
+        b.run()
+    assert e.value.code == _lib.IBM_E_STATE
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+    b.prepare([T(w.phi_uv) for w in wls], [T(w.phi_w) for w in wls], 1.5, [w.z0 for w in wls])
+    with pytest.raises(ibm.IbmError) as e:
+        b.run()                                   # case 0 and 1 unbound
+    assert e.value.code == _lib.IBM_E_STATE
+    with pytest.raises(ibm.IbmError) as e:
+        b.launch()                                # nothing captured
+    assert e.value.code == _lib.IBM_E_STATE
+    with pytest.raises(ibm.IbmError) as e:
+        b.prepare([T(w.phi_uv) for w in wls], [T(w.phi_w) for w in wls], 1.5, [2.0, 1e-3])
+    assert e.value.code == _lib.IBM_E_RANGE
+
+
+def test_autotune_cache(tmp_path):
+    import paper_2006_03343_amd as ibm
+    torch, dev = torch_dev()
+    wl = configs.hill(256, 128, 64, H=16.0, L=40.0, x0=64.0, y0=64.0).cast(np.float32)
+    g = wl.grid
+    _say("autotune 256x128x64 f32 mixed")
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    ctx = ibm.Context(g.nx, g.ny, g.nz, dtype=torch.float32, precision="mixed", device=dev)
+    ctx.prepare(T(wl.phi_uv), T(wl.phi_w), 1.5, 1.5)
+    path = str(tmp_path / "tune.json")
+    t1 = ctx.autotune(path)
+    entries = json.load(open(path))
+    assert len(entries) == 1 and list(entries.values())[0][:4] == list(t1)
+    ctx.set_tile(1, 1, 4, 1)
+    t2 = ctx.autotune(path)                        # read back from the cache
+    assert t2 == t1
+    t3 = ctx.autotune(path, force=True, batch=True)
+    assert t3[1] <= 2 and len(json.load(open(path))) == 2
+    # the divergence does not depend on the tile shape
+    wls = _cases("f32")[:3]
+    b, fs = _batch(wls, None, torch.float32, "mixed", dev)
+    b.tune(path)
+    b.run()
+    torch.cuda.synchronize()
+    for i, (w, f) in enumerate(zip(wls, fs)):
+        tile = b.case(i).get_tile()
+        assert tile[1] <= 2
+        _same(f.snapshot(), _plain(w, tile, torch.float32, "mixed", dev), f"tuned case {i}")
