@@ -13,7 +13,12 @@ algorithmic bytes per launch divided by its mean duration, measured with HIP
 events recorded on the kernel's stream around every launch of the timed
 region.  ``fp64_plain`` repeats the measurement with float64 storage.
 ``cpu_baseline`` times the FP64 CPU oracle (a test checker, never tuned) on
-full passes of the same hill.
+full passes of the same hill.  ``batched`` compares the 64-case ensemble of
+Gaussian-bump terrains advanced by one hipGraph launch of the batched kernels
+(float32, mixed) with the same cases advanced by plain per-case float64 calls.
+``adjoint`` times the forward pass and the hand-written reverse mode on the
+256 x 128 x 128 fractal terrain with a per-node log z0 field (float32 mixed).
+The dense-pass tile shape comes from the autotuner (cached under /tmp).
 """
 import argparse
 import json
@@ -25,6 +30,28 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+TUNE_CACHE = os.environ.get("IBM_TUNE_CACHE", "/tmp/ibm_tune_cache.json")
+PROFILE = os.path.join(ROOT, "profiles", "k_apply_hill512x256x256_f32_mixed.txt")
+
+
+def measured_traffic(tile):
+    """HBM bytes per k_apply launch from the committed counter profile, if the
+    dense-pass source and the tile shape are the ones that were profiled."""
+    import hashlib
+    src = b""
+    for f in ("kernels.h", "stage.hip"):
+        src += open(os.path.join(ROOT, "paper_2006_03343_amd", "csrc", f), "rb").read()
+    h = hashlib.sha256(src).hexdigest()
+    try:
+        lines = open(PROFILE).read().splitlines()
+    except OSError:
+        return None
+    kv = dict(ln.split(": ", 1) for ln in lines if ": " in ln and not ln.startswith(" "))
+    if kv.get("source_sha256 (csrc/kernels.h + csrc/stage.hip)") != h:
+        return None
+    if kv.get("tile") != ",".join(str(x) for x in tile):
+        return None
+    return int(kv["traffic_bytes_per_launch"])
 
 
 def log(msg):
@@ -55,12 +82,14 @@ def run_gpu(wl, dtype, precision, steps, warmup, tile=None):
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev, tdt)
     ctx = ibm.Context(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, dtype=tdt, precision=precision,
                       device=dev)
-    if tile:
-        ctx.set_tile(*tile)
     t0 = time.time()
     ctx.prepare(T(wl.phi_uv), T(wl.phi_w), wl.band_width, wl.phi_c, wl.kappa)
     torch.cuda.synchronize()
     t_prep = time.time() - t0
+    if tile:
+        ctx.set_tile(*tile)
+    else:
+        ctx.autotune(TUNE_CACHE)
     u, v, w = T(wl.u), T(wl.v), T(wl.w)
     tau = torch.stack([T(t) for t in wl.tau]).contiguous()
     gp = [T(t) for t in wl.gradp]
@@ -104,6 +133,136 @@ def run_gpu(wl, dtype, precision, steps, warmup, tile=None):
     return res
 
 
+def _events(n):
+    import torch
+    return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+
+
+def run_ensemble(steps, warmup, ncases=64):
+    """64 Gaussian-bump terrains on uneven grids: batched float32 (mixed) graph
+    launches vs plain per-case float64 calls."""
+    import numpy as np
+    import torch
+
+    import paper_2006_03343_amd as ibm
+    from workloads import configs
+    dev = torch.device("cuda", 0)
+    shapes = configs.ensemble_shapes(ncases)
+    t0 = time.time()
+    f32, f64 = [], []
+    z0 = []
+    for i, shp in enumerate(shapes):
+        wl = configs.bumps_case(i, shp)
+        z0.append(wl.z0)
+        for store, tdt in ((f32, torch.float32), (f64, torch.float64)):
+            if tdt == torch.float32:
+                w = wl.cast(np.float32)
+            else:
+                w = wl
+            T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev, tdt)
+            d = dict(phi_uv=T(w.phi_uv), phi_w=T(w.phi_w), u=T(w.u), v=T(w.v), w=T(w.w),
+                     tau=torch.stack([T(t) for t in w.tau]).contiguous(),
+                     gp=[T(t) for t in w.gradp], dt=w.dt)
+            d["ustar"] = torch.stack([d["u"], d["v"], d["w"]]).contiguous()
+            d["div"] = torch.empty_like(d["ustar"])
+            d["drag"] = torch.zeros(3, dtype=torch.float64, device=dev)
+            d["stats"] = torch.zeros(4, dtype=torch.float64, device=dev)
+            store.append(d)
+        del wl
+    npts = sum(a * b * c for a, b, c in shapes)
+    log(f"ensemble: {ncases} cases, {npts} points, generated in {time.time() - t0:.1f} s")
+    # batched float32, mixed precision, one graph launch per step
+    b = ibm.Batch(shapes, dtype=torch.float32, precision="mixed", device=dev)
+    b.prepare([d["phi_uv"] for d in f32], [d["phi_w"] for d in f32], 1.5, z0, phi_c=1.5)
+    b.tune(TUNE_CACHE)
+    for i, d in enumerate(f32):
+        b.bind(i, d["u"], d["v"], d["w"], list(d["tau"]), list(d["ustar"]), list(d["div"]),
+               gradp=d["gp"], dt=d["dt"], drag=d["drag"], stats=d["stats"])
+    b.capture()
+    for _ in range(warmup):
+        b.launch()
+    e0, e1 = _events(2)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        b.launch()
+    e1.record()
+    torch.cuda.synchronize()
+    ms32 = e0.elapsed_time(e1) / steps
+    # plain float64: two calls per case per step
+    ctxs = []
+    for shp, d, z in zip(shapes, f64, z0):
+        c = ibm.Context(*shp, dtype=torch.float64, device=dev)
+        c.prepare(d["phi_uv"], d["phi_w"], 1.5, 1.5)
+        c.autotune(TUNE_CACHE)
+        ctxs.append((c, d, z))
+
+    def plain_step():
+        for c, d, z in ctxs:
+            c.wall_stress(d["u"], d["v"], d["w"], list(d["tau"]), z0=z, stats=d["stats"])
+            c.apply(list(d["tau"]), list(d["ustar"]), list(d["div"]), gradp=d["gp"], dt=d["dt"],
+                    drag=d["drag"])
+
+    for _ in range(warmup):
+        plain_step()
+    steps64 = max(5, steps // 4)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps64):
+        plain_step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms64 = e0.elapsed_time(e1) / steps64
+    res = {"cases": ncases, "points": npts, "shapes": sorted(set(shapes)),
+           "f32_mixed_batched_graph": {"value": npts / (ms32 * 1e-3), "ms_per_step": ms32,
+                                       "launches_per_step": 1},
+           "f64_plain_per_case": {"value": npts / (ms64 * 1e-3), "ms_per_step": ms64,
+                                  "launches_per_step": 4 * ncases},
+           "ratio": ms64 / ms32}
+    del b, ctxs, f32, f64
+    torch.cuda.empty_cache()
+    return res
+
+
+def run_adjoint(steps, warmup):
+    """Forward pass and reverse mode on the fractal terrain (float32, mixed)."""
+    import numpy as np
+    import torch
+
+    import paper_2006_03343_amd as ibm
+    from workloads import configs
+    dev = torch.device("cuda", 0)
+    wl = configs.fractal().cast(np.float32)
+    g = wl.grid
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    ctx = ibm.Context(g.nx, g.ny, g.nz, dtype=torch.float32, precision="mixed", device=dev)
+    ctx.prepare(T(wl.phi_uv), T(wl.phi_w), wl.band_width, wl.phi_c, wl.kappa)
+    ctx.autotune(TUNE_CACHE)
+    u, v, w, lz = T(wl.u), T(wl.v), T(wl.w), T(wl.log_z0)
+    tau0 = [T(t) for t in wl.tau]
+    gp = [T(t) for t in wl.gradp]
+    fwd = lambda: ibm.stage_forward(ctx, u, v, w, tau0, gp, wl.dt, log_z0=lz)
+    tau, div, us, drag = fwd()
+    bwd = lambda: ctx.vjp(u, v, w, list(div), list(us), [1.0, 0.0, 0.0], log_z0=lz)
+    for _ in range(warmup):
+        fwd()
+        bwd()
+    e0, e1, e2 = _events(3)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        fwd()
+    e1.record()
+    for _ in range(steps):
+        bwd()
+    e2.record()
+    torch.cuda.synchronize()
+    f_ms, b_ms = e0.elapsed_time(e1) / steps, e1.elapsed_time(e2) / steps
+    return {"workload": f"fractal {g.nx}x{g.ny}x{g.nz}, per-node log z0, f32 mixed",
+            "forward_ms": f_ms, "backward_ms": b_ms, "backward_points_per_s": g.n / (b_ms * 1e-3),
+            "note": "forward = out-of-place stage pass incl. tensor copies; backward = ibm_stage_vjp"}
+
+
 def cpu_baseline(wl, budget_s=12.0, max_passes=4):
     """The FP64 oracle timed on full passes of the same workload (per-step work:
     wall stress, divergence, forcing, drag)."""
@@ -133,6 +292,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-f64", action="store_true", help="skip the float64 comparison run")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-case ensemble")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 384 MiB device-to-device copy three times, the "
+                         "reference that scales FETCH_SIZE / WRITE_SIZE counters")
     ap.add_argument("--tile", type=str, default=None, help="vx,ty,kz,wpb for ibm_apply")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -176,7 +340,7 @@ def main():
                    "tile": list(r32["tile"]), "band_records": r32["counts"][1] + r32["counts"][4]},
         "roofline": {"bound": "hbm", "kernel": "ibm_apply (k_apply)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(r32["tile"]),
                      "bytes_per_launch": b_apply, "launch_ms": r32["apply_ms"]},
         "kernels_ms": {"wall_stress": r32["wall_stress_ms"], "apply": r32["apply_ms"]},
         "prepare_s": r32["prepare_s"],
@@ -190,10 +354,23 @@ def main():
                              "apply_GBs": b64 / (r64["apply_ms"] * 1e-3) / 1e9,
                              "f32_mixed_over_f64": r64["ms_per_step"] / r32["ms_per_step"]}
         log(f"f64 plain: {r64['ms_per_step']:.4f} ms/step")
+    if not args.no_batch:
+        out["batched"] = run_ensemble(args.steps, args.warmup)
+        log(f"ensemble: {out['batched']['ratio']:.1f}x (f32 batched graph over f64 plain)")
+    if not args.no_adjoint:
+        out["adjoint"] = run_adjoint(max(5, args.steps // 4), args.warmup)
+        log(f"adjoint: {out['adjoint']}")
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(wl)
         log(f"cpu: {out['cpu_baseline']}")
+    if args.calib_copy:
+        src = torch.ones(3 << 25, dtype=torch.float32, device="cuda")    # 402,653,184 bytes
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = src.numel() * 4
     print(json.dumps(out), flush=True)
 
 
