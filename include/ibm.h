@@ -134,7 +134,8 @@ int ibm_stage_vjp(ibm_ctx* c, const void* u, const void* v, const void* w, doubl
 
 /* Tile shape of the dense pass (ibm_apply): a wave owns vx*64 nodes along x,
  * ty rows and kz planes; wpb waves per block.  vx in {1,2,4} (double: {1,2})
- * and must divide nx; ty in {1,2,4,8}; kz >= 1; wpb in 1..4.  The shape only
+ * and must divide nx; ty in {1,2,4,8}; kz >= 1; wpb in 1..4.  A batch accepts
+ * ty <= 2.  The shape only
  * changes speed and the summation order of the drag, never the divergence or
  * forcing values.  ibm_get_tile reports the shape in use (the default comes
  * from the grid size).  Errors: IBM_E_ARG for an unsupported shape. */

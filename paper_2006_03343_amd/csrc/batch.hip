@@ -2,13 +2,13 @@
 // the tile autotuner.
 //
 // Each case of a batch is an ordinary context (prepare.hip builds its masks,
-// band records and runs).  One step of the whole ensemble is three persistent
+// band records and segment lists).  One step of the whole ensemble is three persistent
 // kernels -- wall stress, dense pass, finalize -- captured once in a hipGraph
 // and replayed with a single hipGraphLaunch:
 //   * the grid of each kernel is sized to what the GPU holds at once, and its
 //     waves (dense pass) or blocks (wall stress) walk a work list that spans
-//     every case: (case, band block | solid run piece) for the wall stress and
-//     (case, forced run piece | wave-tile) for the dense pass;
+//     every case: (case, band block | solid segment) for the wall stress and
+//     (case, quarter of a forcing segment | wave-tile) for the dense pass;
 //   * the work list is cut into 8 contiguous slices of equal estimated cost,
 //     one per XCD (block b runs on XCD b % 8), so each XCD's L2 sees
 //     neighbouring tiles of the same case;
@@ -111,7 +111,10 @@ __global__ void __launch_bounds__(256) k_batch_apply(const ApplyArgs<T>* __restr
         const int shape = __builtin_amdgcn_readfirstlane(w.w);
         const ApplyArgs<T>& a = tab[cs];
         if (kind == 0) {
-            force_chunk<T>(a, a.fchunks[idx], lane, 64);
+            // one quarter of a forcing segment per wave
+            const Seg sg = a.fsegs[idx >> 2];
+            const int off = (idx & 3) * (kSeg / 4);
+            force_seg<T>(a, Seg{sg.q + off, min(kSeg / 4, sg.len - off), 0, 0}, lane, 64);
             continue;
         }
         switch (shape) {
@@ -207,14 +210,18 @@ int build_tables(ibm_batch* b) {
         ap[cs] = make_apply_args<T>(c, c->cfg, io.tau, io.ustar, io.gradp, io.dt, io.div, dr);
         flags[cs] = (c->precision == IBM_PREC_MIXED ? 1 : 0) | (io.log_z0 ? 2 : 0);
         const long nbb = ws[cs].nb_band;
-        for (long k = 0; k < nbb + c->nchunks; ++k) {
+        for (long k = 0; k < nbb + c->nzsegs; ++k) {
             wsi.push_back(make_int2(cs, (int)k));
-            wsc.push_back(k < nbb ? 1.0 : 0.25);   // a band block gathers; a run piece only writes
+            wsc.push_back(k < nbb ? 1.0 : 2.0);    // 256 gathering records; up to kSeg zeroed nodes
         }
-        for (long k = 0; k < c->nfchunks; ++k) {
-            api.push_back(make_int4(cs, 0, (int)k, 0));
-            apc.push_back(0.3 * kChunk);
-        }
+        std::vector<Seg> fs(c->nfsegs);
+        if (c->nfsegs)
+            IBM_HIP(hipMemcpy(fs.data(), c->fsegs, sizeof(Seg) * c->nfsegs, hipMemcpyDeviceToHost));
+        for (long k = 0; k < c->nfsegs; ++k)
+            for (int part = 0; part < 4 && part * (kSeg / 4) < fs[k].len; ++part) {
+                api.push_back(make_int4(cs, 0, (int)(4 * k + part), 0));
+                apc.push_back(0.5 * (kSeg / 4));
+            }
         const int shape = 10 * c->cfg.vx + c->cfg.ty;
         const double tile_pts = 64.0 * c->cfg.vx * c->cfg.ty * c->cfg.kz;
         for (long t = 0; t < ap[cs].ntiles; ++t) {

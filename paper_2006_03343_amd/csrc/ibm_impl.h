@@ -8,10 +8,10 @@
 //  * records : one structure-of-arrays per grid with the band nodes in ascending
 //              linear index: index, unit normal, phi, and the trilinear stencil of
 //              the sample point on the uv and on the w node set
-//  * chunks  : runs of solid nodes along x, split into pieces of at most
-//              kChunk nodes, whose stress components are zeroed each step
-//  * fchunks : runs of forced nodes (phi <= 0) along x, split the same way,
-//              whose intermediate velocity is forced each step
+//  * zsegs   : segments of kSeg consecutive linear indices holding a solid node
+//              of either grid; their solid nodes' stress is zeroed each step
+//  * fsegs   : segments holding a forced node (phi <= 0) of either grid; their
+//              forced nodes' intermediate velocity is set each step
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -25,7 +25,7 @@
 namespace ibm {
 
 constexpr int kWave = 64;
-constexpr int kChunk = 1024;
+constexpr int kSeg = 4096;
 constexpr int kBandBlock = 256;
 
 // Band records of one grid.  T arrays are the context's storage type.
@@ -61,10 +61,12 @@ inline RecView<T> view(const Records& r) {
                       (const T*)r.fzu, (const T*)r.fzw};
 }
 
-struct Chunk {
-    int32_t q;     // first linear index of the run piece
-    int32_t len;   // number of nodes (<= kChunk)
-    int32_t grid;  // 0: zero xx, yy, zz, xy; 1: zero xz, yz; 2: force u, v; 3: force w
+// A segment of consecutive linear indices [q, q + len), len <= kSeg, and which
+// grids hold a solid (zsegs) or forced (fsegs) node in it: bit 0 uv, bit 1 w.
+struct Seg {
+    int32_t q;
+    int32_t len;
+    int32_t sel;
     int32_t pad;
 };
 
@@ -101,10 +103,10 @@ struct ibm_ctx {
     uint32_t* fmask = nullptr;
     int64_t counts[6] = {0, 0, 0, 0, 0, 0};
     ibm::Records rec[2];
-    long nchunks = 0;
-    ibm::Chunk* chunks = nullptr;
-    long nfchunks = 0;
-    ibm::Chunk* fchunks = nullptr;
+    long nzsegs = 0;
+    ibm::Seg* zsegs = nullptr;
+    long nfsegs = 0;
+    ibm::Seg* fsegs = nullptr;
     double* ws_partials = nullptr;      // wall_stress block slots (4 per band block)
     long ws_cap = 0;                    // in doubles
     double* ap_partials = nullptr;      // apply wave slots (3 per tile)

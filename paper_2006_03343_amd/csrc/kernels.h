@@ -9,8 +9,9 @@
 // is the rotation tau_ij = a_im a_jn tau'_mn of the local tensor whose only
 // non-zero entries are tau'_13 = tau'_31 = tau_w = -c |U_r|^2 (eq.
 // bc-bottom-immersed), written without forming the frame.  uv records store
-// xx, yy, zz, xy and w records xz, yz (§3.3).  Other blocks zero the stress on
-// runs of solid nodes (§3.3: stress inside the body set to zero).
+// xx, yy, zz, xy and w records xz, yz (§3.3).  Other blocks zero the stress of
+// the solid nodes of one kSeg-node segment each (§3.3: stress inside the body
+// set to zero): a whole block per segment, its mask bytes read first.
 //
 // Dense pass: one read of the six stress fields and one write of the three
 // divergence components per node (HBM bound, no matrix cores).  A wave owns a
@@ -26,8 +27,9 @@
 //     ahead);
 //   * per plane every load is issued first, branch-free, so a wave waits for
 //     memory once per plane; no LDS and no barriers.
-// Forcing (eq. u-*-IBM) runs on runs of nodes with phi <= 0; the tiles read
-// the 2-bit forcing flags only to leave forced nodes out of the drag.  Each
+// Forcing (eq. u-*-IBM) runs on the kSeg-node segments that hold nodes with
+// phi <= 0; the tiles read the 2-bit forcing flags only to leave forced nodes
+// out of the drag.  Each
 // tile leaves its drag partial in a fixed slot; finalize_slots adds the slots
 // in slot order, so results are deterministic and no atomics are used.
 #pragma once
@@ -45,7 +47,8 @@ struct WSArgs {
     RecView<T> rec[2];
     const T *u, *v, *w, *log_z0;
     T* tau[6];
-    const Chunk* chunks;
+    const Seg* zsegs;              // segments holding solid nodes
+    const uint8_t* mask;           // node classes, one byte per linear index
     int nx, ny, nz;
     long plane;
     int nb_uv, nb_band;            // blocks of uv records, of all records (>= 1)
@@ -70,29 +73,52 @@ __device__ inline T trilerp(const T* __restrict__ f, long c00, long c10, long c0
     return lo * gz + hi * fz;
 }
 
+// Stress of the solid nodes of one segment set to zero, by ``nthr`` threads
+// numbered ``tid``: thread tid takes nodes q + tid + i * nthr, so each store
+// of a wave is contiguous.  kPer mask bytes per thread are loaded before any
+// store (byte loads may alias the stores, so the compiler would not hoist
+// them); offsets are 32-bit (a context holds fewer than 2^31 nodes).
+template <typename T>
+__device__ inline void zero_seg(const WSArgs<T>& a, const Seg sg, int tid, int nthr) {
+    constexpr int kPer = 4;
+    const uint8_t* __restrict__ mk = a.mask + sg.q;
+    T* __restrict__ t0 = a.tau[0] + sg.q;
+    T* __restrict__ t1 = a.tau[1] + sg.q;
+    T* __restrict__ t2 = a.tau[2] + sg.q;
+    T* __restrict__ t3 = a.tau[3] + sg.q;
+    T* __restrict__ t4 = a.tau[4] + sg.q;
+    T* __restrict__ t5 = a.tau[5] + sg.q;
+    for (int o = tid; o < sg.len; o += kPer * nthr) {
+        uint32_t m[kPer];
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int t = o + i * nthr;
+            m[i] = t < sg.len ? mk[t] : 0u;
+        }
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int t = o + i * nthr;
+            if ((m[i] & 3u) == 2u) {
+                t0[t] = T(0);
+                t1[t] = T(0);
+                t2[t] = T(0);
+                t3[t] = T(0);
+            }
+            if (((m[i] >> 2) & 3u) == 2u) {
+                t4[t] = T(0);
+                t5[t] = T(0);
+            }
+        }
+    }
+}
+
 // One block of the wall-stress pass: block b < nb_band handles kBandBlock band
 // records (uv records first, then w records) and leaves its statistics in slot
-// b; block b >= nb_band zeroes one piece of a solid run.
+// b; block b >= nb_band zeroes the solid nodes of segment b - nb_band.
 template <typename T, bool MIXED, bool HAS_LZ>
 __device__ inline void ws_block(const WSArgs<T>& a, int b) {
     if (b >= a.nb_band) {
-        // zero the stress components of one piece of a solid run
-        const Chunk ch = a.chunks[b - a.nb_band];
-        if (ch.grid == IBM_GRID_UV) {
-            for (int t = threadIdx.x; t < ch.len; t += blockDim.x) {
-                const long q = (long)ch.q + t;
-                a.tau[0][q] = T(0);
-                a.tau[1][q] = T(0);
-                a.tau[2][q] = T(0);
-                a.tau[3][q] = T(0);
-            }
-        } else {
-            for (int t = threadIdx.x; t < ch.len; t += blockDim.x) {
-                const long q = (long)ch.q + t;
-                a.tau[4][q] = T(0);
-                a.tau[5][q] = T(0);
-            }
-        }
+        zero_seg<T>(a, a.zsegs[b - a.nb_band], threadIdx.x, blockDim.x);
         return;
     }
     const int kind = b < a.nb_uv ? IBM_GRID_UV : IBM_GRID_W;
@@ -201,6 +227,7 @@ struct ApplyArgs {
     const T* gradp[3];
     T* div[3];
     const uint32_t* fmask;
+    const uint8_t* mask;     // node classes and forcing flags, one byte per node
     int nx, ny, nz, wrow;
     long plane;
     T cx, cy, cz;            // 1/(2 dx), 1/(2 dy), 1/dz
@@ -211,9 +238,9 @@ struct ApplyArgs {
     int per_xcd;             // logical blocks per XCD
     double* partials;        // 3 per tile
     double* drag;            // nullable
-    const Chunk* fchunks;    // runs of forced nodes
+    const Seg* fsegs;        // segments holding forced nodes
     int nfblocks;            // leading blocks that force (a multiple of 8)
-    long nfchunks;
+    long nfsegs;
     double dv;
 };
 
@@ -262,17 +289,48 @@ __device__ inline Vec<T, VX> xdiff(const Vec<T, VX>& r, T edge, int lane, bool l
 // The dense pass.  Per plane every load is issued first, without branches
 // (lanes past the end of the row read a valid clamped address and discard
 // it), so a wave waits for memory once per plane.
-// Direct forcing (eq. u-*-IBM) of one run of nodes with phi <= 0, by
-// ``nthr`` threads numbered ``tid``.
+// Direct forcing (eq. u-*-IBM) of the forced nodes of one segment, by
+// ``nthr`` threads numbered ``tid`` taking nodes q + tid + i * nthr; per round
+// of kPer nodes a thread loads the mask bytes, then the pressure gradient of
+// its forced nodes (exec-masked loads), then stores, so it waits for memory
+// twice per round.
 template <typename T>
-__device__ inline void force_chunk(const ApplyArgs<T>& a, const Chunk ch, int tid, int nthr) {
-    for (int t = tid; t < ch.len; t += nthr) {
-        const long q = (long)ch.q + t;
-        if (ch.grid == 2) {
-            a.ustar[0][q] = a.gradp[0] ? a.fdt * a.gradp[0][q] : T(0);
-            a.ustar[1][q] = a.gradp[1] ? a.fdt * a.gradp[1][q] : T(0);
-        } else {
-            a.ustar[2][q] = a.gradp[2] ? a.fdt * a.gradp[2][q] : T(0);
+__device__ inline void force_seg(const ApplyArgs<T>& a, const Seg sg, int tid, int nthr) {
+    constexpr int kPer = 4;
+    const uint8_t* __restrict__ mk = a.mask + sg.q;
+    const T* __restrict__ g0 = a.gradp[0] ? a.gradp[0] + sg.q : nullptr;
+    const T* __restrict__ g1 = a.gradp[1] ? a.gradp[1] + sg.q : nullptr;
+    const T* __restrict__ g2 = a.gradp[2] ? a.gradp[2] + sg.q : nullptr;
+    T* __restrict__ u0 = a.ustar[0] + sg.q;
+    T* __restrict__ u1 = a.ustar[1] + sg.q;
+    T* __restrict__ u2 = a.ustar[2] + sg.q;
+    const T f = a.fdt;
+    for (int o = tid; o < sg.len; o += kPer * nthr) {
+        uint32_t m[kPer];
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int t = o + i * nthr;
+            m[i] = t < sg.len ? mk[t] : 0u;
+        }
+        T p0[kPer], p1[kPer], p2[kPer];
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int t = o + i * nthr;
+            p0[i] = p1[i] = p2[i] = T(0);
+            if (m[i] & 16u) {
+                if (g0) p0[i] = g0[t];
+                if (g1) p1[i] = g1[t];
+            }
+            if ((m[i] & 32u) && g2) p2[i] = g2[t];
+        }
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int t = o + i * nthr;
+            if (m[i] & 16u) {
+                u0[t] = g0 ? f * p0[i] : T(0);
+                u1[t] = g1 ? f * p1[i] : T(0);
+            }
+            if (m[i] & 32u) u2[t] = g2 ? f * p2[i] : T(0);
         }
     }
 }
@@ -428,7 +486,8 @@ inline WSArgs<T> make_ws_args(const ibm_ctx* c, const T* u, const T* v, const T*
     a.w = w;
     a.log_z0 = log_z0;
     for (int i = 0; i < 6; ++i) a.tau[i] = (T*)tau[i];
-    a.chunks = c->chunks;
+    a.zsegs = c->zsegs;
+    a.mask = c->mask;
     a.nx = c->g.nx;
     a.ny = c->g.ny;
     a.nz = c->g.nz;
@@ -456,6 +515,7 @@ inline ApplyArgs<T> make_apply_args(const ibm_ctx* c, const TileCfg& cfg, const 
         a.div[i] = (T*)div[i];
     }
     a.fmask = c->fmask;
+    a.mask = c->mask;
     a.nx = c->g.nx;
     a.ny = c->g.ny;
     a.nz = c->g.nz;
@@ -475,8 +535,8 @@ inline ApplyArgs<T> make_apply_args(const ibm_ctx* c, const TileCfg& cfg, const 
     a.partials = c->ap_partials;
     a.drag = drag;
     a.dv = c->g.dx * c->g.dy * c->g.dz;
-    a.fchunks = c->fchunks;
-    a.nfchunks = c->nfchunks;
+    a.fsegs = c->fsegs;
+    a.nfsegs = c->nfsegs;
     a.nfblocks = 0;
     return a;
 }

@@ -11,7 +11,8 @@
 //   3. one record per band node: the unit normal (§3.1; central differences on
 //      the node's own grid), phi, and the trilinear stencil of the sample point
 //      x + (phi_c - phi) n on both node sets (§3.3);
-//   4. runs of solid nodes along x, cut into pieces for the per-step zeroing.
+//   4. lists of the kSeg-node segments that hold a solid node (zeroed by the
+//      wall-stress pass) or a forced node (forced by the apply pass).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -136,46 +137,23 @@ __global__ void k_compact(const uint8_t* __restrict__ mask, long n, const long* 
     }
 }
 
-// Runs along x, one thread per (k, j) row, cut into pieces of at most kChunk
-// nodes.  mode 0: solid nodes (class 2) of the uv grid (tag IBM_GRID_UV) and of
-// the w grid (tag IBM_GRID_W); mode 1: forced nodes (phi <= 0) of the uv grid
-// (tag 2) and of the w grid (tag 3).  With out == nullptr only counts.
-__device__ inline bool in_run(uint8_t m, int mode, int grid) {
-    if (mode == 0) return ((m >> (2 * grid)) & 3) == 2;
-    return (m >> (4 + grid)) & 1;
-}
-
-__global__ void k_row_chunks(const uint8_t* __restrict__ mask, int nx, long rows, int mode,
-                             const long* __restrict__ row_off, Chunk* __restrict__ out,
-                             int* __restrict__ row_cnt) {
-    long row = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (row >= rows) return;
-    const uint8_t* m = mask + row * nx;
-    long o = out ? row_off[row] : 0;
-    int cnt = 0;
-    for (int grid = 0; grid < 2; ++grid) {
-        int x = 0;
-        while (x < nx) {
-            if (!in_run(m[x], mode, grid)) {
-                ++x;
-                continue;
-            }
-            int s = x;
-            while (x < nx && in_run(m[x], mode, grid)) ++x;
-            for (int c0 = s; c0 < x; c0 += kChunk) {
-                if (out) {
-                    Chunk ch;
-                    ch.q = (int32_t)(row * nx + c0);
-                    ch.len = min(kChunk, x - c0);
-                    ch.grid = grid + 2 * mode;
-                    ch.pad = 0;
-                    out[o + cnt] = ch;
-                }
-                ++cnt;
-            }
-        }
+// Per segment of kSeg linear indices: bit 0 some uv node solid, bit 1 some w
+// node solid, bit 2 some uv node forced, bit 3 some w node forced.
+__global__ void __launch_bounds__(256) k_seg_flags(const uint8_t* __restrict__ mask, long n,
+                                                   uint8_t* __restrict__ flags) {
+    __shared__ int acc;
+    if (threadIdx.x == 0) acc = 0;
+    __syncthreads();
+    const long q0 = (long)blockIdx.x * kSeg;
+    int bits = 0;
+    for (int t = threadIdx.x; t < kSeg; t += blockDim.x) {
+        if (q0 + t >= n) break;
+        const int m = mask[q0 + t];
+        bits |= ((m & 3) == 2 ? 1 : 0) | (((m >> 2) & 3) == 2 ? 2 : 0) | (((m >> 4) & 3) << 2);
     }
-    if (row_cnt) row_cnt[row] = cnt;
+    if (bits) atomicOr(&acc, bits);
+    __syncthreads();
+    if (threadIdx.x == 0) flags[blockIdx.x] = (uint8_t)acc;
 }
 
 struct RecOut {
@@ -388,34 +366,32 @@ int prepare_t(ibm_ctx* c, const T* pu, const T* pw, hipStream_t s) {
             hipLaunchKernelGGL((k_records<T, false>), dim3(nblk(R.n, 256)), dim3(256), 0, s, ph,
                                kind, R.n, o, ga);
     }
-    // solid runs (zeroed by wall_stress) and forced runs (forced by apply)
-    int* rcnt = nullptr;
-    long* droff = nullptr;
-    IBM_HIP(hipMalloc(&rcnt, sizeof(int) * (size_t)rows));
-    IBM_HIP(hipMalloc(&droff, sizeof(long) * (size_t)rows));
-    std::vector<int> hr(rows);
-    std::vector<long> roff(rows);
-    for (int mode = 0; mode < 2; ++mode) {
-        hipLaunchKernelGGL(k_row_chunks, dim3(nblk(rows, 256)), dim3(256), 0, s, c->mask, nx, rows,
-                           mode, (const long*)nullptr, (Chunk*)nullptr, rcnt);
-        IBM_HIP(hipMemcpyAsync(hr.data(), rcnt, sizeof(int) * rows, hipMemcpyDeviceToHost, s));
-        IBM_HIP(hipStreamSynchronize(s));
-        long tot = 0;
-        for (long r = 0; r < rows; ++r) {
-            roff[r] = tot;
-            tot += hr[r];
-        }
-        Chunk** dst = mode == 0 ? &c->chunks : &c->fchunks;
-        (mode == 0 ? c->nchunks : c->nfchunks) = tot;
-        IBM_HIP(hipMalloc(dst, sizeof(Chunk) * (size_t)std::max<long>(tot, 1)));
-        IBM_HIP(hipMemcpyAsync(droff, roff.data(), sizeof(long) * rows, hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(k_row_chunks, dim3(nblk(rows, 256)), dim3(256), 0, s, c->mask, nx, rows,
-                           mode, (const long*)droff, *dst, (int*)nullptr);
-        IBM_HIP(hipGetLastError());
-        IBM_HIP(hipStreamSynchronize(s));
+    // segments with solid nodes (zeroed by wall_stress) and with forced nodes
+    // (forced by apply)
+    const long nseg = (n + kSeg - 1) / kSeg;
+    uint8_t* dflags = nullptr;
+    IBM_HIP(hipMalloc(&dflags, (size_t)nseg));
+    hipLaunchKernelGGL(k_seg_flags, dim3((unsigned)nseg), dim3(256), 0, s, c->mask, n, dflags);
+    IBM_HIP(hipGetLastError());
+    std::vector<uint8_t> hf(nseg);
+    IBM_HIP(hipMemcpyAsync(hf.data(), dflags, (size_t)nseg, hipMemcpyDeviceToHost, s));
+    IBM_HIP(hipStreamSynchronize(s));
+    (void)hipFree(dflags);
+    std::vector<Seg> zs, fs;
+    for (long i = 0; i < nseg; ++i) {
+        const int32_t q = (int32_t)(i * kSeg);
+        const int32_t len = (int32_t)std::min<long>(kSeg, n - i * kSeg);
+        if (hf[i] & 3) zs.push_back(Seg{q, len, hf[i] & 3, 0});
+        if (hf[i] & 12) fs.push_back(Seg{q, len, (hf[i] >> 2) & 3, 0});
     }
-    (void)hipFree(droff);
-    (void)hipFree(rcnt);
+    c->nzsegs = (long)zs.size();
+    c->nfsegs = (long)fs.size();
+    IBM_HIP(hipMalloc(&c->zsegs, sizeof(Seg) * std::max<size_t>(zs.size(), 1)));
+    IBM_HIP(hipMalloc(&c->fsegs, sizeof(Seg) * std::max<size_t>(fs.size(), 1)));
+    if (!zs.empty())
+        IBM_HIP(hipMemcpy(c->zsegs, zs.data(), sizeof(Seg) * zs.size(), hipMemcpyHostToDevice));
+    if (!fs.empty())
+        IBM_HIP(hipMemcpy(c->fsegs, fs.data(), sizeof(Seg) * fs.size(), hipMemcpyHostToDevice));
     (void)hipFree(doff);
     (void)hipFree(bc);
     return IBM_OK;
@@ -432,12 +408,12 @@ void free_prepared(ibm_ctx* c) {
         (void)hipFree(c->rec[k].buf);
         c->rec[k] = Records();
     }
-    (void)hipFree(c->chunks);
-    c->chunks = nullptr;
-    c->nchunks = 0;
-    (void)hipFree(c->fchunks);
-    c->fchunks = nullptr;
-    c->nfchunks = 0;
+    (void)hipFree(c->zsegs);
+    c->zsegs = nullptr;
+    c->nzsegs = 0;
+    (void)hipFree(c->fsegs);
+    c->fsegs = nullptr;
+    c->nfsegs = 0;
     free_adjoint(c);
     c->prepared = false;
 }

@@ -21,15 +21,15 @@ __global__ void __launch_bounds__(256) k_finalize(const double* __restrict__ p, 
     finalize_slots(p, nslots, nc, maxmask, scale, out);
 }
 
-// Leading blocks force runs of nodes with phi <= 0; the other blocks own
+// Leading blocks force the segments holding nodes with phi <= 0; the other blocks own
 // wave-tiles, taken in an XCD-aware order (the dispatcher deals blocks to the
 // 8 XCDs round-robin, so block b runs on XCD b % 8 and consecutive tiles --
 // which share halos -- are given to the same XCD's L2).
 template <typename T, typename Acc, int VX, int TY>
 __global__ void __launch_bounds__(256) k_apply(ApplyArgs<T> a) {
     if ((int)blockIdx.x < a.nfblocks) {
-        for (long ci = blockIdx.x; ci < a.nfchunks; ci += a.nfblocks)
-            force_chunk<T>(a, a.fchunks[ci], threadIdx.x, blockDim.x);
+        for (long si = blockIdx.x; si < a.nfsegs; si += a.nfblocks)
+            force_seg<T>(a, a.fsegs[si], threadIdx.x, blockDim.x);
         return;
     }
     const int lane = threadIdx.x & 63;
@@ -46,7 +46,7 @@ int wall_stress_t(ibm_ctx* c, const T* u, const T* v, const T* w, double z0, con
                   void* const tau[6], double* stats, hipStream_t s) {
     WSArgs<T> a = make_ws_args<T>(c, u, v, w, z0, log_z0, tau, stats);
     if (c->ws_cap < 4L * a.nb_band) return fail(IBM_E_STATE, "wall_stress: reduction slots not sized");
-    const unsigned grid = (unsigned)(a.nb_band + c->nchunks);
+    const unsigned grid = (unsigned)(a.nb_band + c->nzsegs);
     const bool mixed = c->precision == IBM_PREC_MIXED;
     if (mixed && log_z0)
         hipLaunchKernelGGL((k_wall_stress<T, true, true>), dim3(grid), dim3(kBandBlock), 0, s, a);
@@ -98,7 +98,7 @@ int apply_t(ibm_ctx* c, const TileCfg& cfg, const void* const tau[6], void* cons
             hipStream_t s) {
     ApplyArgs<T> a = make_apply_args<T>(c, cfg, tau, ustar, gradp, dt, div, drag);
     if (c->ap_cap < 3 * a.ntiles) return fail(IBM_E_STATE, "apply: reduction slots not sized");
-    a.nfblocks = (int)std::min<long>((c->nfchunks + 7) / 8 * 8, 1024);
+    a.nfblocks = (int)std::min<long>((c->nfsegs + 7) / 8 * 8, 1024);
     const unsigned grid = (unsigned)(a.nfblocks + 8 * a.per_xcd);
     const unsigned block = (unsigned)(64 * cfg.wpb);
     bool ok;

@@ -179,9 +179,10 @@ def test_errors_are_reported():
     with pytest.raises(ibm.IbmError) as e:
         ctx.wall_stress(z, z, z, [z.clone() for _ in range(6)], z0=2.0)
     assert e.value.code == _lib.IBM_E_RANGE
-    with pytest.raises(ibm.IbmError) as e:
-        ctx.set_tile(3, 4, 16, 4)
-    assert e.value.code == _lib.IBM_E_ARG
+    for bad in ((3, 4, 16, 4), (8, 1, 16, 1), (4, 16, 4, 1)):
+        with pytest.raises(ibm.IbmError) as e:
+            ctx.set_tile(*bad)
+        assert e.value.code == _lib.IBM_E_ARG
     with pytest.raises(TypeError):
         ctx.wall_stress(z.float(), z, z, [z] * 6, z0=1e-3)
     assert ctx.counts()[0] == 512
