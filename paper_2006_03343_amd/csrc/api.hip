@@ -120,6 +120,7 @@ int ibm_levelset_prepare(ibm_ctx* c, const void* phi_uv, const void* phi_w, cons
     if (!finite_pos(q.kappa)) return fail(IBM_E_RANGE, "ibm_levelset_prepare: kappa must be > 0");
     DeviceScope dg(c->device);
     c->p = q;
+    ++c->gen;
     rc = prepare(c, phi_uv, phi_w, (hipStream_t)stream);
     if (rc) return rc;
     return size_partials(c);
@@ -244,6 +245,7 @@ int ibm_set_tile(ibm_ctx* c, int vx, int ty, int kz, int wpb) {
                     kz, wpb);
     DeviceScope dg(c->device);
     c->cfg = t;
+    ++c->gen;
     return c->prepared ? size_partials(c) : IBM_OK;
 }
 

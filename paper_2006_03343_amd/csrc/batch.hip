@@ -35,14 +35,6 @@ struct Split {
     long off[9];
 };
 
-struct FinJob {
-    const double* p;
-    long nslots;
-    int nc;
-    unsigned maxmask;
-    double scale;
-    double* out;
-};
 
 }  // namespace ibm
 
@@ -57,6 +49,7 @@ struct ibm_batch {
     std::vector<double> z0;
     bool prepared = false;
     bool tables = false;
+    std::vector<unsigned long> gens;  // ibm_ctx::gen of each case when the tables were built
     void* ws_tab = nullptr;        // WSArgs<T>[ncases]
     void* ap_tab = nullptr;        // ApplyArgs<T>[ncases]
     int* ws_flags = nullptr;       // per case: bit 0 mixed, bit 1 per-node log z0
@@ -156,6 +149,8 @@ Split split_by_cost(const std::vector<double>& cost) {
 }
 
 void free_tables(ibm_batch* b) {
+    // a replay or run of the old tables may still be in flight
+    if (b->exec || b->ws_tab) (void)hipDeviceSynchronize();
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
@@ -203,6 +198,15 @@ int build_tables(ibm_batch* b) {
         if (c->cfg.ty > 2 || (sizeof(T) == 8 && c->cfg.vx > 2))
             return fail(IBM_E_ARG, "batch: case %d tile shape vx=%d ty=%d is not batchable (ty <= 2)",
                         cs, c->cfg.vx, c->cfg.ty);
+        if (c->cfg.vx > 1) {
+            // vx > 1 moves 16-byte vectors of the stress and divergence fields
+            bool al = true;
+            for (int i = 0; i < 6; ++i) al = al && (uintptr_t)io.tau[i] % 16 == 0;
+            for (int i = 0; i < 3; ++i) al = al && (uintptr_t)io.div[i] % 16 == 0;
+            if (!al)
+                return fail(IBM_E_ARG, "batch: case %d: tau or div not 16-byte aligned for tile vx=%d",
+                            cs, c->cfg.vx);
+        }
         double* st = io.stats_dev ? io.stats_dev : b->stats + 4 * cs;
         double* dr = io.drag_dev ? io.drag_dev : b->drag + 3 * cs;
         ws[cs] = make_ws_args<T>(c, (const T*)io.u, (const T*)io.v, (const T*)io.w, b->z0[cs],
@@ -234,6 +238,8 @@ int build_tables(ibm_batch* b) {
     b->nws = (long)wsi.size();
     b->nap = (long)api.size();
     b->nfin = (int)fin.size();
+    b->gens.resize(n);
+    for (int cs = 0; cs < n; ++cs) b->gens[cs] = b->cases[cs]->gen;
     b->ws_split = split_by_cost(wsc);
     b->ap_split = split_by_cost(apc);
     IBM_HIP(hipMalloc(&b->ws_tab, sizeof(WSArgs<T>) * n));
@@ -281,8 +287,18 @@ int enqueue(ibm_batch* b, hipStream_t s) {
     return IBM_OK;
 }
 
+// True when a case's tile shape or prepared buffers changed after the tables
+// were built (ibm_set_tile, ibm_autotune or ibm_levelset_prepare on a case).
+bool stale(const ibm_batch* b) {
+    if (!b->tables) return true;
+    for (int cs = 0; cs < b->ncases; ++cs)
+        if (b->gens[cs] != b->cases[cs]->gen) return true;
+    return false;
+}
+
 int ensure_tables(ibm_batch* b) {
-    if (b->tables) return IBM_OK;
+    if (b->tables && !stale(b)) return IBM_OK;
+    free_tables(b);
     for (int cs = 0; cs < b->ncases; ++cs)
         if (!b->bound[cs]) return fail(IBM_E_STATE, "batch: case %d is not bound", cs);
     return b->dtype == IBM_F64 ? build_tables<double>(b) : build_tables<float>(b);
@@ -346,6 +362,7 @@ void write_cache(const char* path, const std::map<std::string, std::vector<doubl
 
 int set_cfg(ibm_ctx* c, const TileCfg& t) {
     c->cfg = t;
+    ++c->gen;
     return size_partials(c);
 }
 
@@ -615,8 +632,9 @@ int ibm_batch_capture(ibm_batch* b, void* stream) {
 int ibm_batch_launch(ibm_batch* b, void* stream) {
     int rc = check_batch(b, true, "ibm_batch_launch");
     if (rc) return rc;
-    if (!b->exec || !b->tables)
-        return fail(IBM_E_STATE, "ibm_batch_launch: capture the batch (again) after binding");
+    if (!b->exec || stale(b))
+        return fail(IBM_E_STATE,
+                    "ibm_batch_launch: capture the batch (again) after binding, preparing or changing a tile");
     DeviceScope ds(b->device);
     IBM_HIP(hipGraphLaunch(b->exec, (hipStream_t)stream));
     return IBM_OK;

@@ -113,6 +113,9 @@ struct ibm_ctx {
     long ap_cap = 0;                    // in doubles
     ibm::TileCfg cfg;
     ibm::AdjointMap adj;
+    // bumped whenever the tile shape or any prepared device buffer may change;
+    // a batch compares it against the value its work tables were built with
+    unsigned long gen = 0;
 };
 
 namespace ibm {

@@ -198,26 +198,56 @@ __device__ inline void ws_block(const WSArgs<T>& a, int b) {
 // (sum or max over slots i of p[i * nc + c]); bit ``c`` of maxmask selects max.
 __device__ inline void finalize_slots(const double* __restrict__ p, long nslots, int nc,
                                       unsigned maxmask, double scale, double* __restrict__ out) {
-    __shared__ double red[4];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int c = 0; c < nc; ++c) {
-        const bool mx = (maxmask >> c) & 1u;
-        double acc = 0.0;
-        for (long i = threadIdx.x; i < nslots; i += blockDim.x) {
-            const double x = p[i * nc + c];
-            acc = mx ? fmax(acc, x) : acc + x;
-        }
-        acc = mx ? wave_max(acc) : wave_sum(acc);
-        if (lane == 0) red[wv] = acc;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double r = red[0];
-            for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = mx ? fmax(r, red[w]) : r + red[w];
-            out[c] = mx ? r : scale * r;
-        }
-        __syncthreads();
+    // thread t takes slots t, t + B, t + 2B, ... (B = blockDim.x), four per
+    // step with their loads issued together; then a fixed-order wave and block
+    // combine: deterministic for a given block size
+    constexpr int kU = 4;
+    __shared__ double red[4][16];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const long B = blockDim.x;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    auto add = [&](int c, double x) {
+        acc[c] = ((maxmask >> c) & 1u) ? fmax(acc[c], x) : acc[c] + x;
+    };
+    long i = threadIdx.x;
+    for (; i + (kU - 1) * B < nslots; i += kU * B) {
+        double x[kU][4];
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) x[u][c] = c < nc ? p[(i + u * B) * nc + c] : 0.0;
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (c < nc) add(c, x[u][c]);
     }
+    for (; i < nslots; i += B)
+        for (int c = 0; c < nc; ++c) add(c, p[i * nc + c]);
+    for (int c = 0; c < nc; ++c) {
+        const double r = ((maxmask >> c) & 1u) ? wave_max(acc[c]) : wave_sum(acc[c]);
+        if (lane == 0) red[c][wv] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x < nc) {
+        const int c = threadIdx.x;
+        const bool mx = (maxmask >> c) & 1u;
+        double r = red[c][0];
+        for (int w = 1; w < nw; ++w) r = mx ? fmax(r, red[c][w]) : r + red[c][w];
+        out[c] = mx ? r : scale * r;
+    }
+    __syncthreads();
 }
+
+// One fixed-order reduction: nslots slots of nc doubles into out[nc].
+struct FinJob {
+    const double* p;
+    long nslots;
+    int nc;
+    unsigned maxmask;   // bit c: component c is a maximum, not a sum
+    double scale;       // applied to the sums
+    double* out;
+};
 
 // ----------------------------------------------------------------- dense pass
 template <typename T>
@@ -239,7 +269,7 @@ struct ApplyArgs {
     double* partials;        // 3 per tile
     double* drag;            // nullable
     const Seg* fsegs;        // segments holding forced nodes
-    int nfblocks;            // leading blocks that force (a multiple of 8)
+    int nfblocks;            // blocks after the tile blocks that force
     long nfsegs;
     double dv;
 };
@@ -344,7 +374,8 @@ __device__ inline void apply_tile(const ApplyArgs<T>& a, long tile, int lane) {
     const int xs = (int)(tile % a.nxs);
     const int t2 = (int)(tile / a.nxs);
     const int jt = t2 % a.njt;
-    const int kc = t2 / a.njt;
+    const int kb = (t2 / a.njt) * a.kz;
+    const int ke = min(kb + a.kz, a.nz);
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const int plane = (int)a.plane;
     const int x0 = xs * 64 * VX;
@@ -359,8 +390,6 @@ __device__ inline void apply_tile(const ApplyArgs<T>& a, long tile, int lane) {
     const bool whole_row = (x0 == 0) && (seg_end == nx);   // wave-uniform
     const int last_lane = (seg_end - x0) / VX - 1;
     const int j0 = jt * TY;
-    const int kb = kc * a.kz;
-    const int ke = min(kb + a.kz, nz);
     int roff[TY + 2];   // offset of row j0-1+r (r = 0..TY+1), periodic in y
     int frow[TY];       // forcing-flag row of tile row r (clamped for ragged tiles)
 #pragma unroll

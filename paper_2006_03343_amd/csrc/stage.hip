@@ -21,22 +21,33 @@ __global__ void __launch_bounds__(256) k_finalize(const double* __restrict__ p, 
     finalize_slots(p, nslots, nc, maxmask, scale, out);
 }
 
-// Leading blocks force the segments holding nodes with phi <= 0; the other blocks own
-// wave-tiles, taken in an XCD-aware order (the dispatcher deals blocks to the
-// 8 XCDs round-robin, so block b runs on XCD b % 8 and consecutive tiles --
-// which share halos -- are given to the same XCD's L2).
+// The first 8 * per_xcd blocks own wave-tiles, taken in an XCD-aware order
+// (the dispatcher deals blocks to the 8 XCDs round-robin, so block b runs on
+// XCD b % 8, and consecutive tiles -- which share halos -- are given to the
+// same XCD's L2).  The blocks after them force the segments holding nodes with
+// phi <= 0.  Tiles come first so that they spread evenly over an idle GPU:
+// placed behind short blocks of another role they were dispatched as those
+// retired and piled onto the CUs that freed first.
 template <typename T, typename Acc, int VX, int TY>
 __global__ void __launch_bounds__(256) k_apply(ApplyArgs<T> a) {
-    if ((int)blockIdx.x < a.nfblocks) {
-        for (long si = blockIdx.x; si < a.nfsegs; si += a.nfblocks)
-            force_seg<T>(a, a.fsegs[si], threadIdx.x, blockDim.x);
+    const int ntb = 8 * a.per_xcd;
+    if ((int)blockIdx.x >= ntb) {
+        // quarters of the forcing segments, so a short launch is not left
+        // waiting on a few blocks that each force a whole segment
+        constexpr int kPiece = kSeg / 4;
+        for (long it = blockIdx.x - ntb; it < 4 * a.nfsegs; it += a.nfblocks) {
+            const Seg sg = a.fsegs[it >> 2];
+            const int off = (int)(it & 3) * kPiece;
+            if (off < sg.len)
+                force_seg<T>(a, Seg{sg.q + off, min(kPiece, sg.len - off), 0, 0}, threadIdx.x,
+                             blockDim.x);
+        }
         return;
     }
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wpb = blockDim.x >> 6;
-    const int bid = blockIdx.x - a.nfblocks;                           // nfblocks % 8 == 0
-    const int lb = (bid & 7) * a.per_xcd + (bid >> 3);
+    const int lb = (blockIdx.x & 7) * a.per_xcd + (blockIdx.x >> 3);
     const long tile = (long)lb * wpb + wv;
     if (lb < a.nblocks && tile < a.ntiles) apply_tile<T, Acc, VX, TY>(a, tile, lane);
 }
@@ -98,7 +109,7 @@ int apply_t(ibm_ctx* c, const TileCfg& cfg, const void* const tau[6], void* cons
             hipStream_t s) {
     ApplyArgs<T> a = make_apply_args<T>(c, cfg, tau, ustar, gradp, dt, div, drag);
     if (c->ap_cap < 3 * a.ntiles) return fail(IBM_E_STATE, "apply: reduction slots not sized");
-    a.nfblocks = (int)std::min<long>((c->nfsegs + 7) / 8 * 8, 1024);
+    a.nfblocks = (int)std::min<long>((4 * c->nfsegs + 7) / 8 * 8, 2048);
     const unsigned grid = (unsigned)(a.nfblocks + 8 * a.per_xcd);
     const unsigned block = (unsigned)(64 * cfg.wpb);
     bool ok;

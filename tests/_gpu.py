@@ -20,8 +20,11 @@ def normwise(got, exp):
     return num / den
 
 
-def run_gpu(wl, dtype="f64", precision="plain", tile=None, stats=True, drag=True):
-    """One stage pass of the library; returns numpy outputs and the context."""
+def run_gpu(wl, dtype="f64", precision="plain", tile=None, stats=True, drag=True,
+            in_place=False):
+    """One stage pass of the library (ibm_wall_stress then ibm_apply;
+    ``in_place``: ustar is u, v, w themselves); returns numpy outputs and the
+    context."""
     import paper_2006_03343_amd as ibm
     torch, dev = torch_dev()
     tdt = torch.float64 if dtype == "f64" else torch.float32
@@ -35,12 +38,14 @@ def run_gpu(wl, dtype="f64", precision="plain", tile=None, stats=True, drag=True
     tau = torch.stack([T(t) for t in wl.tau]).contiguous()
     st = torch.zeros(4, dtype=torch.float64, device=dev) if stats else None
     lz = T(wl.log_z0) if wl.log_z0 is not None else None
-    u, v, w = T(wl.u), T(wl.v), T(wl.w)
-    ctx.wall_stress(u, v, w, list(tau), z0=None if lz is not None else wl.z0, log_z0=lz, stats=st)
-    ustar = torch.stack([u, v, w]).contiguous()
+    vel = torch.stack([T(wl.u), T(wl.v), T(wl.w)]).contiguous()
+    u, v, w = vel
+    ustar = vel if in_place else vel.clone()
     div = torch.empty_like(ustar)
     dr = torch.zeros(3, dtype=torch.float64, device=dev) if drag else None
     gp = [T(t) for t in wl.gradp] if wl.gradp is not None else None
+    z0 = None if lz is not None else wl.z0
+    ctx.wall_stress(u, v, w, list(tau), z0=z0, log_z0=lz, stats=st)
     ctx.apply(list(tau), list(ustar), list(div), gradp=gp, dt=wl.dt, drag=dr)
     torch.cuda.synchronize()
     out = dict(tau=tau.cpu().numpy(), div=div.cpu().numpy(), ustar=ustar.cpu().numpy(),

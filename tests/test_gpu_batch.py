@@ -146,6 +146,34 @@ def test_graph_replays_match_eager():
         del junk
 
 
+def test_tile_change_after_capture():
+    """A tile change on a case after capture makes launch refuse the stale graph;
+    run rebuilds the work tables, and a new capture replays the new shapes."""
+    import paper_2006_03343_amd as ibm
+    from paper_2006_03343_amd import _lib
+    torch, dev = torch_dev()
+    wls = _cases("f32")[:3]
+    tiles = list(TILES["f32"][:3])
+    _say("batch f32 mixed: tile change after capture")
+    b, fs = _batch(wls, tiles, torch.float32, "mixed", dev)
+    b.capture()
+    tiles[0] = (1, 1, 3, 2)       # more tiles than before: the case's slots are reallocated
+    b.case(0).set_tile(*tiles[0])
+    with pytest.raises(ibm.IbmError) as e:
+        b.launch()
+    assert e.value.code == _lib.IBM_E_STATE
+    b.run()
+    torch.cuda.synchronize()
+    for i, (w, f) in enumerate(zip(wls, fs)):
+        _same(f.snapshot(), _plain(w, tiles[i], torch.float32, "mixed", dev), f"run, case {i}")
+        f.reset()
+    b.capture()
+    b.launch()
+    torch.cuda.synchronize()
+    for i, (w, f) in enumerate(zip(wls, fs)):
+        _same(f.snapshot(), _plain(w, tiles[i], torch.float32, "mixed", dev), f"replay, case {i}")
+
+
 def test_batch_errors():
     import paper_2006_03343_amd as ibm
     from paper_2006_03343_amd import _lib

@@ -96,6 +96,19 @@ def test_per_node_log_z0(ora, dtype, prec):
     _say(f"errors {errs}")
 
 
+@pytest.mark.parametrize("dtype,prec", [("f64", "plain"), ("f32", "mixed")])
+def test_forcing_in_place(ora, dtype, prec):
+    """ustar given as the velocity fields themselves: the wall stress samples u
+    before apply forces it, so the result is the oracle's."""
+    wl = configs.fractal(64, 48, 40, rms=4.0, seed_offset=3)
+    if dtype == "f32":
+        wl = wl.cast(np.float32)
+    _say(f"fractal 64x48x40 {dtype} {prec}, ustar = u in place")
+    out, _ = run_gpu(wl, dtype, prec, in_place=True)
+    errs = compare(out, _ref(ora, wl), wl, TOL[dtype])
+    _say(f"errors {errs}")
+
+
 def _degenerate_cases():
     out = []
     # single column, single row, single plane and anisotropic spacing
