@@ -84,7 +84,7 @@ struct AdjointMap {
     int32_t* node[2] = {nullptr, nullptr};
     int32_t* off[2] = {nullptr, nullptr};
     int32_t* rec[2] = {nullptr, nullptr};   // record index in [uv records | w records]
-    int32_t* corner[2] = {nullptr, nullptr};
+    void* wgt[2] = {nullptr, nullptr};      // trilinear weight of the entry's corner (storage type)
     void* rbar = nullptr;        // per-record sample-velocity cotangents, 3 x (nuv + nw)
 };
 

@@ -15,8 +15,9 @@
 //                   cotangent dc/dlog z0 = 2 kappa^2 / ln(phi_c / z0)^3;
 //   3. gather pass: each velocity node touched by a sample stencil adds the
 //                   weighted record cotangents, reading a transposed map sorted
-//                   by node (built once per geometry) -- no atomics, so the
-//                   result is deterministic.
+//                   by node (built once per geometry, with each entry's
+//                   trilinear weight) -- no atomics, so the result is
+//                   deterministic.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -36,10 +37,10 @@ __global__ void k_vjp_dense(const T* __restrict__ g0, const T* __restrict__ g1,
                             const T* __restrict__ g2, const uint32_t* __restrict__ fmask, int nx,
                             long rows, int wrow, T* __restrict__ gu, T* __restrict__ gv,
                             T* __restrict__ gw, T* __restrict__ glz) {
-    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= rows * nx) return;
-    const long row = q / nx;
-    const int x = (int)(q - row * nx);
+    const int row = q / nx;
+    const int x = q - row * nx;
     const uint32_t fb = fmask[row * wrow + (x >> 4)] >> (2 * (x & 15));
     gu[q] = (fb & 1u) ? T(0) : g0[q];
     gv[q] = (fb & 1u) ? T(0) : g1[q];
@@ -68,13 +69,15 @@ struct BandArgs {
     T* glz;                    // nullable
 };
 
-// Cotangent of div_c at node (i, j, k), including the drag term; zero outside 0 <= k < nz.
+// Cotangent of div_c at node (ii, jj, k) (ii, jj already wrapped into the
+// periodic range), including the drag term; zero outside 0 <= k < nz.  32-bit
+// offsets: a context holds fewer than 2^31 nodes.
 template <typename T>
-__device__ inline T gbar(const BandArgs<T>& a, int c, long i, long j, long k) {
+__device__ inline T gbar(const BandArgs<T>& a, int c, int ii, int jj, int k) {
     if (k < 0 || k >= a.nz) return T(0);
-    const long ii = pmodl(i, a.nx), jj = pmodl(j, a.ny);
-    const long q = (k * a.ny + jj) * a.nx + ii;
-    const uint32_t fb = a.fmask[(k * a.ny + jj) * a.wrow + (ii >> 4)] >> (2 * (ii & 15));
+    const int row = k * a.ny + jj;
+    const int q = row * a.nx + ii;
+    const uint32_t fb = a.fmask[row * a.wrow + (ii >> 4)] >> (2 * (ii & 15));
     const bool forced = (c < 2) ? (fb & 1u) : (fb & 2u);
     T g = a.g_div[c][q];
     if (!forced) g += (T)(a.dv * a.gdrag[c]);
@@ -82,8 +85,8 @@ __device__ inline T gbar(const BandArgs<T>& a, int c, long i, long j, long k) {
 }
 
 template <typename T>
-__device__ inline T trilerp(const T* __restrict__ f, long c00, long c10, long c01, long c11,
-                            long z0, long z1, T fx, T fy, T fz) {
+__device__ inline T trilerp(const T* __restrict__ f, int c00, int c10, int c01, int c11, int z0,
+                            int z1, T fx, T fy, T fz) {
     const T gx = T(1) - fx, gy = T(1) - fy, gz = T(1) - fz;
     T a0 = f[z0 + c00] * gx + f[z0 + c10] * fx;
     T b0 = f[z0 + c01] * gx + f[z0 + c11] * fx;
@@ -97,15 +100,20 @@ __global__ void k_vjp_band(BandArgs<T> a) {
     const long r = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const RecView<T>& R = a.rec;
     if (r >= R.n) return;
-    const long q = R.q[r];
-    const long i = q % a.nx, j = (q / a.nx) % a.ny, k = q / a.plane;
+    const int q = R.q[r];
+    const int k = q / (int)a.plane;
+    const int rem = q - k * (int)a.plane;
+    const int j = rem / a.nx, i = rem - j * a.nx;
+    const int im = i == 0 ? a.nx - 1 : i - 1, ip = i + 1 == a.nx ? 0 : i + 1;
+    const int jm = j == 0 ? a.ny - 1 : j - 1, jp = j + 1 == a.ny ? 0 : j + 1;
     const T n0 = R.nx[r], n1 = R.ny[r], n2 = R.nz[r];
-    const long base = R.base[r];
-    const long c00 = base, c10 = base + R.sx[r], c01 = base + R.sy[r], c11 = c10 + R.sy[r];
+    const int base = R.base[r];
+    const int c00 = base, c10 = base + R.sx[r], c01 = base + R.sy[r], c11 = c10 + R.sy[r];
     const T fx = R.fx[r], fy = R.fy[r];
     const int ku = R.ku[r], kw = R.kw[r];
-    const long zu0 = ku * a.plane, zu1 = min(ku + 1, a.nz - 1) * a.plane;
-    const long zw0 = kw * a.plane, zw1 = min(kw + 1, a.nz - 1) * a.plane;
+    const int pl = (int)a.plane;
+    const int zu0 = ku * pl, zu1 = min(ku + 1, a.nz - 1) * pl;
+    const int zw0 = kw * pl, zw1 = min(kw + 1, a.nz - 1) * pl;
     const T us = trilerp<T>(a.u, c00, c10, c01, c11, zu0, zu1, fx, fy, R.fzu[r]);
     const T vs = trilerp<T>(a.v, c00, c10, c01, c11, zu0, zu1, fx, fy, R.fzu[r]);
     const T ws = trilerp<T>(a.w, c00, c10, c01, c11, zw0, zw1, fx, fy, R.fzw[r]);
@@ -129,14 +137,14 @@ __global__ void k_vjp_band(BandArgs<T> a) {
     T S, P0, P1, P2;
     if (a.kind == IBM_GRID_UV) {
         const T txx = (a.g_tau[0] ? a.g_tau[0][q] : T(0)) -
-                      (gbar(a, 0, i + 1, j, k) - gbar(a, 0, i - 1, j, k)) * a.cx;
+                      (gbar(a, 0, ip, j, k) - gbar(a, 0, im, j, k)) * a.cx;
         const T tyy = (a.g_tau[1] ? a.g_tau[1][q] : T(0)) -
-                      (gbar(a, 1, i, j + 1, k) - gbar(a, 1, i, j - 1, k)) * a.cy;
+                      (gbar(a, 1, i, jp, k) - gbar(a, 1, i, jm, k)) * a.cy;
         const T tzz = (a.g_tau[2] ? a.g_tau[2][q] : T(0)) +
                       (gbar(a, 2, i, j, k) - gbar(a, 2, i, j, k + 1)) * a.cz;
         const T txy = (a.g_tau[3] ? a.g_tau[3][q] : T(0)) -
-                      (gbar(a, 0, i, j + 1, k) - gbar(a, 0, i, j - 1, k)) * a.cy -
-                      (gbar(a, 1, i + 1, j, k) - gbar(a, 1, i - 1, j, k)) * a.cx;
+                      (gbar(a, 0, i, jp, k) - gbar(a, 0, i, jm, k)) * a.cy -
+                      (gbar(a, 1, ip, j, k) - gbar(a, 1, im, j, k)) * a.cx;
         S = txx * (T(2) * ur0 * n0) + tyy * (T(2) * ur1 * n1) + tzz * (T(2) * ur2 * n2) +
             txy * (ur0 * n1 + n0 * ur1);
         P0 = txx * (T(2) * n0) + txy * n1;
@@ -144,10 +152,10 @@ __global__ void k_vjp_band(BandArgs<T> a) {
         P2 = tzz * (T(2) * n2);
     } else {
         const T txz = (a.g_tau[4] ? a.g_tau[4][q] : T(0)) -
-                      (gbar(a, 2, i + 1, j, k) - gbar(a, 2, i - 1, j, k)) * a.cx +
+                      (gbar(a, 2, ip, j, k) - gbar(a, 2, im, j, k)) * a.cx +
                       (gbar(a, 0, i, j, k - 1) - gbar(a, 0, i, j, k)) * a.cz;
         const T tyz = (a.g_tau[5] ? a.g_tau[5][q] : T(0)) -
-                      (gbar(a, 2, i, j + 1, k) - gbar(a, 2, i, j - 1, k)) * a.cy +
+                      (gbar(a, 2, i, jp, k) - gbar(a, 2, i, jm, k)) * a.cy +
                       (gbar(a, 1, i, j, k - 1) - gbar(a, 1, i, j, k)) * a.cz;
         S = txz * (ur0 * n2 + n0 * ur2) + tyz * (ur1 * n2 + n1 * ur2);
         P0 = txz * n2;
@@ -176,35 +184,48 @@ __global__ void k_vjp_band(BandArgs<T> a) {
 
 template <typename T>
 struct GatherArgs {
-    RecView<T> rec[2];
-    long nuv, ntot;
-    const int32_t *node, *off, *erec, *corner;
+    long ntot;
+    const int32_t *node, *off, *erec;
+    const T* wgt;
     long m;
-    int zgrid;                 // 0: weights use fzu (u, v), 1: fzw (w)
+    int zgrid;                 // 0: u, v cotangents (uv grid), 1: w (w grid)
     const T* rbar;
     T* out0;                   // gu (zgrid 0) or gw (zgrid 1)
     T* out1;                   // gv (zgrid 0) or nullptr
 };
 
+// One thread per touched node; its entries are taken kB at a time with all
+// their loads issued before the (entry-ordered) sums.
 template <typename T>
 __global__ void k_vjp_gather(GatherArgs<T> a) {
+    constexpr int kB = 8;
     const long m = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= a.m) return;
+    const int e0 = a.off[m], e1 = a.off[m + 1];
+    const T* rb0 = a.rbar + (a.zgrid ? 2 * a.ntot : 0);
+    const T* rb1 = a.rbar + a.ntot;
     T s0 = T(0), s1 = T(0);
-    for (int e = a.off[m]; e < a.off[m + 1]; ++e) {
-        const long rr = a.erec[e];
-        const int cn = a.corner[e];
-        const bool isw = rr >= a.nuv;
-        const RecView<T>& R = a.rec[isw];
-        const long r = isw ? rr - a.nuv : rr;
-        const T fx = R.fx[r], fy = R.fy[r], fz = a.zgrid ? R.fzw[r] : R.fzu[r];
-        const T wgt = ((cn & 1) ? fx : T(1) - fx) * ((cn & 2) ? fy : T(1) - fy) *
-                      ((cn & 4) ? fz : T(1) - fz);
-        if (a.zgrid == 0) {
-            s0 += wgt * a.rbar[rr];
-            s1 += wgt * a.rbar[a.ntot + rr];
-        } else {
-            s0 += wgt * a.rbar[2 * a.ntot + rr];
+    for (int e = e0; e < e1; e += kB) {
+        int rr[kB];
+        T wg[kB], b0[kB], b1[kB];
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+            const bool in = e + u < e1;
+            rr[u] = in ? a.erec[e + u] : 0;
+            wg[u] = in ? a.wgt[e + u] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+            const bool in = e + u < e1;
+            b0[u] = in ? rb0[rr[u]] : T(0);
+            b1[u] = (in && a.zgrid == 0) ? rb1[rr[u]] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+            if (e + u < e1) {
+                s0 += wg[u] * b0[u];
+                s1 += wg[u] * b1[u];
+            }
         }
     }
     const long node = a.node[m];
@@ -221,6 +242,7 @@ int build_map(ibm_ctx* c) {
     const long plane = (long)c->g.nx * c->g.ny;
     const int nz = c->g.nz;
     std::vector<int32_t> base(ntot), sx(ntot), sy(ntot), ku(ntot), kw(ntot);
+    std::vector<T> fx(ntot), fy(ntot), fzu(ntot), fzw(ntot);
     for (int kind = 0; kind < 2; ++kind) {
         const Records& R = c->rec[kind];
         if (R.n == 0) continue;
@@ -230,6 +252,10 @@ int build_map(ibm_ctx* c) {
         IBM_HIP(hipMemcpy(sy.data() + o, R.sy, 4 * R.n, hipMemcpyDeviceToHost));
         IBM_HIP(hipMemcpy(ku.data() + o, R.ku, 4 * R.n, hipMemcpyDeviceToHost));
         IBM_HIP(hipMemcpy(kw.data() + o, R.kw, 4 * R.n, hipMemcpyDeviceToHost));
+        IBM_HIP(hipMemcpy(fx.data() + o, R.fx, sizeof(T) * R.n, hipMemcpyDeviceToHost));
+        IBM_HIP(hipMemcpy(fy.data() + o, R.fy, sizeof(T) * R.n, hipMemcpyDeviceToHost));
+        IBM_HIP(hipMemcpy(fzu.data() + o, R.fzu, sizeof(T) * R.n, hipMemcpyDeviceToHost));
+        IBM_HIP(hipMemcpy(fzw.data() + o, R.fzw, sizeof(T) * R.n, hipMemcpyDeviceToHost));
     }
     for (int zg = 0; zg < 2; ++zg) {
         std::vector<uint64_t> key((size_t)ntot * 8);
@@ -243,15 +269,21 @@ int build_map(ibm_ctx* c) {
             }
         }
         std::sort(key.begin(), key.end());
-        std::vector<int32_t> node, off, erec(key.size()), corner(key.size());
+        std::vector<int32_t> node, off, erec(key.size());
+        std::vector<T> wgt(key.size());
         for (size_t e = 0; e < key.size(); ++e) {
             const int32_t nd = (int32_t)(key[e] >> 32);
             if (node.empty() || node.back() != nd) {
                 node.push_back(nd);
                 off.push_back((int32_t)e);
             }
-            erec[e] = (int32_t)((key[e] & 0xffffffffu) >> 3);
-            corner[e] = (int32_t)(key[e] & 7u);
+            const int32_t rr = (int32_t)((key[e] & 0xffffffffu) >> 3);
+            const int cn = (int)(key[e] & 7u);
+            erec[e] = rr;
+            // the trilinear weight of this corner, in the storage type
+            const T wz = zg ? fzw[rr] : fzu[rr];
+            wgt[e] = ((cn & 1) ? fx[rr] : T(1) - fx[rr]) * ((cn & 2) ? fy[rr] : T(1) - fy[rr]) *
+                     ((cn & 4) ? wz : T(1) - wz);
         }
         off.push_back((int32_t)key.size());
         A.m[zg] = (long)node.size();
@@ -260,12 +292,12 @@ int build_map(ibm_ctx* c) {
         IBM_HIP(hipMalloc(&A.node[zg], 4 * nb));
         IBM_HIP(hipMalloc(&A.off[zg], 4 * (nb + 1)));
         IBM_HIP(hipMalloc(&A.rec[zg], 4 * eb));
-        IBM_HIP(hipMalloc(&A.corner[zg], 4 * eb));
+        IBM_HIP(hipMalloc(&A.wgt[zg], sizeof(T) * eb));
         if (!node.empty()) {
             IBM_HIP(hipMemcpy(A.node[zg], node.data(), 4 * node.size(), hipMemcpyHostToDevice));
             IBM_HIP(hipMemcpy(A.off[zg], off.data(), 4 * off.size(), hipMemcpyHostToDevice));
             IBM_HIP(hipMemcpy(A.rec[zg], erec.data(), 4 * erec.size(), hipMemcpyHostToDevice));
-            IBM_HIP(hipMemcpy(A.corner[zg], corner.data(), 4 * corner.size(), hipMemcpyHostToDevice));
+            IBM_HIP(hipMemcpy(A.wgt[zg], wgt.data(), sizeof(T) * wgt.size(), hipMemcpyHostToDevice));
         }
     }
     IBM_HIP(hipMalloc(&A.rbar, sizeof(T) * 3 * (size_t)std::max<long>(ntot, 1)));
@@ -329,16 +361,13 @@ int vjp_t(ibm_ctx* c, const T* u, const T* v, const T* w, double z0, const T* lo
             hipLaunchKernelGGL((k_vjp_band<T, false>), dim3(nblk(a.rec.n, 256)), dim3(256), 0, s, a);
     }
     GatherArgs<T> ga;
-    ga.rec[0] = view<T>(c->rec[0]);
-    ga.rec[1] = view<T>(c->rec[1]);
-    ga.nuv = nuv;
     ga.ntot = ntot;
     ga.rbar = (const T*)c->adj.rbar;
     for (int zg = 0; zg < 2; ++zg) {
         ga.node = c->adj.node[zg];
         ga.off = c->adj.off[zg];
         ga.erec = c->adj.rec[zg];
-        ga.corner = c->adj.corner[zg];
+        ga.wgt = (const T*)c->adj.wgt[zg];
         ga.m = c->adj.m[zg];
         ga.zgrid = zg;
         ga.out0 = zg ? gw : gu;
@@ -358,7 +387,7 @@ void free_adjoint(ibm_ctx* c) {
         (void)hipFree(A.node[zg]);
         (void)hipFree(A.off[zg]);
         (void)hipFree(A.rec[zg]);
-        (void)hipFree(A.corner[zg]);
+        (void)hipFree(A.wgt[zg]);
     }
     (void)hipFree(A.rbar);
     A = AdjointMap();
