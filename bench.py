@@ -18,7 +18,12 @@ Gaussian-bump terrains advanced by one hipGraph launch of the batched kernels
 (float32, mixed) with the same cases advanced by plain per-case float64 calls.
 ``adjoint`` times the forward pass and the hand-written reverse mode on the
 256 x 128 x 128 fractal terrain with a per-node log z0 field (float32 mixed).
-The dense-pass tile shape comes from the autotuner (cached under /tmp).
+``terrains`` reports the same figures for the wall-mounted cube (64 x 32 x 32,
+float64; cache-resident, so no roofline claim) and the 2-D ridge
+(256 x 128 x 128, 100 passes in float64, float32 and float32 mixed; its
+float32 working set fits the 256 MB Infinity Cache, so its fraction is
+flagged).  Dense-pass tile shapes come from the autotuner's cache shipped with
+the package (``--retune`` times them again and rewrites it).
 """
 import argparse
 import json
@@ -30,7 +35,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
-TUNE_CACHE = os.environ.get("IBM_TUNE_CACHE", "/tmp/ibm_tune_cache.json")
+TUNE_CACHE = os.environ.get("IBM_TUNE_CACHE",
+                            os.path.join(ROOT, "paper_2006_03343_amd", "tune_gfx950.json"))
 PROFILE = os.path.join(ROOT, "profiles", "k_apply_hill512x256x256_f32_mixed.txt")
 
 
@@ -105,23 +111,30 @@ def run_gpu(wl, dtype, precision, steps, warmup, tile=None):
 
     for _ in range(warmup):
         step()
-    torch.cuda.synchronize()
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    # the timed region: ``steps`` back-to-back steps between two events
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t_wall = time.perf_counter()
     start.record()
+    for _ in range(steps):
+        step()
+    end.record()
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    total_ms = start.elapsed_time(end)
+    # per-kernel durations: the same steps again with an event around every
+    # launch, on the launch stream (the events themselves add a little to the
+    # step, so this loop is not the one ``value`` comes from)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    torch.cuda.synchronize()
     for e in ev:
         e[0].record()
         ctx.wall_stress(u, v, w, taus, z0=wl.z0, stats=stats)
         e[1].record()
         ctx.apply(taus, uss, divs, gradp=gp, dt=wl.dt, drag=drag)
         e[2].record()
-    end.record()
     torch.cuda.synchronize()
-    t_wall = time.perf_counter() - t_wall
-    total_ms = start.elapsed_time(end)
     ws_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / steps
     ap_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / steps
     mask = ctx.mask()
@@ -263,6 +276,33 @@ def run_adjoint(steps, warmup):
             "note": "forward = out-of-place stage pass incl. tensor copies; backward = ibm_stage_vjp"}
 
 
+def run_terrains(steps, warmup):
+    """Stage throughput on the cube (float64) and the ridge (float64, float32,
+    float32 mixed)."""
+    import numpy as np
+
+    from workloads import configs
+    res = {}
+    cube = configs.cube()
+    ridge64 = configs.ridge()
+    ridge32 = ridge64.cast(np.float32)
+    for name, wl, dtype, prec, claim in (
+            ("cube 64x32x32 f64 plain", cube, "f64", "plain", "none: cache-resident"),
+            ("ridge 256x128x128 f64 plain", ridge64, "f64", "plain", "flagged: fits the MALL"),
+            ("ridge 256x128x128 f32 plain", ridge32, "f32", "plain", "flagged: fits the MALL"),
+            ("ridge 256x128x128 f32 mixed", ridge32, "f32", "mixed", "flagged: fits the MALL")):
+        r = run_gpu(wl, dtype, prec, steps, warmup)
+        s = 8 if dtype == "f64" else 4
+        gbs = apply_bytes(wl, r["mask"], s) / (r["apply_ms"] * 1e-3) / 1e9
+        res[name] = {"value": wl.grid.n / (r["ms_per_step"] * 1e-3), "unit": "grid-points/s",
+                     "ms_per_step": r["ms_per_step"], "apply_ms": r["apply_ms"],
+                     "wall_stress_ms": r["wall_stress_ms"], "apply_GBs": gbs,
+                     "apply_frac": gbs / HBM_PEAK_GBS, "roofline_claim": claim,
+                     "tile": list(r["tile"])}
+        log(f"{name}: {res[name]['value']:.3e} points/s, apply {gbs:.0f} GB/s")
+    return res
+
+
 def cpu_baseline(wl, budget_s=12.0, max_passes=4):
     """The FP64 oracle timed on full passes of the same workload (per-step work:
     wall stress, divergence, forcing, drag)."""
@@ -294,20 +334,25 @@ def main():
     ap.add_argument("--no-f64", action="store_true", help="skip the float64 comparison run")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-case ensemble")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
+    ap.add_argument("--no-terrains", action="store_true", help="skip the cube and ridge runs")
+    ap.add_argument("--retune", action="store_true",
+                    help="time the tile shapes again and rewrite the autotuner's cache")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 384 MiB device-to-device copy three times, the "
                          "reference that scales FETCH_SIZE / WRITE_SIZE counters")
     ap.add_argument("--tile", type=str, default=None, help="vx,ty,kz,wpb for ibm_apply")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the stage has no multi-GPU path in this build "
-              "(see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the stage has no multi-GPU path, so the figure "
+              "is one GPU's throughput; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
     import torch
     from workloads import configs
 
+    if args.retune and os.path.exists(TUNE_CACHE):
+        os.remove(TUNE_CACHE)
     t0 = time.time()
     wl64 = configs.hill()
     wl = wl64.cast(np.float32)
@@ -360,6 +405,8 @@ def main():
     if not args.no_adjoint:
         out["adjoint"] = run_adjoint(max(5, args.steps // 4), args.warmup)
         log(f"adjoint: {out['adjoint']}")
+    if not args.no_terrains:
+        out["terrains"] = run_terrains(args.steps, args.warmup)
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(wl)

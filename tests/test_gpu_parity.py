@@ -96,6 +96,47 @@ def test_per_node_log_z0(ora, dtype, prec):
     _say(f"errors {errs}")
 
 
+def test_ridge_full_size_repeated_passes(ora):
+    """The 256 x 128 x 128 ridge, 100 passes in place (stress, forced velocity)
+    in float64, float32 and float32 mixed: a pass is idempotent, so pass 100
+    equals pass 1 bit for bit, and each is held to the oracle."""
+    import torch
+    import paper_2006_03343_amd as ibm
+    _, dev = torch_dev()
+    wl64 = configs.ridge()
+    wl32 = wl64.cast(np.float32)
+    refs = {"f64": _ref(ora, wl64), "f32": _ref(ora, wl32)}    # on the values each run sees
+    for dtype, prec in (("f64", "plain"), ("f32", "plain"), ("f32", "mixed")):
+        wl = wl64 if dtype == "f64" else wl32
+        ref = refs[dtype]
+        tdt = torch.float64 if dtype == "f64" else torch.float32
+        g = wl.grid
+        T = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev, tdt)
+        ctx = ibm.Context(g.nx, g.ny, g.nz, dtype=tdt, precision=prec, device=dev)
+        ctx.prepare(T(wl.phi_uv), T(wl.phi_w), wl.band_width, wl.phi_c, wl.kappa)
+        tau = torch.stack([T(t) for t in wl.tau]).contiguous()
+        vel = torch.stack([T(wl.u), T(wl.v), T(wl.w)]).contiguous()
+        ustar = vel.clone()
+        div = torch.empty_like(vel)
+        gp = [T(t) for t in wl.gradp]
+        st = torch.zeros(4, dtype=torch.float64, device=dev)
+        dr = torch.zeros(3, dtype=torch.float64, device=dev)
+        snaps = []
+        for p in range(100):
+            ctx.wall_stress(vel[0], vel[1], vel[2], list(tau), z0=wl.z0, stats=st)
+            ctx.apply(list(tau), list(ustar), list(div), gradp=gp, dt=wl.dt, drag=dr)
+            if p in (0, 99):
+                torch.cuda.synchronize()
+                snaps.append(dict(tau=tau.cpu().numpy(), div=div.cpu().numpy(),
+                                  ustar=ustar.cpu().numpy(), stats=st.cpu().numpy(),
+                                  drag=dr.cpu().numpy(), mask=ctx.mask(), counts=ctx.counts()))
+        for k in ("tau", "div", "ustar", "stats", "drag"):
+            assert np.array_equal(snaps[0][k], snaps[1][k]), (dtype, prec, k)
+        errs = compare(snaps[1], ref, wl, TOL[dtype])
+        _say(f"ridge 256x128x128 {dtype} {prec}, 100 passes: errors "
+             + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()))
+
+
 @pytest.mark.parametrize("dtype,prec", [("f64", "plain"), ("f32", "mixed")])
 def test_forcing_in_place(ora, dtype, prec):
     """ustar given as the velocity fields themselves: the wall stress samples u
