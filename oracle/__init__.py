@@ -8,7 +8,8 @@ is compared against the oracle fed with exactly the stored FP32 values.
 Every function follows §3 of Liu & Stevens (arXiv 2006.03343):
 classes (§3.3 lists), normals (§3.1), the wall model (§3.3,
 eq. bc-bottom-immersed and the tensor rotation), the stress divergence
-(§2.4, eqs. dudx/dudz/dwdz) and the direct forcing (§3.2, eq. u-*-IBM).
+(§2.4, eqs. dudx/dudz/dwdz) and the direct forcing (§3.2, eq. u-*-IBM);
+and the Smagorinsky stress with Mason's damping that feeds it (§2.2).
 """
 import ctypes
 import os
@@ -58,6 +59,8 @@ def lib():
         L.ora_counts.argtypes = [vp, vp, vp, vp, vp]
         L.ora_stage_vjp.argtypes = [vp, vp, vp, vp, vp, vp, vp, c_double, vp, vp, vp, vp, vp,
                                     vp, vp, vp, vp]
+        L.ora_smagorinsky.argtypes = [vp, c_double, c_double, vp, vp, vp, vp, vp, c_double, vp,
+                                      vp]
         L.ora_num_threads.restype = c_int
         _lib = L
     return _lib
@@ -169,6 +172,19 @@ def divergence(g, tau):
     gr = _grid(g)
     lib().ora_divergence(ctypes.byref(gr), _parr(t), _parr(div))
     return div
+
+
+def smagorinsky(g, phi_uv, phi_w, u, v, w, z0=None, log_z0=None, cs=0.16, kappa=0.4):
+    """§2.2 Smagorinsky stress with Mason damping (wall distance phi): six fields."""
+    pu, pw = _f64(phi_uv, g), _f64(phi_w, g)
+    vel = [_f64(a, g) for a in (u, v, w)]
+    lz = None if log_z0 is None else _f64(log_z0, g)
+    tau = [np.empty(g.shape) for _ in range(6)]
+    gr = _grid(g)
+    lib().ora_smagorinsky(ctypes.byref(gr), float(cs), float(kappa), _p(pu), _p(pw),
+                          _p(vel[0]), _p(vel[1]), _p(vel[2]), float(z0 or 0.0),
+                          None if lz is None else _p(lz), _parr(tau))
+    return tau
 
 
 def divergence_transpose(g, gdiv):

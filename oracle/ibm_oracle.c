@@ -455,3 +455,79 @@ void ora_stage_vjp(const ora_grid* g, const ora_params* p, const double* phi_uv,
     for (int c = 0; c < 3; ++c) free(gd[c]);
     for (int c = 0; c < 6; ++c) free(gt[c]);
 }
+
+/* ----------------------------------------------- §2.2 Smagorinsky SGS stress */
+static double ddx(const ora_grid* g, const double* f, long i, long j, long k) {
+    return (at_padded(g, f, i + 1, j, k) - at_padded(g, f, i - 1, j, k)) / (2.0 * g->dx);
+}
+
+static double ddy(const ora_grid* g, const double* f, long i, long j, long k) {
+    return (at_padded(g, f, i, j + 1, k) - at_padded(g, f, i, j - 1, k)) / (2.0 * g->dy);
+}
+
+/* S11, S22, S33, S12 on the uv node (i,j,k); zero outside 0 <= k < nz */
+static void strain_uv(const ora_grid* g, const double* u, const double* v, const double* w,
+                      long i, long j, long k, double s[4]) {
+    if (k < 0 || k >= g->nz) {
+        s[0] = s[1] = s[2] = s[3] = 0.0;
+        return;
+    }
+    s[0] = ddx(g, u, i, j, k);
+    s[1] = ddy(g, v, i, j, k);
+    /* eq. dwdz: dw/dz of the w nodes k and k+1, on the uv node k between them */
+    s[2] = (at_padded(g, w, i, j, k + 1) - at_padded(g, w, i, j, k)) / g->dz;
+    s[3] = 0.5 * (ddy(g, u, i, j, k) + ddx(g, v, i, j, k));
+}
+
+/* S13, S23 on the w node (i,j,k); zero outside 0 <= k < nz */
+static void strain_w(const ora_grid* g, const double* u, const double* v, const double* w,
+                     long i, long j, long k, double s[2]) {
+    if (k < 0 || k >= g->nz) {
+        s[0] = s[1] = 0.0;
+        return;
+    }
+    /* eq. dudz: du/dz of the uv nodes k-1 and k, on the w node k between them */
+    const double dudz = (at_padded(g, u, i, j, k) - at_padded(g, u, i, j, k - 1)) / g->dz;
+    const double dvdz = (at_padded(g, v, i, j, k) - at_padded(g, v, i, j, k - 1)) / g->dz;
+    s[0] = 0.5 * (dudz + ddx(g, w, i, j, k));
+    s[1] = 0.5 * (dvdz + ddy(g, w, i, j, k));
+}
+
+/* lambda^2 of eq. smag-1 with n = 2 at wall distance d */
+static double mixing_length_sq(const ora_grid* g, double cs, double kappa, double d, double z0) {
+    const double lambda0 = cs * cbrt(g->dx * g->dy * g->dz);
+    if (!(d + z0 > 0.0)) return 0.0;
+    const double wall = kappa * (d + z0);
+    return 1.0 / (1.0 / (lambda0 * lambda0) + 1.0 / (wall * wall));
+}
+
+void ora_smagorinsky(const ora_grid* g, double cs, double kappa, const double* phi_uv,
+                     const double* phi_w, const double* u, const double* v, const double* w,
+                     double z0, const double* log_z0, double* const tau[6]) {
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < g->nz; ++k)
+        for (long j = 0; j < g->ny; ++j)
+            for (long i = 0; i < g->nx; ++i) {
+                const long q = lin(g, i, j, k);
+                const double zq = log_z0 ? exp(log_z0[q]) : z0;
+                double a[4], below[4], wk[2], wk1[2];
+                strain_uv(g, u, v, w, i, j, k, a);
+                strain_uv(g, u, v, w, i, j, k - 1, below);
+                strain_w(g, u, v, w, i, j, k, wk);
+                strain_w(g, u, v, w, i, j, k + 1, wk1);
+                /* uv node k: S13, S23 from the w nodes k and k+1 */
+                const double s13 = 0.5 * (wk[0] + wk1[0]), s23 = 0.5 * (wk[1] + wk1[1]);
+                const double ss_uv = a[0] * a[0] + a[1] * a[1] + a[2] * a[2] +
+                                     2.0 * (a[3] * a[3] + s13 * s13 + s23 * s23);
+                const double nu_uv = mixing_length_sq(g, cs, kappa, phi_uv[q], zq) * sqrt(2.0 * ss_uv);
+                for (int c = 0; c < 4; ++c) tau[c][q] = -2.0 * nu_uv * a[c];
+                /* w node k: S11, S22, S33, S12 from the uv nodes k-1 and k */
+                double m[4];
+                for (int c = 0; c < 4; ++c) m[c] = 0.5 * (below[c] + a[c]);
+                const double ss_w = m[0] * m[0] + m[1] * m[1] + m[2] * m[2] +
+                                    2.0 * (m[3] * m[3] + wk[0] * wk[0] + wk[1] * wk[1]);
+                const double nu_w = mixing_length_sq(g, cs, kappa, phi_w[q], zq) * sqrt(2.0 * ss_w);
+                tau[4][q] = -2.0 * nu_w * wk[0];
+                tau[5][q] = -2.0 * nu_w * wk[1];
+            }
+}

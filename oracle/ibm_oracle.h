@@ -109,6 +109,24 @@ void ora_stage_vjp(const ora_grid* g, const ora_params* p, const double* phi_uv,
                    const double* const g_div[3], const double* const g_ustar[3],
                    const double g_drag[3], double* gu, double* gv, double* gw, double* glog_z0);
 
+/* §2.2 Smagorinsky sub-grid stress with Mason's wall damping, the wall
+ * distance being phi (the node's own grid):
+ *   S = (grad u + grad u^T) / 2 (eq. t-ij-1963) with the §2.4 differences:
+ *       central in x and y (periodic), eq. dwdz for dw/dz on the uv node,
+ *       eq. dudz for du/dz and dv/dz on the w node; velocity taken as 0
+ *       outside 0 <= k < nz;
+ *   S11, S22, S33, S12 live on uv nodes, S13, S23 on w nodes; |S| =
+ *       sqrt(2 S:S) (eq. nu-t) on each node set, with the components of the
+ *       other set averaged from its two nodes above and below;
+ *   lambda_0 = cs (dx dy dz)^(1/3) (eq. smag), 1/lambda^2 = 1/lambda_0^2 +
+ *       1/[kappa (phi + z0)]^2 (eq. smag-1, n = 2), lambda = 0 where
+ *       phi + z0 <= 0; z0 is the scalar or exp(log_z0[q]);
+ *   nu_t = lambda^2 |S|, tau = -2 nu_t S (eqs. nu-t, t-ij-1963).
+ * Writes all six stress components. */
+void ora_smagorinsky(const ora_grid* g, double cs, double kappa, const double* phi_uv,
+                     const double* phi_w, const double* u, const double* v, const double* w,
+                     double z0, const double* log_z0, double* const tau[6]);
+
 int ora_num_threads(void);
 
 #ifdef __cplusplus
