@@ -18,6 +18,10 @@ Gaussian-bump terrains advanced by one hipGraph launch of the batched kernels
 (float32, mixed) with the same cases advanced by plain per-case float64 calls.
 ``adjoint`` times the forward pass and the hand-written reverse mode on the
 256 x 128 x 128 fractal terrain with a per-node log z0 field (float32 mixed).
+``sgs`` times the Smagorinsky stress with Mason's wall damping that feeds
+the stage (ibm_sgs_stress, float32 on the same hill: its roofline against
+44 algorithmic bytes per node) and the three calls in a row (SGS stress, wall
+stress, dense pass).
 ``terrains`` reports the same figures for the wall-mounted cube (64 x 32 x 32,
 float64; cache-resident, so no roofline claim) and the 2-D ridge
 (256 x 128 x 128, 100 passes in float64, float32 and float32 mixed; its
@@ -279,6 +283,60 @@ def run_adjoint(steps, warmup):
             "note": "forward = out-of-place stage pass incl. tensor copies; backward = ibm_stage_vjp"}
 
 
+def run_sgs(wl, steps, warmup):
+    """ibm_sgs_stress on the hill (float32), alone and followed by the stage."""
+    import numpy as np
+    import torch
+
+    import paper_2006_03343_amd as ibm
+    dev = torch.device("cuda", 0)
+    g = wl.grid
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev, torch.float32)
+    ctx = ibm.Context(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, dtype=torch.float32,
+                      precision="mixed", device=dev)
+    ctx.prepare(T(wl.phi_uv), T(wl.phi_w), wl.band_width, wl.phi_c, wl.kappa)
+    ctx.autotune(TUNE_CACHE)
+    pu, pw, u, v, w = (T(x) for x in (wl.phi_uv, wl.phi_w, wl.u, wl.v, wl.w))
+    tau = torch.empty((6,) + g.shape, dtype=torch.float32, device=dev)
+    taus = list(tau)
+    gp = [T(t) for t in wl.gradp]
+    ustar = torch.stack([u, v, w]).contiguous()
+    div = torch.empty_like(ustar)
+    stats = torch.zeros(4, dtype=torch.float64, device=dev)
+    drag = torch.zeros(3, dtype=torch.float64, device=dev)
+    sgs = lambda: ctx.sgs_stress(pu, pw, u, v, w, taus, z0=wl.z0, kappa=wl.kappa)
+
+    def step():
+        sgs()
+        ctx.wall_stress(u, v, w, taus, z0=wl.z0, stats=stats)
+        ctx.apply(taus, list(ustar), list(div), gradp=gp, dt=wl.dt, drag=drag)
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        e0, e1 = _events(2)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    ms_sgs = timed(sgs)
+    ms_all = timed(step)
+    gbs = g.n * 11 * 4 / (ms_sgs * 1e-3) / 1e9
+    del ctx, tau, ustar, div
+    torch.cuda.empty_cache()
+    return {"workload": f"hill {g.nx}x{g.ny}x{g.nz}, float32, cs 0.16, kappa {wl.kappa}",
+            "sgs_ms": ms_sgs, "sgs_points_per_s": g.n / (ms_sgs * 1e-3),
+            "sgs_roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                             "bytes_per_launch": g.n * 11 * 4},
+            "sgs_wall_stress_apply_ms": ms_all,
+            "sgs_wall_stress_apply_points_per_s": g.n / (ms_all * 1e-3)}
+
+
 def run_terrains(steps, warmup):
     """Stage throughput on the cube (float64) and the ridge (float64, float32,
     float32 mixed)."""
@@ -338,6 +396,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-case ensemble")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--no-terrains", action="store_true", help="skip the cube and ridge runs")
+    ap.add_argument("--no-sgs", action="store_true", help="skip the Smagorinsky stress runs")
     ap.add_argument("--retune", action="store_true",
                     help="time the tile shapes again and rewrite the autotuner's cache")
     ap.add_argument("--calib-copy", action="store_true",
@@ -408,6 +467,10 @@ def main():
     if not args.no_adjoint:
         out["adjoint"] = run_adjoint(max(5, args.steps // 4), args.warmup)
         log(f"adjoint: {out['adjoint']}")
+    if not args.no_sgs:
+        out["sgs"] = run_sgs(wl, args.steps, args.warmup)
+        log(f"sgs: {out['sgs']['sgs_ms']:.4f} ms ({out['sgs']['sgs_roofline']['frac'] * 100:.1f} % "
+            f"of HBM peak); sgs + stage {out['sgs']['sgs_wall_stress_apply_ms']:.4f} ms")
     if not args.no_terrains:
         out["terrains"] = run_terrains(args.steps, args.warmup)
     if not args.no_cpu:

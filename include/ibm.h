@@ -119,6 +119,24 @@ int ibm_apply(ibm_ctx* c, const void* const tau[6], void* const ustar[3],
               const void* const gradp[3], double dt, void* const div[3], double* drag_dev,
               void* stream);
 
+/* Smagorinsky sub-grid stress with Mason's wall damping (§2.2, eqs.
+ * t-ij-1963, nu-t, smag, smag-1): the stress field that ibm_wall_stress then
+ * overwrites at band and solid nodes.  The wall distance in the damping is
+ * phi of each node's own grid (phi_uv for the four uv components, phi_w for
+ * xz, yz).  Strain S = (grad u + grad u^T) / 2 with central differences in x
+ * and y (periodic) and the staggered vertical differences of §2.4 (velocity
+ * outside 0 <= k < nz taken as 0); |S| = sqrt(2 S:S) with the components of
+ * the other node set averaged from its two neighbouring planes; 1/lambda^2 =
+ * 1/(cs (dx dy dz)^(1/3))^2 + 1/(kappa (phi + z0))^2, lambda = 0 where
+ * phi + z0 <= 0; tau = -2 lambda^2 |S| S, all six components written.
+ * z0: scalar (> 0), used when log_z0 == NULL; log_z0: per-node ln z0 field
+ * or NULL.  Needs a context, not a prepare.  tau may alias no input.
+ * Asynchronous on ``stream``.  Errors: IBM_E_ARG (NULL or aliased fields),
+ * IBM_E_RANGE (z0, cs or kappa not finite and > 0). */
+int ibm_sgs_stress(ibm_ctx* c, const void* phi_uv, const void* phi_w, const void* u,
+                   const void* v, const void* w, double z0, const void* log_z0, double cs,
+                   double kappa, void* const tau[6], void* stream);
+
 /* Reverse mode of one stage pass with respect to u, v, w and log z0, for a
  * single velocity state that is both sampled by the wall model and forced
  * (ustar == u).  Cotangents: g_tau[6] (array or entries may be NULL = 0) of

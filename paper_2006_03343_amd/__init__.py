@@ -184,6 +184,20 @@ class Context:
             check(self._lib.ibm_apply(self._h, ptr_array(taus), ptr_array(us), gp, float(dt),
                                       ptr_array(dv), dp, self._stream()))
 
+    def sgs_stress(self, phi_uv, phi_w, u, v, w, tau, z0=None, log_z0=None, cs=0.16, kappa=0.4):
+        """Smagorinsky stress with Mason's wall damping written into ``tau``
+        (6 fields); the wall distance is phi of each node's grid."""
+        if (z0 is None) == (log_z0 is None):
+            raise ValueError("give exactly one of z0 and log_z0")
+        taus = self._fields(tau, "tau", 6)
+        with torch.cuda.device(self.device):
+            check(self._lib.ibm_sgs_stress(self._h, self._field(phi_uv, "phi_uv"),
+                                           self._field(phi_w, "phi_w"), self._field(u, "u"),
+                                           self._field(v, "v"), self._field(w, "w"),
+                                           float(z0 or 0.0), self._field(log_z0, "log_z0"),
+                                           float(cs), float(kappa), ptr_array(taus),
+                                           self._stream()))
+
     def vjp(self, u, v, w, g_div, g_ustar, g_drag, z0=None, log_z0=None, g_tau=None):
         """Reverse mode of one pass (ustar == u): returns (gu, gv, gw, glog_z0 or None)."""
         if (z0 is None) == (log_z0 is None):

@@ -231,6 +231,43 @@ int ibm_apply(ibm_ctx* c, const void* const tau[6], void* const ustar[3],
     return launch_apply(c, cfg, tau, ustar, gradp, dt, div, drag_dev, (hipStream_t)stream);
 }
 
+int ibm_sgs_stress(ibm_ctx* c, const void* phi_uv, const void* phi_w, const void* u,
+                   const void* v, const void* w, double z0, const void* log_z0, double cs,
+                   double kappa, void* const tau[6], void* stream) {
+    g_err[0] = 0;
+    const char* fn = "ibm_sgs_stress";
+    int rc = check_ctx(c, false, fn);
+    if (rc) return rc;
+    if ((rc = check_field(c, phi_uv, fn, "phi_uv")) || (rc = check_field(c, phi_w, fn, "phi_w")) ||
+        (rc = check_field(c, u, fn, "u")) || (rc = check_field(c, v, fn, "v")) ||
+        (rc = check_field(c, w, fn, "w")))
+        return rc;
+    if (!tau) return fail(IBM_E_ARG, "%s: tau is NULL", fn);
+    for (int i = 0; i < 6; ++i) {
+        if ((rc = check_field(c, tau[i], fn, "tau[i]"))) return rc;
+        if (tau[i] == u || tau[i] == v || tau[i] == w || tau[i] == phi_uv || tau[i] == phi_w ||
+            (log_z0 && tau[i] == log_z0))
+            return fail(IBM_E_ARG, "%s: tau may not alias an input", fn);
+    }
+    if (log_z0) {
+        if ((rc = check_field(c, log_z0, fn, "log_z0"))) return rc;
+    } else if (!finite_pos(z0)) {
+        return fail(IBM_E_RANGE, "%s: z0 must be finite and > 0 (got %g)", fn, z0);
+    }
+    if (!finite_pos(cs) || !finite_pos(kappa))
+        return fail(IBM_E_RANGE, "%s: cs and kappa must be finite and > 0", fn);
+    TileCfg cfg = c->cfg;
+    cfg.ty = 1;
+    bool vec = cfg.vx > 1;
+    const void* vecs[6] = {phi_uv, phi_w, u, v, w, log_z0};
+    for (const void* p : vecs) vec = vec && (!p || (uintptr_t)p % 16 == 0);
+    for (int i = 0; i < 6; ++i) vec = vec && (uintptr_t)tau[i] % 16 == 0;
+    if (!vec) cfg.vx = 1;   // a misaligned view: one element per lane
+    DeviceScope dg(c->device);
+    return launch_sgs(c, cfg, phi_uv, phi_w, u, v, w, z0, log_z0, cs, kappa, tau,
+                      (hipStream_t)stream);
+}
+
 int ibm_set_tile(ibm_ctx* c, int vx, int ty, int kz, int wpb) {
     g_err[0] = 0;
     int rc = check_ctx(c, false, "ibm_set_tile");

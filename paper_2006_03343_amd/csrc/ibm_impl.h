@@ -143,6 +143,11 @@ long band_blocks(const ibm_ctx* c);
 // outside launches; waits for the device before freeing a smaller buffer.
 int size_partials(ibm_ctx* c);
 
+// sgs.hip
+int launch_sgs(ibm_ctx* c, const TileCfg& cfg, const void* phi_uv, const void* phi_w,
+               const void* u, const void* v, const void* w, double z0, const void* log_z0,
+               double cs, double kappa, void* const tau[6], hipStream_t s);
+
 // batch.hip
 int autotune(ibm_ctx* c, const char* cache_path, int flags, hipStream_t s);
 
