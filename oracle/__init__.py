@@ -229,6 +229,57 @@ def stage(wl, ustar=None):
     return dict(mask=mask, counts=cnt, tau=tau, stats=stats, div=div, ustar=us, drag=dr)
 
 
+# ------------------------------------------- §2.4 pseudo-spectral horizontal
+def spectral_derivative(f, axis, length):
+    """eq. dudx: the derivative along a periodic axis of physical ``length``
+    as the sum over wavenumbers of i k A_hat exp(i k x) (library FFT as the
+    transform step).  For an even node count the Nyquist mode has no
+    derivative (its i k A_hat term would not be real) and is dropped."""
+    f = np.asarray(f, dtype=np.float64)
+    n = f.shape[axis]
+    m = np.fft.fftfreq(n, d=1.0 / n)            # mode numbers 0, 1, .., -1
+    k = 2.0 * np.pi * m / length
+    if n % 2 == 0:
+        k[n // 2] = 0.0
+    shape = [1] * f.ndim
+    shape[axis] = n
+    return np.real(np.fft.ifft(1j * k.reshape(shape) * np.fft.fft(f, axis=axis), axis=axis))
+
+
+def divergence_spectral(g, tau):
+    """The stress divergence of ``divergence`` with the horizontal derivatives
+    taken pseudo-spectrally (eq. dudx) instead of by central differences; the
+    vertical staggered differences (eqs. dudz, dwdz) and the zero padding at
+    the ends are the same."""
+    txx, tyy, tzz, txy, txz, tyz = (_f64(a, g) for a in tau)
+    ddx = lambda a: spectral_derivative(a, 2, g.nx * g.dx)
+    ddy = lambda a: spectral_derivative(a, 1, g.ny * g.dy)
+
+    def above(a):                 # a[k + 1], zero above the top plane
+        out = np.zeros_like(a)
+        out[:-1] = a[1:]
+        return out
+
+    def below(a):                 # a[k - 1], zero below the bottom plane
+        out = np.zeros_like(a)
+        out[1:] = a[:-1]
+        return out
+
+    div_x = ddx(txx) + ddy(txy) + (above(txz) - txz) / g.dz
+    div_y = ddx(txy) + ddy(tyy) + (above(tyz) - tyz) / g.dz
+    div_z = ddx(txz) + ddy(tyz) + (tzz - below(tzz)) / g.dz
+    return [div_x, div_y, div_z]
+
+
+def stage_spectral(wl, ustar=None):
+    """``stage`` with the pseudo-spectral horizontal derivatives."""
+    out = stage(wl, ustar)
+    g = wl.grid
+    out["div"] = divergence_spectral(g, out["tau"])
+    out["drag"] = drag(g, wl.phi_uv, wl.phi_w, out["div"])
+    return out
+
+
 def stage_vjp(wl, g_tau, g_div, g_ustar, g_drag):
     """Reverse mode of one pass with ustar = u (see ``ora_stage_vjp``)."""
     g = wl.grid
