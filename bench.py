@@ -22,6 +22,9 @@ Gaussian-bump terrains advanced by one hipGraph launch of the batched kernels
 the stage (ibm_sgs_stress, float32 on the same hill: its roofline against
 44 algorithmic bytes per node) and the three calls in a row (SGS stress, wall
 stress, dense pass).
+``spectral`` times ibm_apply_spectral, the dense pass with the paper's
+pseudo-spectral horizontal derivatives, on the same hill (three launches:
+x transforms, y transforms, vertical differences with forcing and drag).
 ``terrains`` reports the same figures for the wall-mounted cube (64 x 32 x 32,
 float64; cache-resident, so no roofline claim) and the 2-D ridge
 (256 x 128 x 128, 100 passes in float64, float32 and float32 mixed; its
@@ -337,6 +340,48 @@ def run_sgs(wl, steps, warmup):
             "sgs_wall_stress_apply_points_per_s": g.n / (ms_all * 1e-3)}
 
 
+def run_spectral(wl, steps, warmup):
+    """ibm_apply_spectral on the hill (float32, mixed), after one wall stress."""
+    import numpy as np
+    import torch
+
+    import paper_2006_03343_amd as ibm
+    dev = torch.device("cuda", 0)
+    g = wl.grid
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev, torch.float32)
+    ctx = ibm.Context(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, dtype=torch.float32,
+                      precision="mixed", device=dev)
+    ctx.prepare(T(wl.phi_uv), T(wl.phi_w), wl.band_width, wl.phi_c, wl.kappa)
+    ctx.autotune(TUNE_CACHE)
+    u, v, w = T(wl.u), T(wl.v), T(wl.w)
+    tau = [T(t) for t in wl.tau]
+    gp = [T(t) for t in wl.gradp]
+    ustar = [u.clone(), v.clone(), w.clone()]
+    div = [torch.empty_like(u) for _ in range(3)]
+    drag = torch.zeros(3, dtype=torch.float64, device=dev)
+    ctx.wall_stress(u, v, w, tau, z0=wl.z0)
+    fn = lambda: ctx.apply_spectral(tau, ustar, div, gradp=gp, dt=wl.dt, drag=drag)
+    for _ in range(warmup):
+        fn()
+    e0, e1 = _events(2)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    wrow = (g.nx + 15) // 16
+    nbytes = g.n * 4 * (6 + 9 + 9) + g.ny * g.nz * wrow * 4
+    del ctx, tau, ustar, div
+    torch.cuda.empty_cache()
+    return {"workload": f"hill {g.nx}x{g.ny}x{g.nz}, float32 mixed",
+            "ms": ms, "points_per_s": g.n / (ms * 1e-3), "bytes_per_call": nbytes,
+            "achieved_GBs": nbytes / (ms * 1e-3) / 1e9,
+            "frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "note": "3 launches; bytes: x pass 6, y pass 9, z pass 9 field accesses per node"}
+
+
 def run_terrains(steps, warmup):
     """Stage throughput on the cube (float64) and the ridge (float64, float32,
     float32 mixed)."""
@@ -397,6 +442,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--no-terrains", action="store_true", help="skip the cube and ridge runs")
     ap.add_argument("--no-sgs", action="store_true", help="skip the Smagorinsky stress runs")
+    ap.add_argument("--no-spectral", action="store_true", help="skip the pseudo-spectral mode")
     ap.add_argument("--retune", action="store_true",
                     help="time the tile shapes again and rewrite the autotuner's cache")
     ap.add_argument("--calib-copy", action="store_true",
@@ -471,6 +517,10 @@ def main():
         out["sgs"] = run_sgs(wl, args.steps, args.warmup)
         log(f"sgs: {out['sgs']['sgs_ms']:.4f} ms ({out['sgs']['sgs_roofline']['frac'] * 100:.1f} % "
             f"of HBM peak); sgs + stage {out['sgs']['sgs_wall_stress_apply_ms']:.4f} ms")
+    if not args.no_spectral:
+        out["spectral"] = run_spectral(wl, args.steps, args.warmup)
+        log(f"spectral: {out['spectral']['ms']:.4f} ms per ibm_apply_spectral "
+            f"({out['spectral']['frac'] * 100:.1f} % of HBM peak)")
     if not args.no_terrains:
         out["terrains"] = run_terrains(args.steps, args.warmup)
     if not args.no_cpu:

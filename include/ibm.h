@@ -119,6 +119,19 @@ int ibm_apply(ibm_ctx* c, const void* const tau[6], void* const ustar[3],
               const void* const gradp[3], double dt, void* const div[3], double* drag_dev,
               void* stream);
 
+/* ibm_apply with the horizontal derivatives of the divergence taken
+ * pseudo-spectrally, as the paper's solver does (§2.4, eq. dudx): d/dx A =
+ * sum of i k A_hat exp(i k x) over the wavenumbers of the periodic x and y
+ * directions, the Nyquist mode without derivative; vertical differences,
+ * zero padding, forcing and drag exactly as in ibm_apply.  nx and ny must be
+ * powers of two that fit one block's LDS (float: nx, ny <= 2048; double:
+ * nx, ny <= 1024), else IBM_E_UNSUPPORTED.  The first call
+ * on a context builds twiddle tables (synchronous).  Asynchronous on
+ * ``stream`` otherwise.  Errors: those of ibm_apply, IBM_E_UNSUPPORTED. */
+int ibm_apply_spectral(ibm_ctx* c, const void* const tau[6], void* const ustar[3],
+                       const void* const gradp[3], double dt, void* const div[3],
+                       double* drag_dev, void* stream);
+
 /* Smagorinsky sub-grid stress with Mason's wall damping (§2.2, eqs.
  * t-ij-1963, nu-t, smag, smag-1): the stress field that ibm_wall_stress then
  * overwrites at band and solid nodes.  The wall distance in the damping is

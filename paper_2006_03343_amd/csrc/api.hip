@@ -97,6 +97,7 @@ int ibm_destroy(ibm_ctx* c) {
     if (!c) return IBM_OK;
     DeviceScope dg(c->device);
     free_prepared(c);
+    free_spectral(c);
     (void)hipFree(c->ws_partials);
     (void)hipFree(c->ap_partials);
     delete c;
@@ -229,6 +230,29 @@ int ibm_apply(ibm_ctx* c, const void* const tau[6], void* const ustar[3],
     if (drag_dev && ((uintptr_t)drag_dev % 8)) return fail(IBM_E_ARG, "%s: drag_dev misaligned", fn);
     DeviceScope dg(c->device);
     return launch_apply(c, cfg, tau, ustar, gradp, dt, div, drag_dev, (hipStream_t)stream);
+}
+
+int ibm_apply_spectral(ibm_ctx* c, const void* const tau[6], void* const ustar[3],
+                       const void* const gradp[3], double dt, void* const div[3],
+                       double* drag_dev, void* stream) {
+    g_err[0] = 0;
+    const char* fn = "ibm_apply_spectral";
+    int rc = check_ctx(c, true, fn);
+    if (rc) return rc;
+    if (!tau || !ustar || !div) return fail(IBM_E_ARG, "%s: tau, ustar and div are required", fn);
+    if (!std::isfinite(dt)) return fail(IBM_E_ARG, "%s: dt must be finite", fn);
+    for (int i = 0; i < 6; ++i)
+        if ((rc = check_field(c, tau[i], fn, "tau[i]"))) return rc;
+    for (int i = 0; i < 3; ++i) {
+        if ((rc = check_field(c, div[i], fn, "div[i]"))) return rc;
+        if ((rc = check_field(c, ustar[i], fn, "ustar[i]"))) return rc;
+        if (gradp && gradp[i] && (rc = check_field(c, gradp[i], fn, "gradp[i]"))) return rc;
+        for (int j = 0; j < 6; ++j)
+            if (div[i] == tau[j]) return fail(IBM_E_ARG, "%s: div may not alias tau", fn);
+    }
+    if (drag_dev && ((uintptr_t)drag_dev % 8)) return fail(IBM_E_ARG, "%s: drag_dev misaligned", fn);
+    DeviceScope dg(c->device);
+    return launch_apply_spectral(c, tau, ustar, gradp, dt, div, drag_dev, (hipStream_t)stream);
 }
 
 int ibm_sgs_stress(ibm_ctx* c, const void* phi_uv, const void* phi_w, const void* u,

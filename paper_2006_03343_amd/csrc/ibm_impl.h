@@ -76,6 +76,12 @@ struct TileCfg {
     int vx = 4, ty = 4, kz = 16, wpb = 4;
 };
 
+// Twiddle tables of the pseudo-spectral mode (built on first use).
+struct SpectralTw {
+    void* twx = nullptr;   // exp(-2 pi i t / nx), t < nx/2, storage-type complex
+    void* twy = nullptr;
+};
+
 // Transposed sample-stencil map for the reverse mode (built on first use).
 struct AdjointMap {
     bool built = false;
@@ -113,6 +119,7 @@ struct ibm_ctx {
     long ap_cap = 0;                    // in doubles
     ibm::TileCfg cfg;
     ibm::AdjointMap adj;
+    ibm::SpectralTw spec;
     // bumped whenever the tile shape or any prepared device buffer may change;
     // a batch compares it against the value its work tables were built with
     unsigned long gen = 0;
@@ -142,6 +149,13 @@ long band_blocks(const ibm_ctx* c);
 // Size the reduction slots for the current geometry and tile shape.  Called
 // outside launches; waits for the device before freeing a smaller buffer.
 int size_partials(ibm_ctx* c);
+
+// spectral.hip
+int launch_apply_spectral(ibm_ctx* c, const void* const tau[6], void* const ustar[3],
+                          const void* const gradp[3], double dt, void* const div[3],
+                          double* drag, hipStream_t s);
+long spectral_slots(const ibm_ctx* c);   // reduction slots (doubles) it needs
+void free_spectral(ibm_ctx* c);
 
 // sgs.hip
 int launch_sgs(ibm_ctx* c, const TileCfg& cfg, const void* phi_uv, const void* phi_w,

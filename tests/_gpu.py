@@ -21,7 +21,7 @@ def normwise(got, exp):
 
 
 def run_gpu(wl, dtype="f64", precision="plain", tile=None, stats=True, drag=True,
-            in_place=False):
+            in_place=False, spectral=False):
     """One stage pass of the library (ibm_wall_stress then ibm_apply;
     ``in_place``: ustar is u, v, w themselves); returns numpy outputs and the
     context."""
@@ -46,7 +46,8 @@ def run_gpu(wl, dtype="f64", precision="plain", tile=None, stats=True, drag=True
     gp = [T(t) for t in wl.gradp] if wl.gradp is not None else None
     z0 = None if lz is not None else wl.z0
     ctx.wall_stress(u, v, w, list(tau), z0=z0, log_z0=lz, stats=st)
-    ctx.apply(list(tau), list(ustar), list(div), gradp=gp, dt=wl.dt, drag=dr)
+    (ctx.apply_spectral if spectral else ctx.apply)(list(tau), list(ustar), list(div), gradp=gp,
+                                                    dt=wl.dt, drag=dr)
     torch.cuda.synchronize()
     out = dict(tau=tau.cpu().numpy(), div=div.cpu().numpy(), ustar=ustar.cpu().numpy(),
                stats=st.cpu().numpy() if stats else None, drag=dr.cpu().numpy() if drag else None,
