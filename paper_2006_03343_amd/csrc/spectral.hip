@@ -6,9 +6,9 @@
 //   u-*-IBM) and the drag are those of the dense pass.
 //
 // Three launches, each HBM bound:
-//   k_dx   one block per two rows: complex FFTs of length nx in LDS on
-//          tau_xx + i tau_xy of each row and tau_xz of both rows packed into
-//          one sequence (the derivative is a real operator, so the real and
+//   k_dx   one block per R rows (up to 8, as LDS allows): complex FFTs of
+//          length nx in LDS on tau_xx + i tau_xy of each row and tau_xz of
+//          two rows packed into one sequence (the derivative is a real operator, so the real and
 //          imaginary parts stay separate); multiply by i k / nx with the
 //          Nyquist mode dropped (explicitly: with two fields packed its term
 //          would leak into the other field); inverse transform; write
@@ -24,7 +24,7 @@
 // frequency on natural-order input computed as conj(FFT(conj X)), so its
 // output is read back at bit-reversed positions and no permutation pass is
 // needed.  Twiddles exp(-2 pi i t / N), t < N/2, come from a table computed
-// in double on the host.
+// in double on the host and staged into LDS by each block.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -48,21 +48,29 @@ __device__ inline unsigned bitrev(unsigned i, int logn) {
     return logn ? (__brev(i) >> (32 - logn)) : 0u;
 }
 
+// The twiddle table (n/2 entries) copied into LDS once per block.
+template <typename T>
+__device__ inline void stage_twiddles(Cx<T>* tl, const Cx<T>* __restrict__ tw, int n) {
+    for (int t = threadIdx.x; t < n / 2; t += blockDim.x) tl[t] = tw[t];
+}
+
 // Forward FFT (decimation in time) of ``ns`` sequences of length n = 2^logn
 // held in LDS in bit-reversed order, sequence s at s * n; natural-order
-// output in place.  All threads of the block take part.
+// output in place.  All threads of the block take part; index arithmetic is
+// shifts and masks (n is a power of two); twiddles from the LDS table.
 template <typename T>
-__device__ void fft_dit(Cx<T>* x, int ns, int logn, const Cx<T>* __restrict__ tw) {
-    const int n = 1 << logn;
-    const int nb = ns * (n >> 1);
+__device__ void fft_dit(Cx<T>* x, int ns, int logn, const Cx<T>* tw) {
+    if (logn == 0) return;
+    const int lh = logn - 1, hmask = (1 << lh) - 1;
+    const int nb = ns << lh;
     for (int s = 1; s <= logn; ++s) {
-        const int half = 1 << (s - 1);
-        const int tstep = n >> s;            // twiddle stride: W_{2 half}^pos = W_n^{pos * tstep}
+        const int ls = s - 1, half = 1 << ls;
+        const int tsh = logn - s;            // W_{2 half}^pos = W_n^(pos << (logn - s))
         for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-            const int seq = b / (n >> 1), bb = b - seq * (n >> 1);
-            const int grp = bb / half, pos = bb - grp * half;
-            Cx<T>* base = x + seq * n + grp * 2 * half + pos;
-            const Cx<T> w = tw[pos * tstep];
+            const int seq = b >> lh, bb = b & hmask;
+            const int grp = bb >> ls, pos = bb & (half - 1);
+            Cx<T>* base = x + (seq << logn) + (grp << s) + pos;
+            const Cx<T> w = tw[pos << tsh];
             const Cx<T> a = base[0], t = cmul(w, base[half]);
             base[0] = Cx<T>{a.re + t.re, a.im + t.im};
             base[half] = Cx<T>{a.re - t.re, a.im - t.im};
@@ -74,17 +82,18 @@ __device__ void fft_dit(Cx<T>* x, int ns, int logn, const Cx<T>* __restrict__ tw
 // Forward FFT (decimation in frequency) of natural-order input; the output
 // lands in bit-reversed order.
 template <typename T>
-__device__ void fft_dif(Cx<T>* x, int ns, int logn, const Cx<T>* __restrict__ tw) {
-    const int n = 1 << logn;
-    const int nb = ns * (n >> 1);
+__device__ void fft_dif(Cx<T>* x, int ns, int logn, const Cx<T>* tw) {
+    if (logn == 0) return;
+    const int lh = logn - 1, hmask = (1 << lh) - 1;
+    const int nb = ns << lh;
     for (int s = logn; s >= 1; --s) {
-        const int half = 1 << (s - 1);
-        const int tstep = n >> s;
+        const int ls = s - 1, half = 1 << ls;
+        const int tsh = logn - s;
         for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-            const int seq = b / (n >> 1), bb = b - seq * (n >> 1);
-            const int grp = bb / half, pos = bb - grp * half;
-            Cx<T>* base = x + seq * n + grp * 2 * half + pos;
-            const Cx<T> w = tw[pos * tstep];
+            const int seq = b >> lh, bb = b & hmask;
+            const int grp = bb >> ls, pos = bb & (half - 1);
+            Cx<T>* base = x + (seq << logn) + (grp << s) + pos;
+            const Cx<T> w = tw[pos << tsh];
             const Cx<T> a = base[0], c = base[half];
             base[0] = Cx<T>{a.re + c.re, a.im + c.im};
             base[half] = cmul(Cx<T>{a.re - c.re, a.im - c.im}, w);
@@ -118,41 +127,49 @@ struct SpecArgs {
     const Cx<T>* twy;
     int nx, ny, nz, logx, logy;
     long rows;               // ny * nz
-    int cols;                // columns per k_dy block
+    int cols;                // columns per k_dy block (even)
+    int rows_per;            // rows per k_dx block (even)
     T kx, ky;                // 2 pi / Lx, 2 pi / Ly
 };
 
-// Two rows per block: sequences 0, 1 = tau_xx + i tau_xy of rows r0, r1;
-// sequence 2 = tau_xz[r0] + i tau_xz[r1].
+// R rows per block (R even): sequence r = tau_xx + i tau_xy of row r0 + r,
+// sequence R + r/2 = tau_xz of rows r0 + r (real part, r even) and r0 + r + 1
+// (imaginary part); the twiddle table follows the sequences in LDS.
 template <typename T>
 __global__ void __launch_bounds__(256) k_dx(SpecArgs<T> a) {
     extern __shared__ unsigned char lds_raw[];
     Cx<T>* x = reinterpret_cast<Cx<T>*>(lds_raw);
-    const int n = a.nx, logn = a.logx;
-    const long r0 = 2L * blockIdx.x;
-    const bool two = r0 + 1 < a.rows;
-    const long o0 = r0 * n, o1 = (r0 + 1) * n;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int n = a.nx, logn = a.logx, R = a.rows_per;
+    const int ns = R + R / 2;
+    Cx<T>* tw = x + ns * n;
+    stage_twiddles(tw, a.twx, n);
+    const long r0 = (long)R * blockIdx.x;
+    for (int e = threadIdx.x; e < R * n; e += blockDim.x) {
+        const int r = e >> logn, i = e & (n - 1);
+        const bool in = r0 + r < a.rows;
+        const long o = (r0 + r) * n + i;
         const unsigned p = bitrev((unsigned)i, logn);
-        x[p] = Cx<T>{a.tau[0][o0 + i], a.tau[3][o0 + i]};
-        x[n + p] = two ? Cx<T>{a.tau[0][o1 + i], a.tau[3][o1 + i]} : Cx<T>{T(0), T(0)};
-        x[2 * n + p] = Cx<T>{a.tau[4][o0 + i], two ? a.tau[4][o1 + i] : T(0)};
+        x[(r << logn) + p] = in ? Cx<T>{a.tau[0][o], a.tau[3][o]} : Cx<T>{T(0), T(0)};
+        const T xz = in ? a.tau[4][o] : T(0);
+        Cx<T>& q = x[((R + r / 2) << logn) + p];
+        if (r & 1) q.im = xz;
+        else q.re = xz;
     }
     __syncthreads();
-    fft_dit(x, 3, logn, a.twx);
-    derivative_conj(x, 3, logn, a.kx);
-    fft_dif(x, 3, logn, a.twx);
+    fft_dit(x, ns, logn, tw);
+    derivative_conj(x, ns, logn, a.kx);
+    fft_dif(x, ns, logn, tw);
     // the derivative at i is conj(x[bitrev(i)]): real part x.re, imaginary -x.im
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    for (int e = threadIdx.x; e < R * n; e += blockDim.x) {
+        const int r = e >> logn, i = e & (n - 1);
+        if (r0 + r >= a.rows) continue;
+        const long o = (r0 + r) * n + i;
         const unsigned p = bitrev((unsigned)i, logn);
-        a.div[0][o0 + i] = x[p].re;
-        a.div[1][o0 + i] = -x[p].im;
-        a.div[2][o0 + i] = x[2 * n + p].re;
-        if (two) {
-            a.div[0][o1 + i] = x[n + p].re;
-            a.div[1][o1 + i] = -x[n + p].im;
-            a.div[2][o1 + i] = -x[2 * n + p].im;
-        }
+        const Cx<T> d = x[(r << logn) + p];
+        const Cx<T> dq = x[((R + r / 2) << logn) + p];
+        a.div[0][o] = d.re;
+        a.div[1][o] = -d.im;
+        a.div[2][o] = (r & 1) ? -dq.im : dq.re;
     }
 }
 
@@ -163,6 +180,8 @@ __global__ void __launch_bounds__(256) k_dy(SpecArgs<T> a) {
     extern __shared__ unsigned char lds_raw[];
     Cx<T>* x = reinterpret_cast<Cx<T>*>(lds_raw);
     const int n = a.ny, logn = a.logy, C = a.cols;
+    Cx<T>* tw = x + (C + C / 2) * n;
+    stage_twiddles(tw, a.twy, n);
     const int groups = (a.nx + C - 1) / C;
     const int k = blockIdx.x / groups;
     const int x0 = (blockIdx.x - k * groups) * C;
@@ -182,9 +201,9 @@ __global__ void __launch_bounds__(256) k_dy(SpecArgs<T> a) {
     }
     __syncthreads();
     const int ns = C + C / 2;
-    fft_dit(x, ns, logn, a.twy);
+    fft_dit(x, ns, logn, tw);
     derivative_conj(x, ns, logn, a.ky);
-    fft_dif(x, ns, logn, a.twy);
+    fft_dif(x, ns, logn, tw);
     for (int e = threadIdx.x; e < C * n; e += blockDim.x) {
         const int c = e % C, j = e / C;
         const int xx = x0 + c;
@@ -302,14 +321,17 @@ int spectral_t(ibm_ctx* c, const void* const tau[6], void* const ustar[3],
     const size_t cs = sizeof(Cx<T>);
     if (lx < 0 || ly < 0)
         return fail(IBM_E_UNSUPPORTED, "apply_spectral: nx and ny must be powers of two (%d, %d)", nx, ny);
-    if (3 * (size_t)nx * cs > lds_limit())
+    // LDS of a block: its sequences plus the twiddle table
+    auto fits = [&](int seqs, int n) { return ((size_t)seqs * n + n / 2) * cs <= lds_limit(); };
+    int R = 8;
+    while (R > 2 && !fits(R + R / 2, nx)) R /= 2;
+    if (!fits(R + R / 2, nx))
         return fail(IBM_E_UNSUPPORTED, "apply_spectral: nx = %d too long for one block's LDS", nx);
     int C = 64;
-    while (C > 2 && (size_t)(C + C / 2) * ny * cs > lds_limit()) C /= 2;
-    if ((size_t)(C + C / 2) * ny * cs > lds_limit())
+    while (C > 2 && !fits(C + C / 2, ny)) C /= 2;
+    if (!fits(C + C / 2, ny))
         return fail(IBM_E_UNSUPPORTED, "apply_spectral: ny = %d too long for one block's LDS", ny);
     C = std::min(C, std::max(2, nx));
-    if (C & 1) ++C;
     if (!c->spec.twx || !c->spec.twy) {
         void *tx = nullptr, *ty = nullptr;
         int rc = twiddles<T>(c, nx, &tx);
@@ -335,12 +357,14 @@ int spectral_t(ibm_ctx* c, const void* const tau[6], void* const ustar[3],
     a.logy = ly;
     a.rows = (long)ny * nz;
     a.cols = C;
+    a.rows_per = R;
     a.kx = (T)(2.0 * M_PI / (nx * c->g.dx));
     a.ky = (T)(2.0 * M_PI / (ny * c->g.dy));
-    hipLaunchKernelGGL(k_dx<T>, dim3((unsigned)((a.rows + 1) / 2)), dim3(256), 3 * nx * cs, s, a);
+    hipLaunchKernelGGL(k_dx<T>, dim3((unsigned)((a.rows + R - 1) / R)), dim3(256),
+                       ((size_t)(R + R / 2) * nx + nx / 2) * cs, s, a);
     const int groups = (nx + C - 1) / C;
     hipLaunchKernelGGL(k_dy<T>, dim3((unsigned)(groups * nz)), dim3(256),
-                       (size_t)(C + C / 2) * ny * cs, s, a);
+                       ((size_t)(C + C / 2) * ny + ny / 2) * cs, s, a);
     ApplyArgs<T> z = make_apply_args<T>(c, c->cfg, tau, ustar, gradp, dt, div, drag);
     const long n = c->n;
     const int nzb = (int)((n + 256L * kZItems - 1) / (256L * kZItems));
