@@ -280,6 +280,90 @@ def stage_spectral(wl, ustar=None):
     return out
 
 
+# ------------------------------------ §2.4 AB2 update and pressure projection
+def ab2_predict(u, rhs_now, rhs_prev, dt):
+    """eq. u-inter: u* = u + dt (3/2 RHS'^t - 1/2 RHS^(t - dt)), per component."""
+    return [np.asarray(a, np.float64) + dt * (1.5 * np.asarray(b, np.float64)
+                                              - 0.5 * np.asarray(c, np.float64))
+            for a, b, c in zip(u, rhs_now, rhs_prev)]
+
+
+def _wavenumbers(n, length):
+    """2 pi m / L for the FFT ordering of modes, the Nyquist mode of an even
+    count set to 0 (as in ``spectral_derivative``)."""
+    m = np.fft.fftfreq(n, d=1.0 / n)
+    k = 2.0 * np.pi * m / length
+    if n % 2 == 0:
+        k[n // 2] = 0.0
+    return k
+
+
+def divergence_velocity(g, u, v, w):
+    """Discrete divergence D of a velocity on the staggered grid, on uv nodes:
+    pseudo-spectral du/dx + dv/dy (eq. dudx) plus (w[k+1] - w[k]) / dz
+    (eq. dwdz), w taken as 0 above the top w node."""
+    u, v, w = (_f64(a, g) for a in (u, v, w))
+    above = np.zeros_like(w)
+    above[:-1] = w[1:]
+    return (spectral_derivative(u, 2, g.nx * g.dx) + spectral_derivative(v, 1, g.ny * g.dy)
+            + (above - w) / g.dz)
+
+
+def gradient_pressure(g, p):
+    """Discrete gradient G of a pressure on uv nodes: pseudo-spectral d/dx,
+    d/dy on uv nodes; (p[k] - p[k-1]) / dz on the w node k >= 1 and 0 on the
+    bottom w node (no correction there: the lowest w node is a wall node)."""
+    p = _f64(p, g)
+    gz = np.zeros_like(p)
+    gz[1:] = (p[1:] - p[:-1]) / g.dz
+    return [spectral_derivative(p, 2, g.nx * g.dx), spectral_derivative(p, 1, g.ny * g.dy), gz]
+
+
+def pressure_poisson(g, ustar, dt):
+    """eqs. p-Poisson, p-Poisson-Fourier: [d2/dz2 - (kx^2 + ky^2)] p_hat =
+    2/(3 dt) (i kx u*_hat + i ky v*_hat + d/dz w*_hat), with d2/dz2 = the
+    vertical part of D G (no flux through the bottom w node or above the top
+    plane: the rows of k = 0 and nz-1 lose their outer neighbour); each
+    horizontal mode is one tridiagonal system in z, solved here by a dense
+    solve; a mode without horizontal wavenumber (kx = ky = 0 once Nyquist
+    modes count as 0: the mean and the Nyquist modes) is singular and takes
+    p_hat = 0 at k = 0 in place of its first row."""
+    rhs = 2.0 / (3.0 * dt) * divergence_velocity(g, *ustar)
+    rh = np.fft.fft2(rhs, axes=(1, 2))                 # [nz][ny][nx] complex
+    kx = _wavenumbers(g.nx, g.nx * g.dx)
+    ky = _wavenumbers(g.ny, g.ny * g.dy)
+    nz, c = g.nz, 1.0 / g.dz ** 2
+    ph = np.zeros_like(rh)
+    for j in range(g.ny):
+        for i in range(g.nx):
+            K2 = kx[i] ** 2 + ky[j] ** 2
+            A = np.zeros((nz, nz))
+            for k in range(nz):
+                if k > 0:
+                    A[k, k - 1] = c
+                    A[k, k] -= c
+                if k < nz - 1:
+                    A[k, k + 1] = c
+                    A[k, k] -= c
+                A[k, k] -= K2
+            b = rh[:, j, i].copy()
+            if K2 == 0.0:
+                A[0, :] = 0.0
+                A[0, 0] = 1.0
+                b[0] = 0.0
+            ph[:, j, i] = np.linalg.solve(A, b)
+    return np.real(np.fft.ifft2(ph, axes=(1, 2)))
+
+
+def pressure_project(g, ustar, dt):
+    """eq. u-t+1: u(t + dt) = u* - (3 dt / 2) G p, with p from
+    ``pressure_poisson``.  Returns (u, v, w, p)."""
+    p = pressure_poisson(g, ustar, dt)
+    gp = gradient_pressure(g, p)
+    out = [_f64(a, g) - 1.5 * dt * b for a, b in zip(ustar, gp)]
+    return out[0], out[1], out[2], p
+
+
 def stage_vjp(wl, g_tau, g_div, g_ustar, g_drag):
     """Reverse mode of one pass with ustar = u (see ``ora_stage_vjp``)."""
     g = wl.grid
