@@ -49,18 +49,20 @@ PROFILE = os.path.join(ROOT, "profiles", "k_apply_hill512x256x256_f32_mixed.txt"
 
 def measured_traffic(tile):
     """HBM bytes per k_apply launch from the committed counter profile, if the
-    dense-pass source and the tile shape are the ones that were profiled."""
+    dense pass's device code and launch code (kernels.h, and stage.hip up to
+    the end of its anonymous namespace) and the tile shape are the ones that
+    were profiled."""
     import hashlib
-    src = b""
-    for f in ("kernels.h", "stage.hip"):
-        src += open(os.path.join(ROOT, "paper_2006_03343_amd", "csrc", f), "rb").read()
-    h = hashlib.sha256(src).hexdigest()
+    csrc = os.path.join(ROOT, "paper_2006_03343_amd", "csrc")
+    stage = open(os.path.join(csrc, "stage.hip"), "rb").read()
+    stage = stage[:stage.index(b"}  // namespace\n")]
+    h = hashlib.sha256(open(os.path.join(csrc, "kernels.h"), "rb").read() + stage).hexdigest()
     try:
         lines = open(PROFILE).read().splitlines()
     except OSError:
         return None
     kv = dict(ln.split(": ", 1) for ln in lines if ": " in ln and not ln.startswith(" "))
-    if kv.get("source_sha256 (csrc/kernels.h + csrc/stage.hip)") != h:
+    if kv.get("source_sha256 (csrc/kernels.h + launch half of csrc/stage.hip)") != h:
         return None
     if kv.get("tile") != ",".join(str(x) for x in tile):
         return None
@@ -382,6 +384,62 @@ def run_spectral(wl, steps, warmup):
             "note": "3 launches; bytes: x pass 6, y pass 9, z pass 9 field accesses per node"}
 
 
+def run_projection(wl, steps, warmup):
+    """ibm_ab2_predict and ibm_pressure_project on the hill's grid (float32):
+    the time advance around the stage."""
+    import numpy as np
+    import torch
+
+    import paper_2006_03343_amd as ibm
+    dev = torch.device("cuda", 0)
+    g = wl.grid
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev, torch.float32)
+    ctx = ibm.Context(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, dtype=torch.float32, device=dev)
+    vel = [T(wl.u), T(wl.v), T(wl.w)]
+    vel[2][0].zero_()
+    rn = [T(t) for t in wl.tau[:3]]
+    rp = [T(t) for t in wl.tau[3:]]
+    ustar = [torch.empty_like(a) for a in vel]
+    uo = [torch.empty_like(a) for a in vel]
+    p = torch.empty_like(vel[0])
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        e0, e1 = _events(2)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    ab2_ms = timed(lambda: ctx.ab2_predict(vel, rn, rp, wl.dt, ustar))
+    proj_ms = timed(lambda: ctx.pressure_project(ustar, wl.dt, uo, p))
+    # algorithmic: AB2 reads u, rhs, rhs_prev and writes u* (3 components);
+    # the projection reads u*, v*, w* and writes u, v, w, p
+    ab2_bytes = g.n * 4 * 4 * 3
+    proj_bytes = g.n * 4 * 7
+    # what the passes move: forward x (4 + 8) and y (8 + 8) per field, the
+    # solve (24 + 24 read, 24 + 24 written), inverse y (16 per field),
+    # inverse x (12 for p, 16 for u and v), the w correction (4 + 4 + 4)
+    pass_bytes = g.n * (3 * 12 + 3 * 16 + 96 + 3 * 16 + 12 + 2 * 16 + 12)
+    del ctx, vel, rn, rp, ustar, uo, p
+    torch.cuda.empty_cache()
+    gbs = lambda b, ms: b / (ms * 1e-3) / 1e9
+    return {"workload": f"{g.nx}x{g.ny}x{g.nz}, float32",
+            "ab2_ms": ab2_ms, "ab2_GBs": gbs(ab2_bytes, ab2_ms),
+            "ab2_frac": gbs(ab2_bytes, ab2_ms) / HBM_PEAK_GBS,
+            "project_ms": proj_ms, "project_points_per_s": g.n / (proj_ms * 1e-3),
+            "project_algorithmic_GBs": gbs(proj_bytes, proj_ms),
+            "project_algorithmic_frac": gbs(proj_bytes, proj_ms) / HBM_PEAK_GBS,
+            "project_pass_GBs": gbs(pass_bytes, proj_ms),
+            "note": "projection: 12 launches (6 forward transforms, solve, 3 inverse y, "
+                    "3 inverse x, w correction); algorithmic bytes 28 per node, the passes "
+                    f"move {pass_bytes // g.n} per node"}
+
+
 def run_terrains(steps, warmup):
     """Stage throughput on the cube (float64) and the ridge (float64, float32,
     float32 mixed)."""
@@ -443,6 +501,8 @@ def main():
     ap.add_argument("--no-terrains", action="store_true", help="skip the cube and ridge runs")
     ap.add_argument("--no-sgs", action="store_true", help="skip the Smagorinsky stress runs")
     ap.add_argument("--no-spectral", action="store_true", help="skip the pseudo-spectral mode")
+    ap.add_argument("--no-projection", action="store_true",
+                    help="skip the AB2 update and the pressure projection")
     ap.add_argument("--retune", action="store_true",
                     help="time the tile shapes again and rewrite the autotuner's cache")
     ap.add_argument("--calib-copy", action="store_true",
@@ -521,6 +581,10 @@ def main():
         out["spectral"] = run_spectral(wl, args.steps, args.warmup)
         log(f"spectral: {out['spectral']['ms']:.4f} ms per ibm_apply_spectral "
             f"({out['spectral']['frac'] * 100:.1f} % of HBM peak)")
+    if not args.no_projection:
+        out["projection"] = run_projection(wl, args.steps, args.warmup)
+        log(f"projection: {out['projection']['project_ms']:.4f} ms per ibm_pressure_project, "
+            f"ab2 {out['projection']['ab2_ms']:.4f} ms")
     if not args.no_terrains:
         out["terrains"] = run_terrains(args.steps, args.warmup)
     if not args.no_cpu:

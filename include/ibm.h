@@ -132,6 +132,32 @@ int ibm_apply_spectral(ibm_ctx* c, const void* const tau[6], void* const ustar[3
                        const void* const gradp[3], double dt, void* const div[3],
                        double* drag_dev, void* stream);
 
+/* The time advance around the stage (§2.4).  ibm_ab2_predict: eq. u-inter,
+ * ustar = u + dt (3/2 rhs_now - 1/2 rhs_prev) per component (ustar may alias
+ * u).  ibm_pressure_project: eqs. p-Poisson, p-Poisson-Fourier and u-t+1 --
+ * solve D G p = 2/(3 dt) D ustar and return u_out = ustar - (3 dt/2) G p and
+ * the pressure p_out (on uv nodes).  D: pseudo-spectral d/dx, d/dy (Nyquist
+ * modes without derivative) plus (w[k+1] - w[k]) / dz on uv nodes, w above
+ * the top w node taken as 0; G: pseudo-spectral d/dx, d/dy of p on uv nodes
+ * and (p[k] - p[k-1]) / dz on w nodes k >= 1, no correction on the bottom w
+ * node.  Each horizontal mode is a tridiagonal system in z (Thomas, in
+ * double for either storage type); a mode
+ * without horizontal wavenumber (the mean and the Nyquist modes) is singular
+ * and takes p = 0 at k = 0 in place of its first row, so u_out is discretely
+ * divergence-free when w is 0 on the bottom plane.  u_out may alias ustar;
+ * p_out may alias neither.  nx, ny: powers of two as for
+ * ibm_apply_spectral, else IBM_E_UNSUPPORTED.  The first call allocates a
+ * workspace of 3 complex volumes (double storage: and 1 real volume) of the
+ * storage type and builds twiddle tables
+ * (synchronous).  Needs a context, not a prepare.  Asynchronous on
+ * ``stream`` otherwise.  Errors: IBM_E_ARG, IBM_E_RANGE (dt <= 0),
+ * IBM_E_UNSUPPORTED, IBM_E_HIP. */
+int ibm_ab2_predict(ibm_ctx* c, const void* const u[3], const void* const rhs_now[3],
+                    const void* const rhs_prev[3], double dt, void* const ustar[3],
+                    void* stream);
+int ibm_pressure_project(ibm_ctx* c, const void* const ustar[3], double dt, void* const u_out[3],
+                         void* p_out, void* stream);
+
 /* Smagorinsky sub-grid stress with Mason's wall damping (§2.2, eqs.
  * t-ij-1963, nu-t, smag, smag-1): the stress field that ibm_wall_stress then
  * overwrites at band and solid nodes.  The wall distance in the damping is

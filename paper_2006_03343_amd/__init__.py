@@ -201,6 +201,23 @@ class Context:
             check(self._lib.ibm_apply_spectral(self._h, ptr_array(taus), ptr_array(us), gp,
                                                float(dt), ptr_array(dv), dp, self._stream()))
 
+    def ab2_predict(self, u, rhs_now, rhs_prev, dt, ustar):
+        """ustar = u + dt (3/2 rhs_now - 1/2 rhs_prev), three components."""
+        args = [ptr_array(self._fields(x, name, 3)) for x, name in
+                ((u, "u"), (rhs_now, "rhs_now"), (rhs_prev, "rhs_prev"))]
+        with torch.cuda.device(self.device):
+            check(self._lib.ibm_ab2_predict(self._h, *args, float(dt),
+                                            ptr_array(self._fields(ustar, "ustar", 3)),
+                                            self._stream()))
+
+    def pressure_project(self, ustar, dt, u_out, p_out):
+        """Pressure Poisson solve and projection: u_out = ustar - (3 dt/2) G p."""
+        with torch.cuda.device(self.device):
+            check(self._lib.ibm_pressure_project(self._h, ptr_array(self._fields(ustar, "ustar", 3)),
+                                                 float(dt),
+                                                 ptr_array(self._fields(u_out, "u_out", 3)),
+                                                 self._field(p_out, "p_out"), self._stream()))
+
     def sgs_stress(self, phi_uv, phi_w, u, v, w, tau, z0=None, log_z0=None, cs=0.16, kappa=0.4):
         """Smagorinsky stress with Mason's wall damping written into ``tau``
         (6 fields); the wall distance is phi of each node's grid."""

@@ -98,6 +98,7 @@ int ibm_destroy(ibm_ctx* c) {
     DeviceScope dg(c->device);
     free_prepared(c);
     free_spectral(c);
+    free_projection(c);
     (void)hipFree(c->ws_partials);
     (void)hipFree(c->ap_partials);
     delete c;
@@ -253,6 +254,44 @@ int ibm_apply_spectral(ibm_ctx* c, const void* const tau[6], void* const ustar[3
     if (drag_dev && ((uintptr_t)drag_dev % 8)) return fail(IBM_E_ARG, "%s: drag_dev misaligned", fn);
     DeviceScope dg(c->device);
     return launch_apply_spectral(c, tau, ustar, gradp, dt, div, drag_dev, (hipStream_t)stream);
+}
+
+int ibm_ab2_predict(ibm_ctx* c, const void* const u[3], const void* const rhs_now[3],
+                    const void* const rhs_prev[3], double dt, void* const ustar[3],
+                    void* stream) {
+    g_err[0] = 0;
+    const char* fn = "ibm_ab2_predict";
+    int rc = check_ctx(c, false, fn);
+    if (rc) return rc;
+    if (!u || !rhs_now || !rhs_prev || !ustar) return fail(IBM_E_ARG, "%s: NULL field array", fn);
+    for (int i = 0; i < 3; ++i)
+        if ((rc = check_field(c, u[i], fn, "u[i]")) || (rc = check_field(c, rhs_now[i], fn, "rhs_now[i]")) ||
+            (rc = check_field(c, rhs_prev[i], fn, "rhs_prev[i]")) ||
+            (rc = check_field(c, ustar[i], fn, "ustar[i]")))
+            return rc;
+    if (!std::isfinite(dt)) return fail(IBM_E_ARG, "%s: dt must be finite", fn);
+    DeviceScope dg(c->device);
+    return launch_ab2(c, u, rhs_now, rhs_prev, dt, ustar, (hipStream_t)stream);
+}
+
+int ibm_pressure_project(ibm_ctx* c, const void* const ustar[3], double dt, void* const u_out[3],
+                         void* p_out, void* stream) {
+    g_err[0] = 0;
+    const char* fn = "ibm_pressure_project";
+    int rc = check_ctx(c, false, fn);
+    if (rc) return rc;
+    if (!ustar || !u_out) return fail(IBM_E_ARG, "%s: NULL field array", fn);
+    if ((rc = check_field(c, p_out, fn, "p_out"))) return rc;
+    for (int i = 0; i < 3; ++i) {
+        if ((rc = check_field(c, ustar[i], fn, "ustar[i]")) ||
+            (rc = check_field(c, u_out[i], fn, "u_out[i]")))
+            return rc;
+        if (p_out == ustar[i] || p_out == u_out[i])
+            return fail(IBM_E_ARG, "%s: p_out may not alias a velocity field", fn);
+    }
+    if (!finite_pos(dt)) return fail(IBM_E_RANGE, "%s: dt must be finite and > 0", fn);
+    DeviceScope dg(c->device);
+    return launch_pressure_project(c, ustar, dt, u_out, p_out, (hipStream_t)stream);
 }
 
 int ibm_sgs_stress(ibm_ctx* c, const void* phi_uv, const void* phi_w, const void* u,

@@ -82,6 +82,13 @@ struct SpectralTw {
     void* twy = nullptr;
 };
 
+// Workspace of the pressure projection (allocated on first use): three
+// complex volumes and one real volume of the storage type.
+struct ProjWs {
+    void* buf = nullptr;
+    size_t bytes = 0;
+};
+
 // Transposed sample-stencil map for the reverse mode (built on first use).
 struct AdjointMap {
     bool built = false;
@@ -120,6 +127,7 @@ struct ibm_ctx {
     ibm::TileCfg cfg;
     ibm::AdjointMap adj;
     ibm::SpectralTw spec;
+    ibm::ProjWs proj;
     // bumped whenever the tile shape or any prepared device buffer may change;
     // a batch compares it against the value its work tables were built with
     unsigned long gen = 0;
@@ -155,7 +163,19 @@ int launch_apply_spectral(ibm_ctx* c, const void* const tau[6], void* const usta
                           const void* const gradp[3], double dt, void* const div[3],
                           double* drag, hipStream_t s);
 long spectral_slots(const ibm_ctx* c);   // reduction slots (doubles) it needs
+int ensure_twiddles(ibm_ctx* c);          // twiddle tables of nx and ny (first use: synchronous)
+// Rows per x-transform block and columns per y-transform block (both even)
+// within one block's LDS; IBM_E_UNSUPPORTED unless nx, ny are powers of two
+// that fit.
+int spectral_plan(const ibm_ctx* c, int* rows_per, int* cols);
 void free_spectral(ibm_ctx* c);
+
+// projection.hip
+int launch_pressure_project(ibm_ctx* c, const void* const ustar[3], double dt,
+                            void* const u_out[3], void* p_out, hipStream_t s);
+int launch_ab2(ibm_ctx* c, const void* const u[3], const void* const rhs_now[3],
+               const void* const rhs_prev[3], double dt, void* const ustar[3], hipStream_t s);
+void free_projection(ibm_ctx* c);
 
 // sgs.hip
 int launch_sgs(ibm_ctx* c, const TileCfg& cfg, const void* phi_uv, const void* phi_w,

@@ -29,95 +29,11 @@
 #include <cmath>
 #include <vector>
 
+#include "fft.h"
 #include "kernels.h"
 
 namespace ibm {
 namespace {
-
-template <typename T>
-struct Cx {
-    T re, im;
-};
-
-template <typename T>
-__device__ inline Cx<T> cmul(Cx<T> a, Cx<T> b) {
-    return Cx<T>{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
-}
-
-__device__ inline unsigned bitrev(unsigned i, int logn) {
-    return logn ? (__brev(i) >> (32 - logn)) : 0u;
-}
-
-// The twiddle table (n/2 entries) copied into LDS once per block.
-template <typename T>
-__device__ inline void stage_twiddles(Cx<T>* tl, const Cx<T>* __restrict__ tw, int n) {
-    for (int t = threadIdx.x; t < n / 2; t += blockDim.x) tl[t] = tw[t];
-}
-
-// Forward FFT (decimation in time) of ``ns`` sequences of length n = 2^logn
-// held in LDS in bit-reversed order, sequence s at s * n; natural-order
-// output in place.  All threads of the block take part; index arithmetic is
-// shifts and masks (n is a power of two); twiddles from the LDS table.
-template <typename T>
-__device__ void fft_dit(Cx<T>* x, int ns, int logn, const Cx<T>* tw) {
-    if (logn == 0) return;
-    const int lh = logn - 1, hmask = (1 << lh) - 1;
-    const int nb = ns << lh;
-    for (int s = 1; s <= logn; ++s) {
-        const int ls = s - 1, half = 1 << ls;
-        const int tsh = logn - s;            // W_{2 half}^pos = W_n^(pos << (logn - s))
-        for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-            const int seq = b >> lh, bb = b & hmask;
-            const int grp = bb >> ls, pos = bb & (half - 1);
-            Cx<T>* base = x + (seq << logn) + (grp << s) + pos;
-            const Cx<T> w = tw[pos << tsh];
-            const Cx<T> a = base[0], t = cmul(w, base[half]);
-            base[0] = Cx<T>{a.re + t.re, a.im + t.im};
-            base[half] = Cx<T>{a.re - t.re, a.im - t.im};
-        }
-        __syncthreads();
-    }
-}
-
-// Forward FFT (decimation in frequency) of natural-order input; the output
-// lands in bit-reversed order.
-template <typename T>
-__device__ void fft_dif(Cx<T>* x, int ns, int logn, const Cx<T>* tw) {
-    if (logn == 0) return;
-    const int lh = logn - 1, hmask = (1 << lh) - 1;
-    const int nb = ns << lh;
-    for (int s = logn; s >= 1; --s) {
-        const int ls = s - 1, half = 1 << ls;
-        const int tsh = logn - s;
-        for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-            const int seq = b >> lh, bb = b & hmask;
-            const int grp = bb >> ls, pos = bb & (half - 1);
-            Cx<T>* base = x + (seq << logn) + (grp << s) + pos;
-            const Cx<T> w = tw[pos << tsh];
-            const Cx<T> a = base[0], c = base[half];
-            base[0] = Cx<T>{a.re + c.re, a.im + c.im};
-            base[half] = cmul(Cx<T>{a.re - c.re, a.im - c.im}, w);
-        }
-        __syncthreads();
-    }
-}
-
-// X[m] -> conj(i k_m X[m] / n) for every sequence (natural order), k_m =
-// 2 pi m' / L with m' = m or m - n, and 0 for the Nyquist mode.
-template <typename T>
-__device__ void derivative_conj(Cx<T>* x, int ns, int logn, T two_pi_over_len) {
-    const int n = 1 << logn;
-    const T inv_n = T(1) / T(n);
-    for (int e = threadIdx.x; e < ns * n; e += blockDim.x) {
-        const int m = e & (n - 1);
-        const int mm = (2 * m < n) ? m : m - n;     // signed mode number (n = 1: mode 0)
-        const T k = (n > 1 && 2 * m == n) ? T(0) : two_pi_over_len * T(mm) * inv_n;
-        const Cx<T> v = x[e];
-        // i k (re + i im) = -k im + i k re; then conjugate
-        x[e] = Cx<T>{-k * v.im, -(k * v.re)};
-    }
-    __syncthreads();
-}
 
 template <typename T>
 struct SpecArgs {
@@ -319,32 +235,11 @@ int spectral_t(ibm_ctx* c, const void* const tau[6], void* const ustar[3],
     const int nx = c->g.nx, ny = c->g.ny, nz = c->g.nz;
     const int lx = ilog2_exact(nx), ly = ilog2_exact(ny);
     const size_t cs = sizeof(Cx<T>);
-    if (lx < 0 || ly < 0)
-        return fail(IBM_E_UNSUPPORTED, "apply_spectral: nx and ny must be powers of two (%d, %d)", nx, ny);
-    // LDS of a block: its sequences plus the twiddle table
-    auto fits = [&](int seqs, int n) { return ((size_t)seqs * n + n / 2) * cs <= lds_limit(); };
-    int R = 8;
-    while (R > 2 && !fits(R + R / 2, nx)) R /= 2;
-    if (!fits(R + R / 2, nx))
-        return fail(IBM_E_UNSUPPORTED, "apply_spectral: nx = %d too long for one block's LDS", nx);
-    int C = 64;
-    while (C > 2 && !fits(C + C / 2, ny)) C /= 2;
-    if (!fits(C + C / 2, ny))
-        return fail(IBM_E_UNSUPPORTED, "apply_spectral: ny = %d too long for one block's LDS", ny);
-    C = std::min(C, std::max(2, nx));
-    if (!c->spec.twx || !c->spec.twy) {
-        void *tx = nullptr, *ty = nullptr;
-        int rc = twiddles<T>(c, nx, &tx);
-        if (!rc) rc = twiddles<T>(c, ny, &ty);
-        if (rc) {
-            (void)hipFree(tx);
-            (void)hipFree(ty);
-            return rc;
-        }
-        free_spectral_tables(c);
-        c->spec.twx = tx;
-        c->spec.twy = ty;
-    }
+    int R = 2, C = 2;
+    int rc0 = spectral_plan(c, &R, &C);
+    if (rc0) return rc0;
+    int rc = ensure_twiddles(c);
+    if (rc) return rc;
     SpecArgs<T> a;
     for (int i = 0; i < 6; ++i) a.tau[i] = (const T*)tau[i];
     for (int i = 0; i < 3; ++i) a.div[i] = (T*)div[i];
@@ -384,6 +279,43 @@ int spectral_t(ibm_ctx* c, const void* const tau[6], void* const ustar[3],
 }
 
 }  // namespace
+
+int ensure_twiddles(ibm_ctx* c) {
+    if (c->spec.twx && c->spec.twy) return IBM_OK;
+    void *tx = nullptr, *ty = nullptr;
+    int rc = c->dtype == IBM_F64 ? twiddles<double>(c, c->g.nx, &tx) : twiddles<float>(c, c->g.nx, &tx);
+    if (!rc)
+        rc = c->dtype == IBM_F64 ? twiddles<double>(c, c->g.ny, &ty) : twiddles<float>(c, c->g.ny, &ty);
+    if (rc) {
+        (void)hipFree(tx);
+        (void)hipFree(ty);
+        return rc;
+    }
+    free_spectral_tables(c);
+    c->spec.twx = tx;
+    c->spec.twy = ty;
+    return IBM_OK;
+}
+
+int spectral_plan(const ibm_ctx* c, int* rows_per, int* cols) {
+    const int nx = c->g.nx, ny = c->g.ny;
+    const size_t cs = c->dtype == IBM_F64 ? 16 : 8;
+    if (ilog2_exact(nx) < 0 || ilog2_exact(ny) < 0)
+        return fail(IBM_E_UNSUPPORTED, "spectral transforms: nx and ny must be powers of two (%d, %d)",
+                    nx, ny);
+    auto fits = [&](int seqs, int n) { return ((size_t)seqs * n + n / 2) * cs <= lds_limit(); };
+    int R = 8;
+    while (R > 2 && !fits(R + R / 2, nx)) R /= 2;
+    if (!fits(R + R / 2, nx))
+        return fail(IBM_E_UNSUPPORTED, "spectral transforms: nx = %d too long for one block's LDS", nx);
+    int C = 64;
+    while (C > 2 && !fits(C + C / 2, ny)) C /= 2;
+    if (!fits(C + C / 2, ny))
+        return fail(IBM_E_UNSUPPORTED, "spectral transforms: ny = %d too long for one block's LDS", ny);
+    *rows_per = R;
+    *cols = std::min(C, std::max(2, nx));
+    return IBM_OK;
+}
 
 long spectral_slots(const ibm_ctx* c) {
     return 3 * ((c->n + 256L * kZItems - 1) / (256L * kZItems));

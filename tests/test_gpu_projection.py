@@ -1,0 +1,158 @@
+"""GPU parity of the AB2 update and the pressure projection
+(ibm_ab2_predict, ibm_pressure_project) against the oracle.
+
+* small grids (float64 and float32): u, v, w after the projection and the
+  pressure, normwise per field <= 1e-12 (float64) and 2e-5 (float32);
+* with w = 0 on the bottom plane the projected field is discretely
+  divergence-free (the oracle's D applied to the GPU's output);
+* output in place of the input;
+* the 512 x 256 x 256 hill in float32: the divergence of the projected
+  field, and the pressure's spectrum at sampled horizontal modes against
+  the oracle's dense solve of those modes' systems (normwise over the
+  sampled modes: float32 rounding of the transforms scales with the whole
+  field, not with one high mode's small amplitude);
+* AB2 against its formula; error paths.
+"""
+import numpy as np
+import pytest
+
+from _gpu import TOL, normwise, torch_dev
+from workloads import Grid
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _fields(g, seed, wall=True):
+    rng = np.random.default_rng(seed)
+    u, v, w = rng.standard_normal((3,) + g.shape)
+    if wall:
+        w[0] = 0.0
+    return [u, v, w]
+
+
+def _project(g, vel, dt, dtype, in_place=False):
+    import torch
+    import paper_2006_03343_amd as ibm
+    _, dev = torch_dev()
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    ctx = ibm.Context(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, dtype=tdt, device=dev)
+    us = [torch.from_numpy(np.ascontiguousarray(a)).to(dev, tdt) for a in vel]
+    out = us if in_place else [torch.empty_like(a) for a in us]
+    p = torch.empty_like(us[0])
+    ctx.pressure_project(us, dt, out, p)
+    torch.cuda.synchronize()
+    return [a.cpu().numpy().astype(np.float64) for a in out], p.cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("shape,sp,dtype", [((8, 8, 6), (1.0, 1.0, 1.0), "f64"),
+                                            ((16, 8, 9), (0.7, 1.3, 0.9), "f64"),
+                                            ((32, 16, 12), (1.0, 1.0, 1.0), "f32"),
+                                            ((4, 2, 1), (1.0, 1.0, 1.0), "f64"),
+                                            ((1, 8, 5), (1.0, 1.0, 1.0), "f64")])
+def test_projection_matches_oracle(ora, shape, sp, dtype):
+    g = Grid(*shape, *sp)
+    vel = _fields(g, sum(shape), wall=False)
+    if dtype == "f32":
+        vel = [a.astype(np.float32).astype(np.float64) for a in vel]
+    dt = 0.017
+    _say(f"projection {shape} {dtype}")
+    out, p = _project(g, vel, dt, dtype)
+    ru, rv, rw, rp = ora.pressure_project(g, vel, dt)
+    errs = [normwise(a, b) for a, b in zip(out + [p], [ru, rv, rw, rp])]
+    _say(f"errors u v w p {errs}")
+    assert max(errs) <= TOL[dtype], errs
+
+
+@pytest.mark.parametrize("dtype,bar", [("f64", 1e-10), ("f32", 2e-5)])
+def test_divergence_free_and_in_place(ora, dtype, bar):
+    g = Grid(64, 32, 24, 1.0, 1.0, 0.8)
+    vel = _fields(g, 7)
+    if dtype == "f32":
+        vel = [a.astype(np.float32).astype(np.float64) for a in vel]
+    _say(f"projection 64x32x24 {dtype}: divergence after, in place")
+    out, p = _project(g, vel, 0.01, dtype, in_place=True)
+    d0 = np.abs(ora.divergence_velocity(g, *vel)).max()
+    d1 = np.abs(ora.divergence_velocity(g, *out)).max()
+    _say(f"max |D u| before {d0:.3e}, after {d1:.3e}")
+    assert d1 <= bar * d0
+    np.testing.assert_array_equal(out[2][0], vel[2][0])     # no correction on the bottom w node
+
+
+def test_hill_size_sampled_modes(ora):
+    g = Grid(512, 256, 256)
+    vel = [a.astype(np.float32).astype(np.float64) for a in _fields(g, 11)]
+    dt = 0.01
+    _say("projection 512x256x256 f32: divergence and sampled modes of p")
+    out, p = _project(g, vel, dt, "f32")
+    d0 = np.abs(ora.divergence_velocity(g, *vel)).max()
+    d1 = np.abs(ora.divergence_velocity(g, *out)).max()
+    _say(f"max |D u| before {d0:.3e}, after {d1:.3e}")
+    assert d1 <= 2e-5 * d0
+    # pressure spectrum at sampled modes vs dense solves of their systems
+    rhs = 2.0 / (3.0 * dt) * ora.divergence_velocity(g, *vel)
+    rh = np.fft.fft2(rhs, axes=(1, 2))
+    ph = np.fft.fft2(p, axes=(1, 2))
+    kx = 2 * np.pi * np.fft.fftfreq(g.nx, d=1.0 / g.nx) / g.lx
+    ky = 2 * np.pi * np.fft.fftfreq(g.ny, d=1.0 / g.ny) / g.ly
+    kx[g.nx // 2] = 0.0
+    ky[g.ny // 2] = 0.0
+    rng = np.random.default_rng(12)
+    modes = [(0, 0), (g.nx // 2, 0), (1, 0), (0, 1), (3, 7), (g.nx - 5, g.ny // 2 + 3)]
+    modes += [(int(rng.integers(g.nx)), int(rng.integers(g.ny))) for _ in range(10)]
+    c = 1.0 / g.dz ** 2
+    num = den = 0.0
+    for i, j in modes:
+        K2 = kx[i] ** 2 + ky[j] ** 2
+        A = np.diag(np.full(g.nz - 1, c), 1) + np.diag(np.full(g.nz - 1, c), -1)
+        A -= np.diag(A.sum(axis=1) + K2)
+        b = rh[:, j, i].copy()
+        if K2 == 0.0:
+            A[0, :] = 0.0
+            A[0, 0] = 1.0
+            b[0] = 0.0
+        ref = np.linalg.solve(A, b)
+        num = max(num, np.abs(ph[:, j, i] - ref).max())
+        den = max(den, np.abs(ref).max())
+    # normwise over the sampled modes, as for every other output
+    _say(f"sampled modes: normwise error {num / den:.2e}")
+    assert num <= 2e-5 * den
+
+
+def test_ab2(ora):
+    import torch
+    import paper_2006_03343_amd as ibm
+    _, dev = torch_dev()
+    g = Grid(20, 12, 7)
+    rng = np.random.default_rng(5)
+    u, rn, rp = ([rng.standard_normal(g.shape) for _ in range(3)] for _ in range(3))
+    ctx = ibm.Context(g.nx, g.ny, g.nz, dtype=torch.float64, device=dev)
+    T = lambda a: torch.from_numpy(a).to(dev)
+    out = [torch.empty(g.shape, dtype=torch.float64, device=dev) for _ in range(3)]
+    ctx.ab2_predict([T(a) for a in u], [T(a) for a in rn], [T(a) for a in rp], 0.03, out)
+    ref = ora.ab2_predict(u, rn, rp, 0.03)
+    for a, b in zip(out, ref):
+        assert normwise(a.cpu().numpy(), b) <= 1e-15
+
+
+def test_errors():
+    import torch
+    import paper_2006_03343_amd as ibm
+    from paper_2006_03343_amd import _lib
+    _, dev = torch_dev()
+    ctx = ibm.Context(12, 8, 4, dtype=torch.float64, device=dev)
+    f = [torch.zeros(4, 8, 12, dtype=torch.float64, device=dev) for _ in range(4)]
+    with pytest.raises(ibm.IbmError) as e:
+        ctx.pressure_project(f[:3], 0.01, f[:3], f[3])
+    assert e.value.code == _lib.IBM_E_UNSUPPORTED              # nx = 12
+    ctx = ibm.Context(16, 8, 4, dtype=torch.float64, device=dev)
+    f = [torch.zeros(4, 8, 16, dtype=torch.float64, device=dev) for _ in range(4)]
+    with pytest.raises(ibm.IbmError) as e:
+        ctx.pressure_project(f[:3], 0.0, f[:3], f[3])
+    assert e.value.code == _lib.IBM_E_RANGE
+    with pytest.raises(ibm.IbmError) as e:
+        ctx.pressure_project(f[:3], 0.01, f[:3], f[0])
+    assert e.value.code == _lib.IBM_E_ARG
