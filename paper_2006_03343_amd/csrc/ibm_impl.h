@@ -78,12 +78,14 @@ struct TileCfg {
 
 // Twiddle tables of the pseudo-spectral mode (built on first use).
 struct SpectralTw {
-    void* twx = nullptr;   // exp(-2 pi i t / nx), t < nx/2, storage-type complex
+    void* twx = nullptr;   // exp(-2 pi i t / nx), t < nx, storage-type complex
     void* twy = nullptr;
 };
 
 // Workspace of the pressure projection (allocated on first use): three
-// complex volumes and one real volume of the storage type.
+// half-spectrum complex volumes of the storage type (nz x ny x (nx/2 + 1)
+// modes, rows padded to an even count), plus one real double volume of the
+// same modes for double storage.
 struct ProjWs {
     void* buf = nullptr;
     size_t bytes = 0;
@@ -164,10 +166,11 @@ int launch_apply_spectral(ibm_ctx* c, const void* const tau[6], void* const usta
                           double* drag, hipStream_t s);
 long spectral_slots(const ibm_ctx* c);   // reduction slots (doubles) it needs
 int ensure_twiddles(ibm_ctx* c);          // twiddle tables of nx and ny (first use: synchronous)
-// Rows per x-transform block and columns per y-transform block (both even)
-// within one block's LDS; IBM_E_UNSUPPORTED unless nx, ny are powers of two
-// that fit.
-int spectral_plan(const ibm_ctx* c, int* rows_per, int* cols);
+// IBM_E_UNSUPPORTED unless nx and ny are powers of two that one block's
+// thread teams and LDS hold (float: <= 2048, double: <= 1024).
+int spectral_check(const ibm_ctx* c);
+// Dynamic LDS bytes of a 256-thread transform block for sequences of n.
+size_t spectral_lds_bytes(const ibm_ctx* c, int n);
 void free_spectral(ibm_ctx* c);
 
 // projection.hip

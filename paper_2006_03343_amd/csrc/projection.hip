@@ -17,12 +17,17 @@
 // projected field is then discretely divergence-free wherever the singular
 // modes are solvable (e.g. w = 0 on the bottom plane).
 //
-// Launches: forward x transforms of u*, v*, w* (real rows -> complex), forward
-// y transforms (complex columns, in place), one thread per horizontal mode
-// for the right-hand side, a Thomas sweep in z (in double) and the gradient spectra
-// i kx p_hat, i ky p_hat, p_hat (coalesced across modes), inverse y
-// transforms, inverse x transforms that apply the horizontal corrections to
-// u and v and return p, and the vertical correction of w.  Transforms: fft.h.
+// Real fields have Hermitian spectra along x, so only the modes 0 .. nx/2 are
+// kept (rows padded to an even length).  Launches (each over the three fields
+// at once where there are three): k_rows_fwd -- forward x transforms, two real
+// rows packed into one complex transform and separated through the team's
+// LDS; k_cols -- y transforms of pairs of half-spectrum columns, in place;
+// k_solve -- one thread per horizontal mode for the right-hand side, a Thomas
+// sweep in z (in double) and the gradient spectra i kx p_hat, i ky p_hat,
+// p_hat (coalesced across modes); k_cols inverse; k_rows_inv -- inverse x
+// transforms from the Hermitian extension, two rows per transform, applying
+// the horizontal corrections to u and v and returning p; k_wcorr -- the
+// vertical correction of w.  Transforms: fft.h.
 #include <algorithm>
 #include <cmath>
 
@@ -35,11 +40,17 @@ namespace {
 template <typename T>
 struct ProjArgs {
     int nx, ny, nz, logx, logy;
+    int nh, nhp;             // x modes kept (nx/2 + 1) and the padded row length (even)
     long rows;               // ny * nz
-    long plane;
-    int rows_per, cols;      // per transform block
+    long plane;              // nx * ny
+    long hplane;             // nhp * ny
     const Cx<T>* twx;
     const Cx<T>* twy;
+    const T* in[3];          // u*, v*, w*
+    Cx<T>* spec[3];          // their half spectra; after the solve i kx p, i ky p, p
+    const T* base[3];        // u*, v*, none
+    T scale[3];              // -3 dt / 2, -3 dt / 2, 1
+    T* out[3];               // u, v, p
     double kx, ky;           // 2 pi / Lx, 2 pi / Ly
     double dz;
     double f;                // 2 / (3 dt)
@@ -56,95 +67,173 @@ __global__ void __launch_bounds__(256) k_ab2(const T* __restrict__ u, const T* _
     out[q] = u[q] + dt * (T(1.5) * rn[q] - T(0.5) * rp[q]);
 }
 
-// Forward x transform of R real rows per block into complex rows (natural
-// order).
+// Forward x transforms: a team of P = max(1, nx / 8) consecutive threads per
+// pair of rows (r, r+1) of field blockIdx.y transforms Z = f_r + i f_{r+1};
+// F_r = (Z_m + conj Z_{-m}) / 2 and F_{r+1} = (Z_m - conj Z_{-m}) / (2 i) for
+// the modes m <= nx / 2.
 template <typename T>
-__global__ void __launch_bounds__(256) k_rows_fwd(ProjArgs<T> a, const T* __restrict__ f,
-                                                  Cx<T>* __restrict__ out) {
+__global__ void __launch_bounds__(256) k_rows_fwd(ProjArgs<T> a) {
     extern __shared__ unsigned char lds_raw[];
-    Cx<T>* x = reinterpret_cast<Cx<T>*>(lds_raw);
-    const int n = a.nx, logn = a.logx, R = a.rows_per;
-    Cx<T>* tw = x + R * n;
+    Cx<T>* xl = reinterpret_cast<Cx<T>*>(lds_raw);
+    const int n = a.nx, logn = a.logx;
+    const int P = n >= 8 ? n >> 3 : 1, ns = n >= 8 ? 8 : n;
+    const int teams = (int)blockDim.x / P;
+    Cx<T>* tw = xl + team_lds_elems(blockDim.x);
     stage_twiddles(tw, a.twx, n);
-    const long r0 = (long)R * blockIdx.x;
-    for (int e = threadIdx.x; e < R * n; e += blockDim.x) {
-        const int r = e >> logn, i = e & (n - 1);
-        const bool in = r0 + r < a.rows;
-        x[(r << logn) + bitrev((unsigned)i, logn)] =
-            Cx<T>{in ? f[(r0 + r) * n + i] : T(0), T(0)};
+    const int team = (int)threadIdx.x / P;
+    const Team tm = make_team(logn, (int)threadIdx.x - team * P, team, teams, false);
+    const long r0 = 2 * ((long)blockIdx.x * teams + team);
+    const bool in0 = r0 < a.rows, in1 = r0 + 1 < a.rows;
+    const T* __restrict__ f = a.in[blockIdx.y];
+    Cx<T>* __restrict__ out = a.spec[blockIdx.y];
+    Cx<T> v[1][8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        v[0][u] = Cx<T>{T(0), T(0)};
+        if (u >= ns) continue;
+        const long o = r0 * n + tm.elem(u);
+        v[0][u] = Cx<T>{in0 ? f[o] : T(0), in1 ? f[o + n] : T(0)};
     }
+    __syncthreads();   // twiddles staged
+    team_fft<T, 1>(v, tm, xl, tw);
     __syncthreads();
-    fft_dit(x, R, logn, tw);
-    for (int e = threadIdx.x; e < R * n; e += blockDim.x) {
-        const int r = e >> logn, i = e & (n - 1);
-        if (r0 + r < a.rows) out[(r0 + r) * n + i] = x[e];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+        if (u < ns) xl[tm.lds(tm.elem(u))] = v[0][u];
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int e = tm.elem(u);
+        if (u >= ns || 2 * e > n) continue;
+        const Cx<T> z = v[0][u], zc = xl[tm.lds((n - e) & (n - 1))];
+        const T h = T(0.5);
+        if (in0) out[r0 * a.nhp + e] = Cx<T>{h * (z.re + zc.re), h * (z.im - zc.im)};
+        if (in1) out[(r0 + 1) * a.nhp + e] = Cx<T>{h * (z.im + zc.im), h * (zc.re - z.re)};
     }
 }
 
-// Inverse x transform of R complex rows per block (natural order); the real
-// result, times ``scale``, is added to ``base`` (or stored if base is null).
+// Inverse x transforms of field blockIdx.y: a team per pair of rows builds
+// Z_e = A_e + i B_e over all e from the half spectra (A_e = conj A_{n-e}
+// above nx / 2; the imaginary parts of modes 0 and nx / 2 are dropped, as a
+// real inverse does), inverts it, and stores base + scale * Re / nx for row
+// r and base + scale * Im / nx for row r+1.
 template <typename T>
-__global__ void __launch_bounds__(256) k_rows_inv(ProjArgs<T> a, const Cx<T>* __restrict__ in,
-                                                  const T* base, T scale, T* out) {
+__global__ void __launch_bounds__(256) k_rows_inv(ProjArgs<T> a) {
     extern __shared__ unsigned char lds_raw[];
-    Cx<T>* x = reinterpret_cast<Cx<T>*>(lds_raw);
-    const int n = a.nx, logn = a.logx, R = a.rows_per;
-    Cx<T>* tw = x + R * n;
+    Cx<T>* xl = reinterpret_cast<Cx<T>*>(lds_raw);
+    const int n = a.nx, logn = a.logx;
+    const int P = n >= 8 ? n >> 3 : 1, ns = n >= 8 ? 8 : n;
+    const int teams = (int)blockDim.x / P;
+    Cx<T>* tw = xl + team_lds_elems(blockDim.x);
     stage_twiddles(tw, a.twx, n);
-    const long r0 = (long)R * blockIdx.x;
-    for (int e = threadIdx.x; e < R * n; e += blockDim.x) {
-        const int r = e >> logn;
-        const Cx<T> v = r0 + r < a.rows ? in[r0 * n + e] : Cx<T>{T(0), T(0)};
-        x[e] = Cx<T>{v.re, -v.im};                         // conj
+    const int team = (int)threadIdx.x / P;
+    const Team tm = make_team(logn, (int)threadIdx.x - team * P, team, teams, false);
+    const long r0 = 2 * ((long)blockIdx.x * teams + team);
+    const bool in0 = r0 < a.rows, in1 = r0 + 1 < a.rows;
+    const Cx<T>* __restrict__ A = a.spec[blockIdx.y];
+    Cx<T> v[1][8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        v[0][u] = Cx<T>{T(0), T(0)};
+        if (u >= ns) continue;
+        const int e = tm.elem(u);
+        const bool upper = 2 * e > n;
+        const int m = upper ? n - e : e;
+        Cx<T> za = in0 ? A[r0 * a.nhp + m] : Cx<T>{T(0), T(0)};
+        Cx<T> zb = in1 ? A[(r0 + 1) * a.nhp + m] : Cx<T>{T(0), T(0)};
+        if (m == 0 || 2 * m == n) {
+            za.im = T(0);
+            zb.im = T(0);
+        }
+        if (upper) {
+            za.im = -za.im;
+            zb.im = -zb.im;
+        }
+        v[0][u] = Cx<T>{za.re - zb.im, za.im + zb.re};
     }
-    __syncthreads();
-    fft_dif(x, R, logn, tw);
-    const T s = scale / T(n);
-    for (int e = threadIdx.x; e < R * n; e += blockDim.x) {
-        const int r = e >> logn, i = e & (n - 1);
-        if (r0 + r >= a.rows) continue;
-        const long o = (r0 + r) * n + i;
-        // inverse = conj(FFT(conj X)) / n; its real part is the bit-reversed
-        // output's real part
-        const T v = x[(r << logn) + bitrev((unsigned)i, logn)].re * s;
-        out[o] = base ? base[o] + v : v;
+    __syncthreads();   // twiddles staged
+    team_ifft<T, 1>(v, tm, xl, tw);
+    const T s = a.scale[blockIdx.y] / T(n);
+    const T* base = a.base[blockIdx.y];
+    T* out = a.out[blockIdx.y];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        if (u >= ns) continue;
+        const long o = r0 * n + tm.elem(u);
+        const T va = v[0][u].re * s, vb = v[0][u].im * s;
+        if (in0) out[o] = base ? base[o] + va : va;
+        if (in1) out[o + n] = base ? base[o + n] + vb : vb;
     }
 }
 
-// y transform in place of C complex columns of one plane per block; inverse
-// includes the 1/ny factor.
+// y transforms in place of field blockIdx.y's half spectrum: a team per pair
+// of adjacent columns of one plane, teams interleaved across lanes (lane =
+// j * teams + team) so a row's columns are read together; the inverse
+// includes 1 / ny.
 template <typename T>
-__global__ void __launch_bounds__(256) k_cols(ProjArgs<T> a, Cx<T>* __restrict__ data,
-                                              int inverse) {
+struct alignas(2 * sizeof(Cx<T>)) CxPair {
+    Cx<T> a, b;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_cols(ProjArgs<T> a, int inverse) {
     extern __shared__ unsigned char lds_raw[];
-    Cx<T>* x = reinterpret_cast<Cx<T>*>(lds_raw);
-    const int n = a.ny, logn = a.logy, C = a.cols;
-    Cx<T>* tw = x + C * n;
+    Cx<T>* xl = reinterpret_cast<Cx<T>*>(lds_raw);
+    const int n = a.ny, logn = a.logy;
+    const int P = n >= 8 ? n >> 3 : 1, ns = n >= 8 ? 8 : n;
+    const int teams = (int)blockDim.x / P;
+    Cx<T>* tw = xl + team_lds_elems(blockDim.x);
     stage_twiddles(tw, a.twy, n);
-    const int groups = (a.nx + C - 1) / C;
-    const int k = blockIdx.x / groups;
-    const int x0 = (blockIdx.x - k * groups) * C;
-    const long pk = (long)k * a.plane;
-    for (int e = threadIdx.x; e < C * n; e += blockDim.x) {
-        const int c = e % C, j = e / C;
-        const bool in = x0 + c < a.nx;
-        const Cx<T> v = in ? data[pk + (long)j * a.nx + x0 + c] : Cx<T>{T(0), T(0)};
-        if (inverse) x[c * n + j] = Cx<T>{v.re, -v.im};
-        else x[c * n + bitrev((unsigned)j, logn)] = v;
-    }
-    __syncthreads();
-    if (inverse) fft_dif(x, C, logn, tw);
-    else fft_dit(x, C, logn, tw);
-    const T s = T(1) / T(n);
-    for (int e = threadIdx.x; e < C * n; e += blockDim.x) {
-        const int c = e % C, j = e / C;
-        if (x0 + c >= a.nx) continue;
-        Cx<T>& d = data[pk + (long)j * a.nx + x0 + c];
-        if (inverse) {
-            const Cx<T> v = x[c * n + bitrev((unsigned)j, logn)];
-            d = Cx<T>{v.re * s, -v.im * s};
-        } else {
-            d = x[c * n + j];
+    const int cpairs = a.nhp / 2;
+    const int groups = (cpairs + teams - 1) / teams;
+    const int k = (int)blockIdx.x / groups;
+    const int g = (int)blockIdx.x - k * groups;
+    const int team = (int)threadIdx.x % teams;
+    const Team tm = make_team(logn, (int)threadIdx.x / teams, team, teams, true);
+    const int cp = g * teams + team;
+    const bool act = cp < cpairs;
+    const T s = inverse ? T(1) / T(n) : T(1);
+    if constexpr (sizeof(T) == 4) {
+        // both columns at once, one 16-byte access per row
+        CxPair<T>* d = reinterpret_cast<CxPair<T>*>(a.spec[blockIdx.y] + (long)k * a.hplane + 2 * cp);
+        const int rs = a.nhp / 2;                  // row stride in pairs
+        Cx<T> v[2][8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            v[0][u] = v[1][u] = Cx<T>{T(0), T(0)};
+            if (u >= ns || !act) continue;
+            const CxPair<T> p = d[(long)tm.elem(u) * rs];
+            v[0][u] = p.a;
+            v[1][u] = p.b;
+        }
+        __syncthreads();   // twiddles staged
+        if (inverse) team_ifft<T, 2>(v, tm, xl, tw);
+        else team_fft<T, 2>(v, tm, xl, tw);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (u >= ns || !act) continue;
+            d[(long)tm.elem(u) * rs] = CxPair<T>{Cx<T>{v[0][u].re * s, v[0][u].im * s},
+                                                 Cx<T>{v[1][u].re * s, v[1][u].im * s}};
+        }
+    } else {
+        // one column after the other (two would spill registers)
+        Cx<T>* d = a.spec[blockIdx.y] + (long)k * a.hplane + 2 * cp;
+        for (int h = 0; h < 2; ++h) {
+            Cx<T> v[1][8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                v[0][u] = Cx<T>{T(0), T(0)};
+                if (u >= ns || !act) continue;
+                v[0][u] = d[(long)tm.elem(u) * a.nhp + h];
+            }
+            __syncthreads();
+            if (inverse) team_ifft<T, 1>(v, tm, xl, tw);
+            else team_fft<T, 1>(v, tm, xl, tw);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (u >= ns || !act) continue;
+                d[(long)tm.elem(u) * a.nhp + h] = Cx<T>{v[0][u].re * s, v[0][u].im * s};
+            }
         }
     }
 }
@@ -163,8 +252,9 @@ __global__ void __launch_bounds__(256) k_solve(ProjArgs<T> a, Cx<T>* __restrict_
                                                double* __restrict__ cp) {
     constexpr bool narrow = sizeof(T) == 4;
     const long mode = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (mode >= a.plane) return;
-    const int i = (int)(mode % a.nx), j = (int)(mode / a.nx);
+    if (mode >= a.hplane) return;
+    const int i = (int)(mode % a.nhp), j = (int)(mode / a.nhp);
+    if (i >= a.nh) return;
     auto wavenumber = [](int m, int n, double k0) {
         if (n > 1 && 2 * m == n) return 0.0;                // Nyquist
         return k0 * (double)(2 * m < n ? m : m - n);
@@ -182,9 +272,9 @@ __global__ void __launch_bounds__(256) k_solve(ProjArgs<T> a, Cx<T>* __restrict_
     Cx<double> dprev{0.0, 0.0};
     double cprev = 0.0;
     for (int k = 0; k < nz; ++k) {
-        const long q = (long)k * a.plane + mode;
+        const long q = (long)k * a.hplane + mode;
         const Cx<T> u = U[q], v = V[q], w = W[q];
-        const Cx<T> wu = k + 1 < nz ? W[q + a.plane] : Cx<T>{T(0), T(0)};
+        const Cx<T> wu = k + 1 < nz ? W[q + a.hplane] : Cx<T>{T(0), T(0)};
         // i kx u + i ky v + (w[k+1] - w[k]) / dz
         Cx<double> r{-(kx * (double)u.im) - ky * (double)v.im + ((double)wu.re - (double)w.re) * invdz,
                      kx * (double)u.re + ky * (double)v.re + ((double)wu.im - (double)w.im) * invdz};
@@ -214,7 +304,7 @@ __global__ void __launch_bounds__(256) k_solve(ProjArgs<T> a, Cx<T>* __restrict_
     // back substitution and the gradient spectra
     Cx<double> pnext{0.0, 0.0};
     for (int k = nz - 1; k >= 0; --k) {
-        const long q = (long)k * a.plane + mode;
+        const long q = (long)k * a.hplane + mode;
         Cx<double> d;
         double cc;
         if constexpr (narrow) {
@@ -247,22 +337,9 @@ inline unsigned nb256(long n) { return (unsigned)((n + 255) / 256); }
 template <typename T>
 int project_t(ibm_ctx* c, const void* const ustar[3], double dt, void* const uo[3], void* p_out,
               hipStream_t s) {
-    int R = 2, C = 2;
-    int rc = spectral_plan(c, &R, &C);
+    int rc = spectral_check(c);
     if (rc) return rc;
     if ((rc = ensure_twiddles(c))) return rc;
-    const long n = c->n;
-    if (!c->proj.buf) {
-        // float storage keeps the sweep's doubles in the three spectra
-        const size_t cb = sizeof(Cx<T>) * (size_t)n;
-        const size_t rb = sizeof(T) == 8 ? sizeof(double) * (size_t)n : 0;
-        IBM_HIP(hipMalloc(&c->proj.buf, 3 * cb + rb));
-        c->proj.bytes = 3 * cb + rb;
-    }
-    Cx<T>* U = (Cx<T>*)c->proj.buf;
-    Cx<T>* V = U + n;
-    Cx<T>* W = V + n;
-    double* cp = sizeof(T) == 8 ? (double*)(W + n) : nullptr;
     ProjArgs<T> a;
     a.nx = c->g.nx;
     a.ny = c->g.ny;
@@ -271,10 +348,23 @@ int project_t(ibm_ctx* c, const void* const ustar[3], double dt, void* const uo[
     while ((1 << a.logx) < a.nx) ++a.logx;
     a.logy = 0;
     while ((1 << a.logy) < a.ny) ++a.logy;
+    a.nh = a.nx / 2 + 1;
+    a.nhp = (a.nh + 1) & ~1;
     a.rows = (long)a.ny * a.nz;
     a.plane = (long)a.nx * a.ny;
-    a.rows_per = R;
-    a.cols = C;
+    a.hplane = (long)a.nhp * a.ny;
+    const long nspec = a.hplane * a.nz;
+    if (!c->proj.buf) {
+        // float storage keeps the sweep's doubles in the three spectra
+        const size_t cb = sizeof(Cx<T>) * (size_t)nspec;
+        const size_t rb = sizeof(T) == 8 ? sizeof(double) * (size_t)nspec : 0;
+        IBM_HIP(hipMalloc(&c->proj.buf, 3 * cb + rb));
+        c->proj.bytes = 3 * cb + rb;
+    }
+    Cx<T>* U = (Cx<T>*)c->proj.buf;
+    Cx<T>* V = U + nspec;
+    Cx<T>* W = V + nspec;
+    double* cp = sizeof(T) == 8 ? (double*)(W + nspec) : nullptr;
     a.twx = (const Cx<T>*)c->spec.twx;
     a.twy = (const Cx<T>*)c->spec.twy;
     a.kx = 2.0 * M_PI / (a.nx * c->g.dx);
@@ -283,26 +373,31 @@ int project_t(ibm_ctx* c, const void* const ustar[3], double dt, void* const uo[
     a.f = 2.0 / (3.0 * dt);
     a.c = (T)(1.5 * dt);
     a.dzs = (T)c->g.dz;
-    const size_t lx = ((size_t)R * a.nx + a.nx / 2) * sizeof(Cx<T>);
-    const size_t ly = ((size_t)C * a.ny + a.ny / 2) * sizeof(Cx<T>);
-    const unsigned gx = (unsigned)((a.rows + R - 1) / R);
-    const unsigned gy = (unsigned)(((a.nx + C - 1) / C) * a.nz);
     Cx<T>* spec[3] = {U, V, W};
     for (int i = 0; i < 3; ++i) {
-        hipLaunchKernelGGL(k_rows_fwd<T>, dim3(gx), dim3(256), lx, s, a, (const T*)ustar[i], spec[i]);
-        hipLaunchKernelGGL(k_cols<T>, dim3(gy), dim3(256), ly, s, a, spec[i], 0);
+        a.in[i] = (const T*)ustar[i];
+        a.spec[i] = spec[i];
     }
-    hipLaunchKernelGGL(k_solve<T>, dim3(nb256(a.plane)), dim3(256), 0, s, a, U, V, W, cp);
-    for (int i = 0; i < 3; ++i)
-        hipLaunchKernelGGL(k_cols<T>, dim3(gy), dim3(256), ly, s, a, spec[i], 1);
-    // u = u* - c d/dx p, v = v* - c d/dy p, then p itself
-    hipLaunchKernelGGL(k_rows_inv<T>, dim3(gx), dim3(256), lx, s, a, (const Cx<T>*)U,
-                       (const T*)ustar[0], -a.c, (T*)uo[0]);
-    hipLaunchKernelGGL(k_rows_inv<T>, dim3(gx), dim3(256), lx, s, a, (const Cx<T>*)V,
-                       (const T*)ustar[1], -a.c, (T*)uo[1]);
-    hipLaunchKernelGGL(k_rows_inv<T>, dim3(gx), dim3(256), lx, s, a, (const Cx<T>*)W,
-                       (const T*)nullptr, T(1), (T*)p_out);
-    hipLaunchKernelGGL(k_wcorr<T>, dim3(nb256(n)), dim3(256), 0, s, a, (const T*)ustar[2],
+    a.base[0] = (const T*)ustar[0];
+    a.base[1] = (const T*)ustar[1];
+    a.base[2] = nullptr;
+    a.scale[0] = a.scale[1] = -a.c;
+    a.scale[2] = T(1);
+    a.out[0] = (T*)uo[0];
+    a.out[1] = (T*)uo[1];
+    a.out[2] = (T*)p_out;
+    const int tx = 256 / (a.nx >= 8 ? a.nx / 8 : 1);     // teams per block
+    const int ty = 256 / (a.ny >= 8 ? a.ny / 8 : 1);
+    const unsigned gx = (unsigned)(((a.rows + 1) / 2 + tx - 1) / tx);
+    const unsigned gy = (unsigned)(((a.nhp / 2 + ty - 1) / ty) * a.nz);
+    const size_t lx = spectral_lds_bytes(c, a.nx), ly = spectral_lds_bytes(c, a.ny);
+    hipLaunchKernelGGL(k_rows_fwd<T>, dim3(gx, 3), dim3(256), lx, s, a);
+    hipLaunchKernelGGL(k_cols<T>, dim3(gy, 3), dim3(256), ly, s, a, 0);
+    hipLaunchKernelGGL(k_solve<T>, dim3(nb256(a.hplane)), dim3(256), 0, s, a, U, V, W, cp);
+    hipLaunchKernelGGL(k_cols<T>, dim3(gy, 3), dim3(256), ly, s, a, 1);
+    // u = u* - c d/dx p, v = v* - c d/dy p, and p itself
+    hipLaunchKernelGGL(k_rows_inv<T>, dim3(gx, 3), dim3(256), lx, s, a);
+    hipLaunchKernelGGL(k_wcorr<T>, dim3(nb256(c->n)), dim3(256), 0, s, a, (const T*)ustar[2],
                        (const T*)p_out, (T*)uo[2]);
     IBM_HIP(hipGetLastError());
     return IBM_OK;

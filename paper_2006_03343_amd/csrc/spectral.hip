@@ -5,26 +5,23 @@
 //   vertical staggered differences (eqs. dudz, dwdz), the forcing (eq.
 //   u-*-IBM) and the drag are those of the dense pass.
 //
-// Three launches, each HBM bound:
-//   k_dx   one block per R rows (up to 8, as LDS allows): complex FFTs of
-//          length nx in LDS on tau_xx + i tau_xy of each row and tau_xz of
-//          two rows packed into one sequence (the derivative is a real operator, so the real and
-//          imaginary parts stay separate); multiply by i k / nx with the
-//          Nyquist mode dropped (explicitly: with two fields packed its term
-//          would leak into the other field); inverse transform; write
-//          div_x = d/dx tau_xx, div_y = d/dx tau_xy, div_z = d/dx tau_xz;
-//   k_dy   one block per C consecutive columns of one plane: the same along
-//          y on tau_xy + i tau_yy and on tau_yz of two columns, adding
-//          d/dy tau_xy, d/dy tau_yy, d/dy tau_yz;
+// Three launches:
+//   k_dx   a thread team per pair of rows (r, r+1) holds three complex
+//          sequences in registers: tau_xx + i tau_xy of each row and
+//          tau_xz of row r + i tau_xz of row r+1 (the derivative is a real
+//          operator, so the real and imaginary parts stay apart); forward
+//          transform, product with i k / nx with the Nyquist mode dropped
+//          (explicitly: with two fields packed its term would leak into the
+//          other field), inverse transform; writes div_x = d/dx tau_xx,
+//          div_y = d/dx tau_xy, div_z = d/dx tau_xz;
+//   k_dy   the same along y, a team per pair of columns of one plane, on
+//          tau_xy + i tau_yy and tau_yz, adding d/dy tau_xy, d/dy tau_yy,
+//          d/dy tau_yz;
 //   k_spec_z  adds the staggered vertical differences, leaves per-block drag
 //          partials (finalized in slot order), and forces the forcing
 //          segments in the blocks after the dense ones.
-// Transform: iterative radix-2; the forward one is decimation in time on
-// bit-reversed input (natural-order output), the inverse one decimation in
-// frequency on natural-order input computed as conj(FFT(conj X)), so its
-// output is read back at bit-reversed positions and no permutation pass is
-// needed.  Twiddles exp(-2 pi i t / N), t < N/2, come from a table computed
-// in double on the host and staged into LDS by each block.
+// Transforms: fft.h (register-resident Stockham passes of radix 8, thread
+// teams of n / 8).
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -43,94 +40,148 @@ struct SpecArgs {
     const Cx<T>* twy;
     int nx, ny, nz, logx, logy;
     long rows;               // ny * nz
-    int cols;                // columns per k_dy block (even)
-    int rows_per;            // rows per k_dx block (even)
     T kx, ky;                // 2 pi / Lx, 2 pi / Ly
 };
 
-// R rows per block (R even): sequence r = tau_xx + i tau_xy of row r0 + r,
-// sequence R + r/2 = tau_xz of rows r0 + r (real part, r even) and r0 + r + 1
-// (imaginary part); the twiddle table follows the sequences in LDS.
-template <typename T>
-__global__ void __launch_bounds__(256) k_dx(SpecArgs<T> a) {
-    extern __shared__ unsigned char lds_raw[];
-    Cx<T>* x = reinterpret_cast<Cx<T>*>(lds_raw);
-    const int n = a.nx, logn = a.logx, R = a.rows_per;
-    const int ns = R + R / 2;
-    Cx<T>* tw = x + ns * n;
-    stage_twiddles(tw, a.twx, n);
-    const long r0 = (long)R * blockIdx.x;
-    for (int e = threadIdx.x; e < R * n; e += blockDim.x) {
-        const int r = e >> logn, i = e & (n - 1);
-        const bool in = r0 + r < a.rows;
-        const long o = (r0 + r) * n + i;
-        const unsigned p = bitrev((unsigned)i, logn);
-        x[(r << logn) + p] = in ? Cx<T>{a.tau[0][o], a.tau[3][o]} : Cx<T>{T(0), T(0)};
-        const T xz = in ? a.tau[4][o] : T(0);
-        Cx<T>& q = x[((R + r / 2) << logn) + p];
-        if (r & 1) q.im = xz;
-        else q.re = xz;
-    }
-    __syncthreads();
-    fft_dit(x, ns, logn, tw);
-    derivative_conj(x, ns, logn, a.kx);
-    fft_dif(x, ns, logn, tw);
-    // the derivative at i is conj(x[bitrev(i)]): real part x.re, imaginary -x.im
-    for (int e = threadIdx.x; e < R * n; e += blockDim.x) {
-        const int r = e >> logn, i = e & (n - 1);
-        if (r0 + r >= a.rows) continue;
-        const long o = (r0 + r) * n + i;
-        const unsigned p = bitrev((unsigned)i, logn);
-        const Cx<T> d = x[(r << logn) + p];
-        const Cx<T> dq = x[((R + r / 2) << logn) + p];
-        a.div[0][o] = d.re;
-        a.div[1][o] = -d.im;
-        a.div[2][o] = (r & 1) ? -dq.im : dq.re;
+// i k_m X_m / n for every slot (the Nyquist mode gets k = 0).
+template <typename T, int S>
+__device__ inline void derivative(Cx<T> (&v)[S][8], const Team& tm, int n, T two_pi_over_len) {
+    const T inv_n = T(1) / T(n);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const T k = two_pi_over_len * T(mode_number(tm.elem(u) & (n - 1), n)) * inv_n;
+#pragma unroll
+        for (int s = 0; s < S; ++s) v[s][u] = Cx<T>{-(k * v[s][u].im), k * v[s][u].re};
     }
 }
 
-// C columns (x0 .. x0+C-1) of plane k per block: sequences c = tau_xy + i
-// tau_yy of column c, and C + c/2 = tau_yz of columns c, c+1 (C even).
+// Sequences a team transforms at once: all three in float; one after another
+// in double, whose registers would spill otherwise.
+template <typename T>
+constexpr int kSeqAtOnce = sizeof(T) == 4 ? 3 : 1;
+
+// A team of P = max(1, nx / 8) consecutive threads per pair of rows (r, r+1);
+// sequence 0 = tau_xx + i tau_xy of row r, 1 = the same of row r+1, 2 =
+// tau_xz of row r + i tau_xz of row r+1.
+template <typename T>
+__global__ void __launch_bounds__(256) k_dx(SpecArgs<T> a) {
+    constexpr int G = kSeqAtOnce<T>;
+    extern __shared__ unsigned char lds_raw[];
+    Cx<T>* xl = reinterpret_cast<Cx<T>*>(lds_raw);
+    const int n = a.nx, logn = a.logx;
+    const int P = n >= 8 ? n >> 3 : 1, ns = n >= 8 ? 8 : n;
+    const int teams = (int)blockDim.x / P;
+    Cx<T>* tw = xl + team_lds_elems(blockDim.x);
+    stage_twiddles(tw, a.twx, n);
+    const int team = (int)threadIdx.x / P;
+    const Team tm = make_team(logn, (int)threadIdx.x - team * P, team, teams, false);
+    const long r0 = 2 * ((long)blockIdx.x * teams + team);
+    const bool in[2] = {r0 < a.rows, r0 + 1 < a.rows};
+    for (int s0 = 0; s0 < 3; s0 += G) {
+        Cx<T> v[G][8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const long o = r0 * n + tm.elem(u);
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int sq = s0 + g;
+                v[g][u] = Cx<T>{T(0), T(0)};
+                if (u >= ns) continue;
+                if (sq < 2) {
+                    if (in[sq]) v[g][u] = Cx<T>{a.tau[0][o + sq * n], a.tau[3][o + sq * n]};
+                } else {
+                    if (in[0]) v[g][u].re = a.tau[4][o];
+                    if (in[1]) v[g][u].im = a.tau[4][o + n];
+                }
+            }
+        }
+        __syncthreads();   // twiddles staged; the previous group's exchanges done
+        team_fft<T, G>(v, tm, xl, tw);
+        derivative<T, G>(v, tm, n, a.kx);
+        team_ifft<T, G>(v, tm, xl, tw);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (u >= ns) continue;
+            const long o = r0 * n + tm.elem(u);
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int sq = s0 + g;
+                if (sq < 2) {
+                    if (in[sq]) {
+                        a.div[0][o + sq * n] = v[g][u].re;
+                        a.div[1][o + sq * n] = v[g][u].im;
+                    }
+                } else {
+                    if (in[0]) a.div[2][o] = v[g][u].re;
+                    if (in[1]) a.div[2][o + n] = v[g][u].im;
+                }
+            }
+        }
+    }
+}
+
+// A team per pair of columns (c, c+1) of plane k; the teams of a block are
+// interleaved across lanes (lane = j * teams + team), so a row's columns are
+// read together.  Sequences: tau_xy + i tau_yy of column c, of column c+1,
+// and tau_yz of column c + i tau_yz of column c+1.
 template <typename T>
 __global__ void __launch_bounds__(256) k_dy(SpecArgs<T> a) {
+    constexpr int G = kSeqAtOnce<T>;
     extern __shared__ unsigned char lds_raw[];
-    Cx<T>* x = reinterpret_cast<Cx<T>*>(lds_raw);
-    const int n = a.ny, logn = a.logy, C = a.cols;
-    Cx<T>* tw = x + (C + C / 2) * n;
+    Cx<T>* xl = reinterpret_cast<Cx<T>*>(lds_raw);
+    const int n = a.ny, logn = a.logy;
+    const int P = n >= 8 ? n >> 3 : 1, ns = n >= 8 ? 8 : n;
+    const int teams = (int)blockDim.x / P;
+    Cx<T>* tw = xl + team_lds_elems(blockDim.x);
     stage_twiddles(tw, a.twy, n);
-    const int groups = (a.nx + C - 1) / C;
-    const int k = blockIdx.x / groups;
-    const int x0 = (blockIdx.x - k * groups) * C;
+    const int groups = (a.nx + 2 * teams - 1) / (2 * teams);
+    const int k = (int)blockIdx.x / groups;
+    const int gi = (int)blockIdx.x - k * groups;
+    const int team = (int)threadIdx.x % teams;
+    const Team tm = make_team(logn, (int)threadIdx.x / teams, team, teams, true);
+    const int c0 = 2 * (gi * teams + team);
+    const bool in[2] = {c0 < a.nx, c0 + 1 < a.nx};
     const long pk = (long)k * a.ny * a.nx;
-    // thread t: column t % C, rows t / C, t / C + 256 / C, ...  (coalesced in x)
-    for (int e = threadIdx.x; e < C * n; e += blockDim.x) {
-        const int c = e % C, j = e / C;
-        const int xx = x0 + c;
-        const bool in = xx < a.nx;
-        const long q = pk + (long)j * a.nx + (in ? xx : 0);
-        const unsigned p = bitrev((unsigned)j, logn);
-        x[c * n + p] = in ? Cx<T>{a.tau[3][q], a.tau[1][q]} : Cx<T>{T(0), T(0)};
-        const T yz = in ? a.tau[5][q] : T(0);
-        Cx<T>& s = x[(C + c / 2) * n + p];
-        if (c & 1) s.im = yz;
-        else s.re = yz;
-    }
-    __syncthreads();
-    const int ns = C + C / 2;
-    fft_dit(x, ns, logn, tw);
-    derivative_conj(x, ns, logn, a.ky);
-    fft_dif(x, ns, logn, tw);
-    for (int e = threadIdx.x; e < C * n; e += blockDim.x) {
-        const int c = e % C, j = e / C;
-        const int xx = x0 + c;
-        if (xx >= a.nx) continue;
-        const long q = pk + (long)j * a.nx + xx;
-        const unsigned p = bitrev((unsigned)j, logn);
-        const Cx<T> d = x[c * n + p];
-        const Cx<T> dz = x[(C + c / 2) * n + p];
-        a.div[0][q] += d.re;
-        a.div[1][q] += -d.im;
-        a.div[2][q] += (c & 1) ? -dz.im : dz.re;
+    for (int s0 = 0; s0 < 3; s0 += G) {
+        Cx<T> v[G][8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const long q = pk + (long)tm.elem(u) * a.nx + c0;
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int sq = s0 + g;
+                v[g][u] = Cx<T>{T(0), T(0)};
+                if (u >= ns) continue;
+                if (sq < 2) {
+                    if (in[sq]) v[g][u] = Cx<T>{a.tau[3][q + sq], a.tau[1][q + sq]};
+                } else {
+                    if (in[0]) v[g][u].re = a.tau[5][q];
+                    if (in[1]) v[g][u].im = a.tau[5][q + 1];
+                }
+            }
+        }
+        __syncthreads();
+        team_fft<T, G>(v, tm, xl, tw);
+        derivative<T, G>(v, tm, n, a.ky);
+        team_ifft<T, G>(v, tm, xl, tw);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (u >= ns) continue;
+            const long q = pk + (long)tm.elem(u) * a.nx + c0;
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int sq = s0 + g;
+                if (sq < 2) {
+                    if (in[sq]) {
+                        a.div[0][q + sq] += v[g][u].re;
+                        a.div[1][q + sq] += v[g][u].im;
+                    }
+                } else {
+                    if (in[0]) a.div[2][q] += v[g][u].re;
+                    if (in[1]) a.div[2][q + 1] += v[g][u].im;
+                }
+            }
+        }
     }
 }
 
@@ -214,12 +265,10 @@ int ilog2_exact(int n) {
     return (1 << l) == n ? l : -1;
 }
 
-size_t lds_limit() { return 64 * 1024; }   // dynamic LDS a block may take without an attribute
-
 template <typename T>
 int twiddles(ibm_ctx* c, int n, void** dst) {
-    std::vector<Cx<T>> t(std::max(1, n / 2));
-    for (int i = 0; i < n / 2; ++i) {
+    std::vector<Cx<T>> t(n);
+    for (int i = 0; i < n; ++i) {
         const double ang = -2.0 * M_PI * (double)i / (double)n;
         t[i] = Cx<T>{(T)std::cos(ang), (T)std::sin(ang)};
     }
@@ -234,12 +283,9 @@ int spectral_t(ibm_ctx* c, const void* const tau[6], void* const ustar[3],
                hipStream_t s) {
     const int nx = c->g.nx, ny = c->g.ny, nz = c->g.nz;
     const int lx = ilog2_exact(nx), ly = ilog2_exact(ny);
-    const size_t cs = sizeof(Cx<T>);
-    int R = 2, C = 2;
-    int rc0 = spectral_plan(c, &R, &C);
-    if (rc0) return rc0;
-    int rc = ensure_twiddles(c);
+    int rc = spectral_check(c);
     if (rc) return rc;
+    if ((rc = ensure_twiddles(c))) return rc;
     SpecArgs<T> a;
     for (int i = 0; i < 6; ++i) a.tau[i] = (const T*)tau[i];
     for (int i = 0; i < 3; ++i) a.div[i] = (T*)div[i];
@@ -251,15 +297,16 @@ int spectral_t(ibm_ctx* c, const void* const tau[6], void* const ustar[3],
     a.logx = lx;
     a.logy = ly;
     a.rows = (long)ny * nz;
-    a.cols = C;
-    a.rows_per = R;
     a.kx = (T)(2.0 * M_PI / (nx * c->g.dx));
     a.ky = (T)(2.0 * M_PI / (ny * c->g.dy));
-    hipLaunchKernelGGL(k_dx<T>, dim3((unsigned)((a.rows + R - 1) / R)), dim3(256),
-                       ((size_t)(R + R / 2) * nx + nx / 2) * cs, s, a);
-    const int groups = (nx + C - 1) / C;
+    const int tx = 256 / (nx >= 8 ? nx / 8 : 1);            // teams per block
+    const long pairs = (a.rows + 1) / 2;
+    hipLaunchKernelGGL(k_dx<T>, dim3((unsigned)((pairs + tx - 1) / tx)), dim3(256),
+                       spectral_lds_bytes(c, nx), s, a);
+    const int ty = 256 / (ny >= 8 ? ny / 8 : 1);
+    const int groups = (nx + 2 * ty - 1) / (2 * ty);
     hipLaunchKernelGGL(k_dy<T>, dim3((unsigned)(groups * nz)), dim3(256),
-                       ((size_t)(C + C / 2) * ny + ny / 2) * cs, s, a);
+                       spectral_lds_bytes(c, ny), s, a);
     ApplyArgs<T> z = make_apply_args<T>(c, c->cfg, tau, ustar, gradp, dt, div, drag);
     const long n = c->n;
     const int nzb = (int)((n + 256L * kZItems - 1) / (256L * kZItems));
@@ -297,24 +344,23 @@ int ensure_twiddles(ibm_ctx* c) {
     return IBM_OK;
 }
 
-int spectral_plan(const ibm_ctx* c, int* rows_per, int* cols) {
+int spectral_check(const ibm_ctx* c) {
     const int nx = c->g.nx, ny = c->g.ny;
-    const size_t cs = c->dtype == IBM_F64 ? 16 : 8;
     if (ilog2_exact(nx) < 0 || ilog2_exact(ny) < 0)
         return fail(IBM_E_UNSUPPORTED, "spectral transforms: nx and ny must be powers of two (%d, %d)",
                     nx, ny);
-    auto fits = [&](int seqs, int n) { return ((size_t)seqs * n + n / 2) * cs <= lds_limit(); };
-    int R = 8;
-    while (R > 2 && !fits(R + R / 2, nx)) R /= 2;
-    if (!fits(R + R / 2, nx))
-        return fail(IBM_E_UNSUPPORTED, "spectral transforms: nx = %d too long for one block's LDS", nx);
-    int C = 64;
-    while (C > 2 && !fits(C + C / 2, ny)) C /= 2;
-    if (!fits(C + C / 2, ny))
-        return fail(IBM_E_UNSUPPORTED, "spectral transforms: ny = %d too long for one block's LDS", ny);
-    *rows_per = R;
-    *cols = std::min(C, std::max(2, nx));
+    // a team of n / 8 threads within a 256-thread block; LDS for the teams'
+    // exchanges and the twiddle table within 64 KiB
+    const int nmax = c->dtype == IBM_F64 ? 1024 : 2048;
+    if (nx > nmax || ny > nmax)
+        return fail(IBM_E_UNSUPPORTED, "spectral transforms: nx, ny <= %d for this storage type (%d, %d)",
+                    nmax, nx, ny);
     return IBM_OK;
+}
+
+size_t spectral_lds_bytes(const ibm_ctx* c, int n) {
+    const size_t cs = c->dtype == IBM_F64 ? 16 : 8;
+    return ((size_t)team_lds_elems(256) + (size_t)n) * cs;
 }
 
 long spectral_slots(const ibm_ctx* c) {
