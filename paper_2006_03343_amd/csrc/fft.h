@@ -156,12 +156,17 @@ __device__ inline void pass_regs(Cx<T> (&v)[S][8], const Team& tm, int Ns, int l
 }
 
 // The outputs of a pass of radix RAD and span Ns (not the last pass) go to
-// LDS one sequence at a time and come back as the next pass's slots.
-template <typename T, int RAD, int S>
+// LDS and come back as the next pass's slots: all S sequences at once when
+// ALL (sequence s at s * team_lds_elems(blockDim.x)), else one at a time
+// through one sequence's space.
+template <typename T, int RAD, int S, bool ALL>
 __device__ inline void pass_exchange(Cx<T> (&v)[S][8], const Team& tm, int Ns, Cx<T>* lds) {
     constexpr int VT = 8 / RAD;
+    constexpr int NB = ALL ? 1 : S;             // rounds
+    constexpr int PR = ALL ? S : 1;             // sequences per round
+    const int sst = team_lds_elems(blockDim.x);
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
+    for (int b = 0; b < NB; ++b) {
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < VT; ++t) {
@@ -169,18 +174,26 @@ __device__ inline void pass_exchange(Cx<T> (&v)[S][8], const Team& tm, int Ns, C
             const int k = vv & (Ns - 1);
             const int e0 = (vv - k) * RAD + k;
 #pragma unroll
-            for (int m = 0; m < RAD; ++m) lds[tm.lds(e0 + m * Ns)] = v[s][t + m * VT];
+            for (int m = 0; m < RAD; ++m) {
+                const int a = tm.lds(e0 + m * Ns);
+#pragma unroll
+                for (int r = 0; r < PR; ++r) lds[a + r * sst] = v[b * PR + r][t + m * VT];
+            }
         }
         __syncthreads();
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[s][u] = lds[tm.lds(tm.elem(u))];
+        for (int u = 0; u < 8; ++u) {
+            const int a = tm.lds(tm.elem(u));
+#pragma unroll
+            for (int r = 0; r < PR; ++r) v[b * PR + r][u] = lds[a + r * sst];
+        }
     }
 }
 
 // Forward DFT (exponent -2 pi i) of S sequences held in the team's slots.
 // Every thread of the block must call it (it synchronises the block) with the
-// same logn.
-template <typename T, int S>
+// same logn.  LDS: team_lds_elems(blockDim.x) elements, times S when ALL.
+template <typename T, int S, bool ALL = false>
 __device__ void team_fft(Cx<T> (&v)[S][8], const Team& tm, Cx<T>* lds, const Cx<T>* tw) {
     const int logn = tm.logn;
     if (logn < 3) {
@@ -195,18 +208,18 @@ __device__ void team_fft(Cx<T> (&v)[S][8], const Team& tm, Cx<T>* lds, const Cx<
     int Ns = 1, lspan = 0;                      // lspan = log2(Ns)
     if (r0 == 1) {
         pass_regs<T, 2, S>(v, tm, Ns, logn - 1, tw);
-        pass_exchange<T, 2, S>(v, tm, Ns, lds);
+        pass_exchange<T, 2, S, ALL>(v, tm, Ns, lds);
         Ns = 2;
         lspan = 1;
     } else if (r0 == 2) {
         pass_regs<T, 4, S>(v, tm, Ns, logn - 2, tw);
-        pass_exchange<T, 4, S>(v, tm, Ns, lds);
+        pass_exchange<T, 4, S, ALL>(v, tm, Ns, lds);
         Ns = 4;
         lspan = 2;
     }
     for (int p = 0; p < logn / 3; ++p) {
         pass_regs<T, 8, S>(v, tm, Ns, logn - lspan - 3, tw);
-        if (lspan + 3 < logn) pass_exchange<T, 8, S>(v, tm, Ns, lds);
+        if (lspan + 3 < logn) pass_exchange<T, 8, S, ALL>(v, tm, Ns, lds);
         Ns <<= 3;
         lspan += 3;
     }
@@ -222,10 +235,10 @@ __device__ inline void swap_parts(Cx<T> (&v)[S][8]) {
         for (int u = 0; u < 8; ++u) v[s][u] = Cx<T>{v[s][u].im, v[s][u].re};
 }
 
-template <typename T, int S>
+template <typename T, int S, bool ALL = false>
 __device__ void team_ifft(Cx<T> (&v)[S][8], const Team& tm, Cx<T>* lds, const Cx<T>* tw) {
     swap_parts(v);
-    team_fft(v, tm, lds, tw);
+    team_fft<T, S, ALL>(v, tm, lds, tw);
     swap_parts(v);
 }
 

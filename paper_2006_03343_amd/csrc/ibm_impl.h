@@ -169,8 +169,9 @@ int ensure_twiddles(ibm_ctx* c);          // twiddle tables of nx and ny (first 
 // IBM_E_UNSUPPORTED unless nx and ny are powers of two that one block's
 // thread teams and LDS hold (float: <= 2048, double: <= 1024).
 int spectral_check(const ibm_ctx* c);
-// Dynamic LDS bytes of a 256-thread transform block for sequences of n.
-size_t spectral_lds_bytes(const ibm_ctx* c, int n);
+// Dynamic LDS bytes of a 256-thread transform block for sequences of n that
+// exchanges ``seqs`` sequences at once.
+size_t spectral_lds_bytes(const ibm_ctx* c, int n, int seqs);
 void free_spectral(ibm_ctx* c);
 
 // projection.hip

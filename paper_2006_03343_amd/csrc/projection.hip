@@ -182,7 +182,7 @@ __global__ void __launch_bounds__(256) k_cols(ProjArgs<T> a, int inverse) {
     const int n = a.ny, logn = a.logy;
     const int P = n >= 8 ? n >> 3 : 1, ns = n >= 8 ? 8 : n;
     const int teams = (int)blockDim.x / P;
-    Cx<T>* tw = xl + team_lds_elems(blockDim.x);
+    Cx<T>* tw = xl + team_lds_elems(blockDim.x) * (sizeof(T) == 4 ? 2 : 1);
     stage_twiddles(tw, a.twy, n);
     const int cpairs = a.nhp / 2;
     const int groups = (cpairs + teams - 1) / teams;
@@ -207,8 +207,8 @@ __global__ void __launch_bounds__(256) k_cols(ProjArgs<T> a, int inverse) {
             v[1][u] = p.b;
         }
         __syncthreads();   // twiddles staged
-        if (inverse) team_ifft<T, 2>(v, tm, xl, tw);
-        else team_fft<T, 2>(v, tm, xl, tw);
+        if (inverse) team_ifft<T, 2, true>(v, tm, xl, tw);
+        else team_fft<T, 2, true>(v, tm, xl, tw);
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             if (u >= ns || !act) continue;
@@ -268,28 +268,39 @@ __global__ void __launch_bounds__(256) k_solve(ProjArgs<T> a, Cx<T>* __restrict_
     double* const dre = (double*)U;
     double* const dim = (double*)V;
     double* const cw = (double*)W;
-    // forward sweep; level k's slots are rewritten once W[k] and W[k+1] have been read
+    // forward sweep; a mode's thread has no other parallelism, so the next
+    // level's loads go out before this level's work (issuing several levels
+    // at once measured slower).  Level k's slots are rewritten once W[k] and
+    // W[k+1] have been read.
+    const Cx<T> zero{T(0), T(0)};
     Cx<double> dprev{0.0, 0.0};
     double cprev = 0.0;
+    Cx<T> un = U[mode], vn = V[mode], wn = W[mode];
+    Cx<T> wun = nz > 1 ? W[a.hplane + mode] : zero;
     for (int k = 0; k < nz; ++k) {
         const long q = (long)k * a.hplane + mode;
-        const Cx<T> u = U[q], v = V[q], w = W[q];
-        const Cx<T> wu = k + 1 < nz ? W[q + a.hplane] : Cx<T>{T(0), T(0)};
+        const Cx<T> u = un, v = vn, w = wn, wu = wun;       // wu: 0 above the top
+        if (k + 1 < nz) {
+            un = U[q + a.hplane];
+            vn = V[q + a.hplane];
+            wn = wu;
+            wun = k + 2 < nz ? W[q + 2 * a.hplane] : zero;
+        }
         // i kx u + i ky v + (w[k+1] - w[k]) / dz
         Cx<double> r{-(kx * (double)u.im) - ky * (double)v.im + ((double)wu.re - (double)w.re) * invdz,
                      kx * (double)u.re + ky * (double)v.re + ((double)wu.im - (double)w.im) * invdz};
         r.re *= a.f;
         r.im *= a.f;
         double lo = k > 0 ? e : 0.0, up = k + 1 < nz ? e : 0.0;
-        double b = -K2 - lo - up;
+        double bd = -K2 - lo - up;
         if (pin && k == 0) {
-            b = 1.0;
+            bd = 1.0;
             up = 0.0;
             r = Cx<double>{0.0, 0.0};
         }
-        const double m = b - lo * cprev;
-        const double cn = up / m;
-        const Cx<double> dn{(r.re - lo * dprev.re) / m, (r.im - lo * dprev.im) / m};
+        const double rm = 1.0 / (bd - lo * cprev);
+        const double cn = up * rm;
+        const Cx<double> dn{(r.re - lo * dprev.re) * rm, (r.im - lo * dprev.im) * rm};
         if constexpr (narrow) {
             dre[q] = dn.re;
             dim[q] = dn.im;
@@ -301,12 +312,8 @@ __global__ void __launch_bounds__(256) k_solve(ProjArgs<T> a, Cx<T>* __restrict_
         cprev = cn;
         dprev = dn;
     }
-    // back substitution and the gradient spectra
-    Cx<double> pnext{0.0, 0.0};
-    for (int k = nz - 1; k >= 0; --k) {
-        const long q = (long)k * a.hplane + mode;
-        Cx<double> d;
-        double cc;
+    // back substitution and the gradient spectra, the next level's loads first
+    auto sweep_load = [&](long q, Cx<double>& d, double& cc) {
         if constexpr (narrow) {
             d = Cx<double>{dre[q], dim[q]};
             cc = cw[q];
@@ -315,6 +322,15 @@ __global__ void __launch_bounds__(256) k_solve(ProjArgs<T> a, Cx<T>* __restrict_
             d = Cx<double>{(double)t.re, (double)t.im};
             cc = cp[q];
         }
+    };
+    Cx<double> pnext{0.0, 0.0}, dnx;
+    double cnx;
+    sweep_load((long)(nz - 1) * a.hplane + mode, dnx, cnx);
+    for (int k = nz - 1; k >= 0; --k) {
+        const long q = (long)k * a.hplane + mode;
+        const Cx<double> d = dnx;
+        const double cc = cnx;
+        if (k > 0) sweep_load(q - a.hplane, dnx, cnx);
         const Cx<double> p{d.re - cc * pnext.re, d.im - cc * pnext.im};
         W[q] = Cx<T>{(T)p.re, (T)p.im};
         U[q] = Cx<T>{(T)(-(kx * p.im)), (T)(kx * p.re)};
@@ -390,7 +406,9 @@ int project_t(ibm_ctx* c, const void* const ustar[3], double dt, void* const uo[
     const int ty = 256 / (a.ny >= 8 ? a.ny / 8 : 1);
     const unsigned gx = (unsigned)(((a.rows + 1) / 2 + tx - 1) / tx);
     const unsigned gy = (unsigned)(((a.nhp / 2 + ty - 1) / ty) * a.nz);
-    const size_t lx = spectral_lds_bytes(c, a.nx), ly = spectral_lds_bytes(c, a.ny);
+    const size_t lx = spectral_lds_bytes(c, a.nx, 1);
+    // float: the two columns of a team through LDS at once
+    const size_t ly = spectral_lds_bytes(c, a.ny, sizeof(T) == 4 ? 2 : 1);
     hipLaunchKernelGGL(k_rows_fwd<T>, dim3(gx, 3), dim3(256), lx, s, a);
     hipLaunchKernelGGL(k_cols<T>, dim3(gy, 3), dim3(256), ly, s, a, 0);
     hipLaunchKernelGGL(k_solve<T>, dim3(nb256(a.hplane)), dim3(256), 0, s, a, U, V, W, cp);

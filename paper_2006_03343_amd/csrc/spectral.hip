@@ -24,6 +24,7 @@
 // teams of n / 8).
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <vector>
 
 #include "fft.h"
@@ -63,7 +64,7 @@ constexpr int kSeqAtOnce = sizeof(T) == 4 ? 3 : 1;
 // A team of P = max(1, nx / 8) consecutive threads per pair of rows (r, r+1);
 // sequence 0 = tau_xx + i tau_xy of row r, 1 = the same of row r+1, 2 =
 // tau_xz of row r + i tau_xz of row r+1.
-template <typename T>
+template <typename T, bool ALL>
 __global__ void __launch_bounds__(256) k_dx(SpecArgs<T> a) {
     constexpr int G = kSeqAtOnce<T>;
     extern __shared__ unsigned char lds_raw[];
@@ -71,7 +72,7 @@ __global__ void __launch_bounds__(256) k_dx(SpecArgs<T> a) {
     const int n = a.nx, logn = a.logx;
     const int P = n >= 8 ? n >> 3 : 1, ns = n >= 8 ? 8 : n;
     const int teams = (int)blockDim.x / P;
-    Cx<T>* tw = xl + team_lds_elems(blockDim.x);
+    Cx<T>* tw = xl + team_lds_elems(blockDim.x) * (ALL ? G : 1);
     stage_twiddles(tw, a.twx, n);
     const int team = (int)threadIdx.x / P;
     const Team tm = make_team(logn, (int)threadIdx.x - team * P, team, teams, false);
@@ -96,9 +97,9 @@ __global__ void __launch_bounds__(256) k_dx(SpecArgs<T> a) {
             }
         }
         __syncthreads();   // twiddles staged; the previous group's exchanges done
-        team_fft<T, G>(v, tm, xl, tw);
+        team_fft<T, G, ALL>(v, tm, xl, tw);
         derivative<T, G>(v, tm, n, a.kx);
-        team_ifft<T, G>(v, tm, xl, tw);
+        team_ifft<T, G, ALL>(v, tm, xl, tw);
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             if (u >= ns) continue;
@@ -123,16 +124,23 @@ __global__ void __launch_bounds__(256) k_dx(SpecArgs<T> a) {
 // A team per pair of columns (c, c+1) of plane k; the teams of a block are
 // interleaved across lanes (lane = j * teams + team), so a row's columns are
 // read together.  Sequences: tau_xy + i tau_yy of column c, of column c+1,
-// and tau_yz of column c + i tau_yz of column c+1.
+// and tau_yz of column c + i tau_yz of column c+1.  PAIR (float, nx even,
+// fields 8-byte aligned): each field's two columns move as one 8-byte access.
 template <typename T>
+struct alignas(2 * sizeof(T)) Two {
+    T x, y;
+};
+
+template <typename T, bool ALL, bool PAIR>
 __global__ void __launch_bounds__(256) k_dy(SpecArgs<T> a) {
     constexpr int G = kSeqAtOnce<T>;
+    static_assert(!PAIR || G == 3, "column pairs move together only with all sequences at once");
     extern __shared__ unsigned char lds_raw[];
     Cx<T>* xl = reinterpret_cast<Cx<T>*>(lds_raw);
     const int n = a.ny, logn = a.logy;
     const int P = n >= 8 ? n >> 3 : 1, ns = n >= 8 ? 8 : n;
     const int teams = (int)blockDim.x / P;
-    Cx<T>* tw = xl + team_lds_elems(blockDim.x);
+    Cx<T>* tw = xl + team_lds_elems(blockDim.x) * (ALL ? G : 1);
     stage_twiddles(tw, a.twy, n);
     const int groups = (a.nx + 2 * teams - 1) / (2 * teams);
     const int k = (int)blockIdx.x / groups;
@@ -148,37 +156,59 @@ __global__ void __launch_bounds__(256) k_dy(SpecArgs<T> a) {
         for (int u = 0; u < 8; ++u) {
             const long q = pk + (long)tm.elem(u) * a.nx + c0;
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
-                const int sq = s0 + g;
-                v[g][u] = Cx<T>{T(0), T(0)};
-                if (u >= ns) continue;
-                if (sq < 2) {
-                    if (in[sq]) v[g][u] = Cx<T>{a.tau[3][q + sq], a.tau[1][q + sq]};
-                } else {
-                    if (in[0]) v[g][u].re = a.tau[5][q];
-                    if (in[1]) v[g][u].im = a.tau[5][q + 1];
+            for (int g = 0; g < G; ++g) v[g][u] = Cx<T>{T(0), T(0)};
+            if (u >= ns) continue;
+            if constexpr (PAIR) {
+                if (!in[0]) continue;
+                const Two<T> xy = *reinterpret_cast<const Two<T>*>(a.tau[3] + q);
+                const Two<T> yy = *reinterpret_cast<const Two<T>*>(a.tau[1] + q);
+                const Two<T> yz = *reinterpret_cast<const Two<T>*>(a.tau[5] + q);
+                v[0][u] = Cx<T>{xy.x, yy.x};
+                v[1][u] = Cx<T>{xy.y, yy.y};
+                v[2][u] = Cx<T>{yz.x, yz.y};
+            } else {
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    const int sq = s0 + g;
+                    if (sq < 2) {
+                        if (in[sq]) v[g][u] = Cx<T>{a.tau[3][q + sq], a.tau[1][q + sq]};
+                    } else {
+                        if (in[0]) v[g][u].re = a.tau[5][q];
+                        if (in[1]) v[g][u].im = a.tau[5][q + 1];
+                    }
                 }
             }
         }
         __syncthreads();
-        team_fft<T, G>(v, tm, xl, tw);
+        team_fft<T, G, ALL>(v, tm, xl, tw);
         derivative<T, G>(v, tm, n, a.ky);
-        team_ifft<T, G>(v, tm, xl, tw);
+        team_ifft<T, G, ALL>(v, tm, xl, tw);
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             if (u >= ns) continue;
             const long q = pk + (long)tm.elem(u) * a.nx + c0;
+            if constexpr (PAIR) {
+                if (!in[0]) continue;
+                Two<T>* d0 = reinterpret_cast<Two<T>*>(a.div[0] + q);
+                Two<T>* d1 = reinterpret_cast<Two<T>*>(a.div[1] + q);
+                Two<T>* d2 = reinterpret_cast<Two<T>*>(a.div[2] + q);
+                const Two<T> o0 = *d0, o1 = *d1, o2 = *d2;
+                *d0 = Two<T>{o0.x + v[0][u].re, o0.y + v[1][u].re};
+                *d1 = Two<T>{o1.x + v[0][u].im, o1.y + v[1][u].im};
+                *d2 = Two<T>{o2.x + v[2][u].re, o2.y + v[2][u].im};
+            } else {
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
-                const int sq = s0 + g;
-                if (sq < 2) {
-                    if (in[sq]) {
-                        a.div[0][q + sq] += v[g][u].re;
-                        a.div[1][q + sq] += v[g][u].im;
+                for (int g = 0; g < G; ++g) {
+                    const int sq = s0 + g;
+                    if (sq < 2) {
+                        if (in[sq]) {
+                            a.div[0][q + sq] += v[g][u].re;
+                            a.div[1][q + sq] += v[g][u].im;
+                        }
+                    } else {
+                        if (in[0]) a.div[2][q] += v[g][u].re;
+                        if (in[1]) a.div[2][q + 1] += v[g][u].im;
                     }
-                } else {
-                    if (in[0]) a.div[2][q] += v[g][u].re;
-                    if (in[1]) a.div[2][q + 1] += v[g][u].im;
                 }
             }
         }
@@ -301,12 +331,20 @@ int spectral_t(ibm_ctx* c, const void* const tau[6], void* const ustar[3],
     a.ky = (T)(2.0 * M_PI / (ny * c->g.dy));
     const int tx = 256 / (nx >= 8 ? nx / 8 : 1);            // teams per block
     const long pairs = (a.rows + 1) / 2;
-    hipLaunchKernelGGL(k_dx<T>, dim3((unsigned)((pairs + tx - 1) / tx)), dim3(256),
-                       spectral_lds_bytes(c, nx), s, a);
+    const dim3 gdx((unsigned)((pairs + tx - 1) / tx));
+    // one sequence's exchange space: exchanging all three at once measured
+    // slower here (more registers, fewer waves)
+    hipLaunchKernelGGL((k_dx<T, false>), gdx, dim3(256), spectral_lds_bytes(c, nx, 1), s, a);
     const int ty = 256 / (ny >= 8 ? ny / 8 : 1);
     const int groups = (nx + 2 * ty - 1) / (2 * ty);
-    hipLaunchKernelGGL(k_dy<T>, dim3((unsigned)(groups * nz)), dim3(256),
-                       spectral_lds_bytes(c, ny), s, a);
+    const dim3 gdy((unsigned)(groups * nz));
+    bool aligned = sizeof(T) == 4 && nx % 2 == 0;
+    for (int i = 0; i < 6; ++i) aligned = aligned && (uintptr_t)tau[i] % (2 * sizeof(T)) == 0;
+    for (int i = 0; i < 3; ++i) aligned = aligned && (uintptr_t)div[i] % (2 * sizeof(T)) == 0;
+    if (aligned)
+        hipLaunchKernelGGL((k_dy<T, false, sizeof(T) == 4>), gdy, dim3(256), spectral_lds_bytes(c, ny, 1), s, a);
+    else
+        hipLaunchKernelGGL((k_dy<T, false, false>), gdy, dim3(256), spectral_lds_bytes(c, ny, 1), s, a);
     ApplyArgs<T> z = make_apply_args<T>(c, c->cfg, tau, ustar, gradp, dt, div, drag);
     const long n = c->n;
     const int nzb = (int)((n + 256L * kZItems - 1) / (256L * kZItems));
@@ -358,9 +396,9 @@ int spectral_check(const ibm_ctx* c) {
     return IBM_OK;
 }
 
-size_t spectral_lds_bytes(const ibm_ctx* c, int n) {
+size_t spectral_lds_bytes(const ibm_ctx* c, int n, int seqs) {
     const size_t cs = c->dtype == IBM_F64 ? 16 : 8;
-    return ((size_t)team_lds_elems(256) + (size_t)n) * cs;
+    return ((size_t)team_lds_elems(256) * seqs + (size_t)n) * cs;
 }
 
 long spectral_slots(const ibm_ctx* c) {
