@@ -140,16 +140,16 @@ int ibm_apply_spectral(ibm_ctx* c, const void* const tau[6], void* const ustar[3
  * modes without derivative) plus (w[k+1] - w[k]) / dz on uv nodes, w above
  * the top w node taken as 0; G: pseudo-spectral d/dx, d/dy of p on uv nodes
  * and (p[k] - p[k-1]) / dz on w nodes k >= 1, no correction on the bottom w
- * node.  Each horizontal mode is a tridiagonal system in z (Thomas, in
- * double for either storage type); a mode
+ * node.  Each horizontal mode is a tridiagonal system in z (Thomas, its
+ * recurrences in double for either storage type); a mode
  * without horizontal wavenumber (the mean and the Nyquist modes) is singular
  * and takes p = 0 at k = 0 in place of its first row, so u_out is discretely
  * divergence-free when w is 0 on the bottom plane.  u_out may alias ustar;
  * p_out may alias neither.  nx, ny: powers of two as for
  * ibm_apply_spectral, else IBM_E_UNSUPPORTED.  The first call allocates a
- * workspace of 3 complex volumes (double storage: and 1 real volume) of the
- * storage type and builds twiddle tables
- * (synchronous).  Needs a context, not a prepare.  Asynchronous on
+ * workspace of 3 half-spectrum complex volumes of the storage type
+ * (nz x ny x (nx/2 + 1) modes, rows padded to an even count) and builds
+ * twiddle tables (synchronous).  Needs a context, not a prepare.  Asynchronous on
  * ``stream`` otherwise.  Errors: IBM_E_ARG, IBM_E_RANGE (dt <= 0),
  * IBM_E_UNSUPPORTED, IBM_E_HIP. */
 int ibm_ab2_predict(ibm_ctx* c, const void* const u[3], const void* const rhs_now[3],

@@ -84,8 +84,7 @@ struct SpectralTw {
 
 // Workspace of the pressure projection (allocated on first use): three
 // half-spectrum complex volumes of the storage type (nz x ny x (nx/2 + 1)
-// modes, rows padded to an even count), plus one real double volume of the
-// same modes for double storage.
+// modes, rows padded to an even count).
 struct ProjWs {
     void* buf = nullptr;
     size_t bytes = 0;

@@ -22,9 +22,10 @@
 // at once where there are three): k_rows_fwd -- forward x transforms, two real
 // rows packed into one complex transform and separated through the team's
 // LDS; k_cols -- y transforms of pairs of half-spectrum columns, in place;
-// k_solve -- one thread per horizontal mode for the right-hand side, a Thomas
-// sweep in z (in double) and the gradient spectra i kx p_hat, i ky p_hat,
-// p_hat (coalesced across modes); k_cols inverse; k_rows_inv -- inverse x
+// k_solve -- two threads per horizontal mode for the right-hand side, the
+// tridiagonal system in z eliminated from both ends (recurrences in double)
+// and the gradient spectra i kx p_hat, i ky p_hat, p_hat (coalesced across
+// modes); k_cols inverse; k_rows_inv -- inverse x
 // transforms from the Hermitian extension, two rows per transform, applying
 // the horizontal corrections to u and v and returning p; k_wcorr -- the
 // vertical correction of w.  Transforms: fft.h.
@@ -238,23 +239,34 @@ __global__ void __launch_bounds__(256) k_cols(ProjArgs<T> a, int inverse) {
     }
 }
 
-// One thread per horizontal mode (i, j): right-hand side, Thomas sweep in z,
-// then U = i kx p_hat, V = i ky p_hat, W = p_hat.  The sweep runs in double whatever the
-// storage type.  A K = 0 system is a Neumann chain pinned at one end whose
-// condition number grows as nz^2, so a float sweep over a few hundred levels
-// would lose the digits the transforms keep.  The forward sweep stores d' and
-// c' in the slots of the level it has just read: with float storage each
-// complex slot of U, V, W is 8 bytes, one double (d'.re in U, d'.im in V, c'
-// in W); with double storage d' goes into W and c' into cp.
+// Two threads per horizontal mode (i, j): the right-hand side, the
+// tridiagonal system in z eliminated from both ends at once, and then U =
+// i kx p_hat, V = i ky p_hat, W = p_hat.  Thread "top" runs Thomas forward
+// elimination over rows 0 .. h-1 (h = nz / 2), leaving p_k = d'_k - c'_k
+// p_{k+1}; thread "bottom" eliminates rows nz-1 .. h+1 upward, leaving p_k =
+// d''_k - a''_k p_{k-1}, and forms row h's right-hand side.  Through LDS
+// each gets the other's last coefficients and both solve row h with the same
+// expression, then substitute back over their own rows.  A mode's chain is
+// thus half as long and twice as many threads hide the memory latency.
+//
+// The recurrences run in double whatever the storage type: a K = 0 system is
+// a Neumann chain pinned at one end whose condition number grows as nz^2, and
+// float arithmetic in them over a few hundred levels loses the digits the
+// transforms keep (rounding only the stored coefficients to float costs
+// ~1e-7).  Each level's coefficient goes into the real part of U and its d
+// into W, once that level's own values (and, going up, the w above it) have
+// been read; row h is written by the top thread only after the exchange.
+constexpr int kSolveModes = 128;    // modes per block; blockDim = 2 * kSolveModes
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_solve(ProjArgs<T> a, Cx<T>* __restrict__ U,
-                                               Cx<T>* __restrict__ V, Cx<T>* __restrict__ W,
-                                               double* __restrict__ cp) {
-    constexpr bool narrow = sizeof(T) == 4;
-    const long mode = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (mode >= a.hplane) return;
+                                               Cx<T>* __restrict__ V, Cx<T>* __restrict__ W) {
+    __shared__ double xs[8][kSolveModes];
+    const int lane = (int)threadIdx.x % kSolveModes;
+    const bool top = (int)threadIdx.x < kSolveModes;
+    const long mode = (long)blockIdx.x * kSolveModes + lane;
     const int i = (int)(mode % a.nhp), j = (int)(mode / a.nhp);
-    if (i >= a.nh) return;
+    const bool act = mode < a.hplane && i < a.nh;
     auto wavenumber = [](int m, int n, double k0) {
         if (n > 1 && 2 * m == n) return 0.0;                // Nyquist
         return k0 * (double)(2 * m < n ? m : m - n);
@@ -263,79 +275,131 @@ __global__ void __launch_bounds__(256) k_solve(ProjArgs<T> a, Cx<T>* __restrict_
     const double K2 = kx * kx + ky * ky;
     const double e = 1.0 / (a.dz * a.dz);
     const double invdz = 1.0 / a.dz;
-    const int nz = a.nz;
+    const int nz = a.nz, h = nz / 2;
     const bool pin = K2 == 0.0;
-    double* const dre = (double*)U;
-    double* const dim = (double*)V;
-    double* const cw = (double*)W;
-    // forward sweep; a mode's thread has no other parallelism, so the next
-    // level's loads go out before this level's work (issuing several levels
-    // at once measured slower).  Level k's slots are rewritten once W[k] and
-    // W[k+1] have been read.
+    const long hp = a.hplane;
     const Cx<T> zero{T(0), T(0)};
-    Cx<double> dprev{0.0, 0.0};
-    double cprev = 0.0;
-    Cx<T> un = U[mode], vn = V[mode], wn = W[mode];
-    Cx<T> wun = nz > 1 ? W[a.hplane + mode] : zero;
-    for (int k = 0; k < nz; ++k) {
-        const long q = (long)k * a.hplane + mode;
-        const Cx<T> u = un, v = vn, w = wn, wu = wun;       // wu: 0 above the top
-        if (k + 1 < nz) {
-            un = U[q + a.hplane];
-            vn = V[q + a.hplane];
-            wn = wu;
-            wun = k + 2 < nz ? W[q + 2 * a.hplane] : zero;
-        }
-        // i kx u + i ky v + (w[k+1] - w[k]) / dz
-        Cx<double> r{-(kx * (double)u.im) - ky * (double)v.im + ((double)wu.re - (double)w.re) * invdz,
-                     kx * (double)u.re + ky * (double)v.re + ((double)wu.im - (double)w.im) * invdz};
-        r.re *= a.f;
-        r.im *= a.f;
-        double lo = k > 0 ? e : 0.0, up = k + 1 < nz ? e : 0.0;
-        double bd = -K2 - lo - up;
-        if (pin && k == 0) {
-            bd = 1.0;
-            up = 0.0;
-            r = Cx<double>{0.0, 0.0};
-        }
-        const double rm = 1.0 / (bd - lo * cprev);
-        const double cn = up * rm;
-        const Cx<double> dn{(r.re - lo * dprev.re) * rm, (r.im - lo * dprev.im) * rm};
-        if constexpr (narrow) {
-            dre[q] = dn.re;
-            dim[q] = dn.im;
-            cw[q] = cn;
-        } else {
-            W[q] = Cx<T>{dn.re, dn.im};
-            cp[q] = cn;
-        }
-        cprev = cn;
-        dprev = dn;
-    }
-    // back substitution and the gradient spectra, the next level's loads first
-    auto sweep_load = [&](long q, Cx<double>& d, double& cc) {
-        if constexpr (narrow) {
-            d = Cx<double>{dre[q], dim[q]};
-            cc = cw[q];
-        } else {
-            const Cx<T> t = W[q];
-            d = Cx<double>{(double)t.re, (double)t.im};
-            cc = cp[q];
-        }
+    // 2 / (3 dt) (i kx u + i ky v + (w[k+1] - w[k]) / dz)
+    auto rhs = [&](Cx<T> u, Cx<T> v, Cx<T> w, Cx<T> wu) {
+        return Cx<double>{a.f * (-(kx * (double)u.im) - ky * (double)v.im +
+                                 ((double)wu.re - (double)w.re) * invdz),
+                          a.f * (kx * (double)u.re + ky * (double)v.re +
+                                 ((double)wu.im - (double)w.im) * invdz)};
     };
-    Cx<double> pnext{0.0, 0.0}, dnx;
-    double cnx;
-    sweep_load((long)(nz - 1) * a.hplane + mode, dnx, cnx);
-    for (int k = nz - 1; k >= 0; --k) {
-        const long q = (long)k * a.hplane + mode;
-        const Cx<double> d = dnx;
-        const double cc = cnx;
-        if (k > 0) sweep_load(q - a.hplane, dnx, cnx);
-        const Cx<double> p{d.re - cc * pnext.re, d.im - cc * pnext.im};
+    if (top) {
+        // rows 0 .. h-1, the next level's loads issued before this level's work
+        double cT = 0.0;
+        Cx<double> dT{0.0, 0.0};
+        if (act && h > 0) {
+            Cx<T> un = U[mode], vn = V[mode], wn = W[mode], wun = W[hp + mode];
+            for (int k = 0; k < h; ++k) {
+                const long q = (long)k * hp + mode;
+                const Cx<T> u = un, v = vn, w = wn, wu = wun;
+                if (k + 1 < h) {
+                    un = U[q + hp];
+                    vn = V[q + hp];
+                    wn = wu;
+                    wun = W[q + 2 * hp];                    // k + 2 <= h < nz
+                }
+                Cx<double> r = rhs(u, v, w, wu);
+                const double lo = k > 0 ? e : 0.0;
+                double up = e, b = -K2 - lo - e;            // k + 1 <= h < nz
+                if (pin && k == 0) {
+                    b = 1.0;
+                    up = 0.0;
+                    r = Cx<double>{0.0, 0.0};
+                }
+                const double rm = 1.0 / (b - lo * cT);
+                cT = up * rm;
+                dT = Cx<double>{(r.re - lo * dT.re) * rm, (r.im - lo * dT.im) * rm};
+                W[q] = Cx<T>{(T)dT.re, (T)dT.im};
+                U[q].re = (T)cT;
+            }
+        }
+        xs[0][lane] = cT;
+        xs[1][lane] = dT.re;
+        xs[2][lane] = dT.im;
+    } else {
+        // rows nz-1 .. h+1 going up, then row h's right-hand side
+        double aB = 0.0;
+        Cx<double> dB{0.0, 0.0}, rh{0.0, 0.0};
+        if (act) {
+            Cx<T> wu = zero;                                 // original w one level up
+            const long qt = (long)(nz - 1) * hp + mode;
+            Cx<T> un = U[qt], vn = V[qt], wn = W[qt];
+            for (int k = nz - 1; k > h; --k) {
+                const long q = (long)k * hp + mode;
+                const Cx<T> u = un, v = vn, w = wn;
+                un = U[q - hp];                              // k - 1 >= h
+                vn = V[q - hp];
+                wn = W[q - hp];
+                const Cx<double> r = rhs(u, v, w, wu);
+                const double up = k + 1 < nz ? e : 0.0;
+                const double b = -K2 - e - up;               // k >= 1
+                const double rm = 1.0 / (b - up * aB);
+                aB = e * rm;
+                dB = Cx<double>{(r.re - up * dB.re) * rm, (r.im - up * dB.im) * rm};
+                W[q] = Cx<T>{(T)dB.re, (T)dB.im};
+                U[q].re = (T)aB;
+                wu = w;
+            }
+            rh = rhs(un, vn, wn, wu);                        // row h, from the originals
+        }
+        xs[3][lane] = aB;
+        xs[4][lane] = dB.re;
+        xs[5][lane] = dB.im;
+        xs[6][lane] = rh.re;
+        xs[7][lane] = rh.im;
+    }
+    __syncthreads();
+    if (!act) return;
+    // row h: lo p_{h-1} + b p_h + up p_{h+1} = r_h with p_{h-1} = d'_{h-1} -
+    // c'_{h-1} p_h and p_{h+1} = d''_{h+1} - a''_{h+1} p_h
+    const double cT = xs[0][lane], aB = xs[3][lane];
+    const Cx<double> dT{xs[1][lane], xs[2][lane]}, dB{xs[4][lane], xs[5][lane]};
+    Cx<double> r{xs[6][lane], xs[7][lane]};
+    const double lo = h > 0 ? e : 0.0;
+    double up = h + 1 < nz ? e : 0.0, b = -K2 - lo - up;
+    if (pin && h == 0) {
+        b = 1.0;
+        up = 0.0;
+        r = Cx<double>{0.0, 0.0};
+    }
+    const double rm = 1.0 / (b - lo * cT - up * aB);
+    const Cx<double> ph{(r.re - lo * dT.re - up * dB.re) * rm, (r.im - lo * dT.im - up * dB.im) * rm};
+    auto put = [&](long q, Cx<double> p) {
         W[q] = Cx<T>{(T)p.re, (T)p.im};
         U[q] = Cx<T>{(T)(-(kx * p.im)), (T)(kx * p.re)};
         V[q] = Cx<T>{(T)(-(ky * p.im)), (T)(ky * p.re)};
-        pnext = p;
+    };
+    auto coef = [&](long q, Cx<double>& d, double& c) {
+        const Cx<T> t = W[q];
+        d = Cx<double>{(double)t.re, (double)t.im};
+        c = (double)U[q].re;
+    };
+    Cx<double> p = ph, dn;
+    double cn;
+    if (top) {
+        put((long)h * hp + mode, ph);
+        if (h > 0) coef((long)(h - 1) * hp + mode, dn, cn);
+        for (int k = h - 1; k >= 0; --k) {
+            const long q = (long)k * hp + mode;
+            const Cx<double> d = dn;
+            const double c = cn;
+            if (k > 0) coef(q - hp, dn, cn);
+            p = Cx<double>{d.re - c * p.re, d.im - c * p.im};
+            put(q, p);
+        }
+    } else {
+        if (h + 1 < nz) coef((long)(h + 1) * hp + mode, dn, cn);
+        for (int k = h + 1; k < nz; ++k) {
+            const long q = (long)k * hp + mode;
+            const Cx<double> d = dn;
+            const double c = cn;
+            if (k + 1 < nz) coef(q + hp, dn, cn);
+            p = Cx<double>{d.re - c * p.re, d.im - c * p.im};
+            put(q, p);
+        }
     }
 }
 
@@ -371,16 +435,13 @@ int project_t(ibm_ctx* c, const void* const ustar[3], double dt, void* const uo[
     a.hplane = (long)a.nhp * a.ny;
     const long nspec = a.hplane * a.nz;
     if (!c->proj.buf) {
-        // float storage keeps the sweep's doubles in the three spectra
         const size_t cb = sizeof(Cx<T>) * (size_t)nspec;
-        const size_t rb = sizeof(T) == 8 ? sizeof(double) * (size_t)nspec : 0;
-        IBM_HIP(hipMalloc(&c->proj.buf, 3 * cb + rb));
-        c->proj.bytes = 3 * cb + rb;
+        IBM_HIP(hipMalloc(&c->proj.buf, 3 * cb));
+        c->proj.bytes = 3 * cb;
     }
     Cx<T>* U = (Cx<T>*)c->proj.buf;
     Cx<T>* V = U + nspec;
     Cx<T>* W = V + nspec;
-    double* cp = sizeof(T) == 8 ? (double*)(W + nspec) : nullptr;
     a.twx = (const Cx<T>*)c->spec.twx;
     a.twy = (const Cx<T>*)c->spec.twy;
     a.kx = 2.0 * M_PI / (a.nx * c->g.dx);
@@ -411,7 +472,8 @@ int project_t(ibm_ctx* c, const void* const ustar[3], double dt, void* const uo[
     const size_t ly = spectral_lds_bytes(c, a.ny, sizeof(T) == 4 ? 2 : 1);
     hipLaunchKernelGGL(k_rows_fwd<T>, dim3(gx, 3), dim3(256), lx, s, a);
     hipLaunchKernelGGL(k_cols<T>, dim3(gy, 3), dim3(256), ly, s, a, 0);
-    hipLaunchKernelGGL(k_solve<T>, dim3(nb256(a.hplane)), dim3(256), 0, s, a, U, V, W, cp);
+    hipLaunchKernelGGL(k_solve<T>, dim3((unsigned)((a.hplane + kSolveModes - 1) / kSolveModes)),
+                       dim3(2 * kSolveModes), 0, s, a, U, V, W);
     hipLaunchKernelGGL(k_cols<T>, dim3(gy, 3), dim3(256), ly, s, a, 1);
     // u = u* - c d/dx p, v = v* - c d/dy p, and p itself
     hipLaunchKernelGGL(k_rows_inv<T>, dim3(gx, 3), dim3(256), lx, s, a);
