@@ -18,17 +18,18 @@
 // modes are solvable (e.g. w = 0 on the bottom plane).
 //
 // Real fields have Hermitian spectra along x, so only the modes 0 .. nx/2 are
-// kept (rows padded to an even length).  Launches (each over the three fields
-// at once where there are three): k_rows_fwd -- forward x transforms, two real
-// rows packed into one complex transform and separated through the team's
-// LDS; k_cols -- y transforms of pairs of half-spectrum columns, in place;
-// k_solve -- two threads per horizontal mode for the right-hand side, the
-// tridiagonal system in z eliminated from both ends (recurrences in double)
-// and the gradient spectra i kx p_hat, i ky p_hat, p_hat (coalesced across
-// modes); k_cols inverse; k_rows_inv -- inverse x
-// transforms from the Hermitian extension, two rows per transform, applying
-// the horizontal corrections to u and v and returning p; k_wcorr -- the
-// vertical correction of w.  Transforms: fft.h.
+// kept (rows padded to an even length).  Launches: k_rows_fwd -- forward x
+// transforms of u*, v*, w*, two real rows packed into one complex transform
+// and separated through the team's LDS; k_cols_fwd -- y transforms of pairs
+// of half-spectrum columns, which leave the horizontal divergence spectrum
+// H = i kx u_hat + i ky v_hat and w_hat; k_solve -- two threads per
+// horizontal mode for the right-hand side 2 / (3 dt) (H + (w_hat[k+1] -
+// w_hat[k]) / dz) and the tridiagonal system in z, eliminated from both ends
+// (recurrences in double), leaving p_hat; k_cols_inv -- inverse y transforms
+// of p_hat and i ky p_hat from one read; k_rows_inv -- inverse x transforms
+// from the Hermitian extension, two rows per transform, returning p and u =
+// u* - (3 dt / 2) d/dx p (i kx formed in the same pass) and v = v* - (3 dt /
+// 2) d/dy p; k_wcorr -- the vertical correction of w.  Transforms: fft.h.
 #include <algorithm>
 #include <cmath>
 
@@ -48,11 +49,14 @@ struct ProjArgs {
     const Cx<T>* twx;
     const Cx<T>* twy;
     const T* in[3];          // u*, v*, w*
-    Cx<T>* spec[3];          // their half spectra; after the solve i kx p, i ky p, p
-    const T* base[3];        // u*, v*, none
-    T scale[3];              // -3 dt / 2, -3 dt / 2, 1
-    T* out[3];               // u, v, p
+    Cx<T>* spec[3];          // their x spectra; then H and w_hat, p_hat; P and DY
+    const T* ub;             // u*, v*: bases of the horizontal corrections
+    const T* vb;
+    T* uo;                   // u, v, p
+    T* vo;
+    T* po;
     double kx, ky;           // 2 pi / Lx, 2 pi / Ly
+    T kxs, kys;              // the same in the storage type
     double dz;
     double f;                // 2 / (3 dt)
     T c;                     // 3 dt / 2
@@ -113,29 +117,22 @@ __global__ void __launch_bounds__(256) k_rows_fwd(ProjArgs<T> a) {
     }
 }
 
-// Inverse x transforms of field blockIdx.y: a team per pair of rows builds
-// Z_e = A_e + i B_e over all e from the half spectra (A_e = conj A_{n-e}
-// above nx / 2; the imaginary parts of modes 0 and nx / 2 are dropped, as a
-// real inverse does), inverts it, and stores base + scale * Re / nx for row
-// r and base + scale * Im / nx for row r+1.
-template <typename T>
-__global__ void __launch_bounds__(256) k_rows_inv(ProjArgs<T> a) {
-    extern __shared__ unsigned char lds_raw[];
-    Cx<T>* xl = reinterpret_cast<Cx<T>*>(lds_raw);
-    const int n = a.nx, logn = a.logx;
-    const int P = n >= 8 ? n >> 3 : 1, ns = n >= 8 ? 8 : n;
-    const int teams = (int)blockDim.x / P;
-    Cx<T>* tw = xl + team_lds_elems(blockDim.x);
-    stage_twiddles(tw, a.twx, n);
-    const int team = (int)threadIdx.x / P;
-    const Team tm = make_team(logn, (int)threadIdx.x - team * P, team, teams, false);
-    const long r0 = 2 * ((long)blockIdx.x * teams + team);
-    const bool in0 = r0 < a.rows, in1 = r0 + 1 < a.rows;
-    const Cx<T>* __restrict__ A = a.spec[blockIdx.y];
-    Cx<T> v[1][8];
+// Inverse x transforms: a team per pair of rows builds Z_e = A_e + i B_e
+// over all e from the half spectra A (row r) and B (row r+1) (A_e = conj
+// A_{n-e} above nx / 2; the imaginary parts of modes 0 and nx / 2 are
+// dropped, as a real inverse does) and inverts it.  blockIdx.y = 0: from P,
+// p and, with the same loads, i kx P for u = u* - (3 dt / 2) d/dx p;
+// blockIdx.y = 1: from DY, v = v* - (3 dt / 2) d/dy p.
+template <typename T, int S>
+__device__ inline void rows_inv_body(const ProjArgs<T>& a, const Cx<T>* __restrict__ A,
+                                     const Team& tm, Cx<T>* xl, const Cx<T>* tw, long r0,
+                                     bool in0, bool in1, int ns) {
+    const int n = a.nx;
+    Cx<T> v[S][8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-        v[0][u] = Cx<T>{T(0), T(0)};
+#pragma unroll
+        for (int s = 0; s < S; ++s) v[s][u] = Cx<T>{T(0), T(0)};
         if (u >= ns) continue;
         const int e = tm.elem(u);
         const bool upper = 2 * e > n;
@@ -151,117 +148,229 @@ __global__ void __launch_bounds__(256) k_rows_inv(ProjArgs<T> a) {
             zb.im = -zb.im;
         }
         v[0][u] = Cx<T>{za.re - zb.im, za.im + zb.re};
+        if constexpr (S == 2) {
+            // i kx A + i (i kx B), kx signed, 0 at the Nyquist mode
+            const T k = a.kxs * T(mode_number(e, n));
+            v[1][u] = Cx<T>{-(k * za.im) - k * zb.re, k * za.re - k * zb.im};
+        }
     }
     __syncthreads();   // twiddles staged
-    team_ifft<T, 1>(v, tm, xl, tw);
-    const T s = a.scale[blockIdx.y] / T(n);
-    const T* base = a.base[blockIdx.y];
-    T* out = a.out[blockIdx.y];
+    team_ifft<T, S>(v, tm, xl, tw);
+    const T inv = T(1) / T(n), s = -a.c / T(n);
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
         if (u >= ns) continue;
         const long o = r0 * n + tm.elem(u);
-        const T va = v[0][u].re * s, vb = v[0][u].im * s;
-        if (in0) out[o] = base ? base[o] + va : va;
-        if (in1) out[o + n] = base ? base[o + n] + vb : vb;
+        if constexpr (S == 2) {
+            if (in0) {
+                a.po[o] = v[0][u].re * inv;
+                a.uo[o] = a.ub[o] + v[1][u].re * s;
+            }
+            if (in1) {
+                a.po[o + n] = v[0][u].im * inv;
+                a.uo[o + n] = a.ub[o + n] + v[1][u].im * s;
+            }
+        } else {
+            if (in0) a.vo[o] = a.vb[o] + v[0][u].re * s;
+            if (in1) a.vo[o + n] = a.vb[o + n] + v[0][u].im * s;
+        }
     }
 }
 
-// y transforms in place of field blockIdx.y's half spectrum: a team per pair
-// of adjacent columns of one plane, teams interleaved across lanes (lane =
-// j * teams + team) so a row's columns are read together; the inverse
-// includes 1 / ny.
+template <typename T>
+__global__ void __launch_bounds__(256) k_rows_inv(ProjArgs<T> a) {
+    extern __shared__ unsigned char lds_raw[];
+    Cx<T>* xl = reinterpret_cast<Cx<T>*>(lds_raw);
+    const int n = a.nx, logn = a.logx;
+    const int P = n >= 8 ? n >> 3 : 1, ns = n >= 8 ? 8 : n;
+    const int teams = (int)blockDim.x / P;
+    Cx<T>* tw = xl + team_lds_elems(blockDim.x);
+    stage_twiddles(tw, a.twx, n);
+    const int team = (int)threadIdx.x / P;
+    const Team tm = make_team(logn, (int)threadIdx.x - team * P, team, teams, false);
+    const long r0 = 2 * ((long)blockIdx.x * teams + team);
+    const bool in0 = r0 < a.rows, in1 = r0 + 1 < a.rows;
+    if (blockIdx.y == 0) rows_inv_body<T, 2>(a, a.spec[0], tm, xl, tw, r0, in0, in1, ns);
+    else rows_inv_body<T, 1>(a, a.spec[1], tm, xl, tw, r0, in0, in1, ns);
+}
+
+// y transforms of the half spectra: a team per pair of adjacent columns of
+// one plane, teams interleaved across lanes (lane = j * teams + team) so a
+// row's columns are read together.  Float moves both columns of a pair as
+// one 16-byte access and transforms them together; double takes one column
+// at a time (two would spill registers).
 template <typename T>
 struct alignas(2 * sizeof(Cx<T>)) CxPair {
     Cx<T> a, b;
 };
 
+template <typename T, int G>
+__device__ inline void col_load(Cx<T> (&v)[G][8], const Cx<T>* base, const Team& tm, int nhp,
+                                int ns, bool act) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) v[g][u] = Cx<T>{T(0), T(0)};
+        if (u >= ns || !act) continue;
+        const Cx<T>* p = base + (long)tm.elem(u) * nhp;
+        if constexpr (G == 2) {
+            const CxPair<T> t = *reinterpret_cast<const CxPair<T>*>(p);
+            v[0][u] = t.a;
+            v[1][u] = t.b;
+        } else {
+            v[0][u] = *p;
+        }
+    }
+}
+
+template <typename T, int G>
+__device__ inline void col_store(const Cx<T> (&v)[G][8], T scale, Cx<T>* base, const Team& tm,
+                                 int nhp, int ns, bool act) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        if (u >= ns || !act) continue;
+        Cx<T>* p = base + (long)tm.elem(u) * nhp;
+        if constexpr (G == 2) {
+            *reinterpret_cast<CxPair<T>*>(p) =
+                CxPair<T>{Cx<T>{v[0][u].re * scale, v[0][u].im * scale},
+                          Cx<T>{v[1][u].re * scale, v[1][u].im * scale}};
+        } else {
+            *p = Cx<T>{v[0][u].re * scale, v[0][u].im * scale};
+        }
+    }
+}
+
+// Signed x wavenumber of half-spectrum column i (0 at the Nyquist mode).
 template <typename T>
-__global__ void __launch_bounds__(256) k_cols(ProjArgs<T> a, int inverse) {
+__device__ inline T kx_of(const ProjArgs<T>& a, int i) {
+    return (a.nx > 1 && 2 * i == a.nx) ? T(0) : a.kxs * T(i);
+}
+
+// Forward: u_hat, v_hat -> H = i kx u_hat + i ky v_hat (into spec[0]); w_hat
+// in place.
+template <typename T>
+__global__ void __launch_bounds__(256) k_cols_fwd(ProjArgs<T> a) {
+    constexpr int G = sizeof(T) == 4 ? 2 : 1;
     extern __shared__ unsigned char lds_raw[];
     Cx<T>* xl = reinterpret_cast<Cx<T>*>(lds_raw);
     const int n = a.ny, logn = a.logy;
     const int P = n >= 8 ? n >> 3 : 1, ns = n >= 8 ? 8 : n;
     const int teams = (int)blockDim.x / P;
-    Cx<T>* tw = xl + team_lds_elems(blockDim.x) * (sizeof(T) == 4 ? 2 : 1);
+    Cx<T>* tw = xl + team_lds_elems(blockDim.x) * G;
     stage_twiddles(tw, a.twy, n);
     const int cpairs = a.nhp / 2;
     const int groups = (cpairs + teams - 1) / teams;
     const int k = (int)blockIdx.x / groups;
-    const int g = (int)blockIdx.x - k * groups;
+    const int gi = (int)blockIdx.x - k * groups;
     const int team = (int)threadIdx.x % teams;
     const Team tm = make_team(logn, (int)threadIdx.x / teams, team, teams, true);
-    const int cp = g * teams + team;
+    const int cp = gi * teams + team;
     const bool act = cp < cpairs;
-    const T s = inverse ? T(1) / T(n) : T(1);
-    if constexpr (sizeof(T) == 4) {
-        // both columns at once, one 16-byte access per row
-        CxPair<T>* d = reinterpret_cast<CxPair<T>*>(a.spec[blockIdx.y] + (long)k * a.hplane + 2 * cp);
-        const int rs = a.nhp / 2;                  // row stride in pairs
-        Cx<T> v[2][8];
+    const long off = (long)k * a.hplane + 2 * cp;
+    __syncthreads();   // twiddles staged
+    for (int c = 0; c < 2; c += G) {
+        Cx<T> hs[G][8], v[G][8];
+        col_load<T, G>(v, a.spec[0] + off + c, tm, a.nhp, ns, act);
+        team_fft<T, G, G == 2>(v, tm, xl, tw);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const T kx = kx_of(a, 2 * cp + c + g);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) hs[g][u] = Cx<T>{-(kx * v[g][u].im), kx * v[g][u].re};
+        }
+        col_load<T, G>(v, a.spec[1] + off + c, tm, a.nhp, ns, act);
+        team_fft<T, G, G == 2>(v, tm, xl, tw);
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            v[0][u] = v[1][u] = Cx<T>{T(0), T(0)};
-            if (u >= ns || !act) continue;
-            const CxPair<T> p = d[(long)tm.elem(u) * rs];
-            v[0][u] = p.a;
-            v[1][u] = p.b;
-        }
-        __syncthreads();   // twiddles staged
-        if (inverse) team_ifft<T, 2, true>(v, tm, xl, tw);
-        else team_fft<T, 2, true>(v, tm, xl, tw);
+            const T ky = a.kys * T(mode_number(tm.elem(u) & (n - 1), n));
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            if (u >= ns || !act) continue;
-            d[(long)tm.elem(u) * rs] = CxPair<T>{Cx<T>{v[0][u].re * s, v[0][u].im * s},
-                                                 Cx<T>{v[1][u].re * s, v[1][u].im * s}};
-        }
-    } else {
-        // one column after the other (two would spill registers)
-        Cx<T>* d = a.spec[blockIdx.y] + (long)k * a.hplane + 2 * cp;
-        for (int h = 0; h < 2; ++h) {
-            Cx<T> v[1][8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                v[0][u] = Cx<T>{T(0), T(0)};
-                if (u >= ns || !act) continue;
-                v[0][u] = d[(long)tm.elem(u) * a.nhp + h];
-            }
-            __syncthreads();
-            if (inverse) team_ifft<T, 1>(v, tm, xl, tw);
-            else team_fft<T, 1>(v, tm, xl, tw);
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                if (u >= ns || !act) continue;
-                d[(long)tm.elem(u) * a.nhp + h] = Cx<T>{v[0][u].re * s, v[0][u].im * s};
+            for (int g = 0; g < G; ++g) {
+                hs[g][u].re -= ky * v[g][u].im;
+                hs[g][u].im += ky * v[g][u].re;
             }
         }
+        col_store<T, G>(hs, T(1), a.spec[0] + off + c, tm, a.nhp, ns, act);
+        col_load<T, G>(v, a.spec[2] + off + c, tm, a.nhp, ns, act);
+        team_fft<T, G, G == 2>(v, tm, xl, tw);
+        col_store<T, G>(v, T(1), a.spec[2] + off + c, tm, a.nhp, ns, act);
     }
 }
 
-// Two threads per horizontal mode (i, j): the right-hand side, the
-// tridiagonal system in z eliminated from both ends at once, and then U =
-// i kx p_hat, V = i ky p_hat, W = p_hat.  Thread "top" runs Thomas forward
-// elimination over rows 0 .. h-1 (h = nz / 2), leaving p_k = d'_k - c'_k
-// p_{k+1}; thread "bottom" eliminates rows nz-1 .. h+1 upward, leaving p_k =
-// d''_k - a''_k p_{k-1}, and forms row h's right-hand side.  Through LDS
-// each gets the other's last coefficients and both solve row h with the same
-// expression, then substitute back over their own rows.  A mode's chain is
-// thus half as long and twice as many threads hide the memory latency.
+// Inverse: p_hat (spec[0]) -> P = its inverse y transform (in place) and
+// DY = that of i ky p_hat (into spec[1]), both with 1 / ny.
+template <typename T>
+__global__ void __launch_bounds__(256) k_cols_inv(ProjArgs<T> a) {
+    constexpr int G = sizeof(T) == 4 ? 2 : 1;
+    extern __shared__ unsigned char lds_raw[];
+    Cx<T>* xl = reinterpret_cast<Cx<T>*>(lds_raw);
+    const int n = a.ny, logn = a.logy;
+    const int P = n >= 8 ? n >> 3 : 1, ns = n >= 8 ? 8 : n;
+    const int teams = (int)blockDim.x / P;
+    Cx<T>* tw = xl + team_lds_elems(blockDim.x);
+    stage_twiddles(tw, a.twy, n);
+    const int cpairs = a.nhp / 2;
+    const int groups = (cpairs + teams - 1) / teams;
+    const int k = (int)blockIdx.x / groups;
+    const int gi = (int)blockIdx.x - k * groups;
+    const int team = (int)threadIdx.x % teams;
+    const Team tm = make_team(logn, (int)threadIdx.x / teams, team, teams, true);
+    const int cp = gi * teams + team;
+    const bool act = cp < cpairs;
+    const long off = (long)k * a.hplane + 2 * cp;
+    const T inv = T(1) / T(n);
+    __syncthreads();   // twiddles staged
+    for (int c = 0; c < 2; c += G) {
+        Cx<T> pv[G][8];
+        col_load<T, G>(pv, a.spec[0] + off + c, tm, a.nhp, ns, act);
+        Cx<T> v[2 * G][8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const T ky = a.kys * T(mode_number(tm.elem(u) & (n - 1), n));
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                v[g][u] = pv[g][u];
+                v[G + g][u] = Cx<T>{-(ky * pv[g][u].im), ky * pv[g][u].re};
+            }
+        }
+        team_ifft<T, 2 * G>(v, tm, xl, tw);
+        Cx<T> o[G][8];
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) o[g][u] = v[g][u];
+        col_store<T, G>(o, inv, a.spec[0] + off + c, tm, a.nhp, ns, act);
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) o[g][u] = v[G + g][u];
+        col_store<T, G>(o, inv, a.spec[1] + off + c, tm, a.nhp, ns, act);
+    }
+}
+
+// Two threads per horizontal mode (i, j): the right-hand side and the
+// tridiagonal system in z, eliminated from both ends at once, leaving p_hat
+// in H's place.  Thread "top" runs Thomas forward elimination over rows 0 ..
+// h-1 (h = nz / 2), leaving p_k = d'_k - c'_k p_{k+1}; thread "bottom"
+// eliminates rows nz-1 .. h+1 upward, leaving p_k = d''_k - a''_k p_{k-1},
+// and forms row h's right-hand side.  Through LDS each gets the other's last
+// coefficients and both solve row h with the same expression, then
+// substitute back over their own rows.  A mode's chain is thus half as long
+// and twice as many threads hide the memory latency.
 //
 // The recurrences run in double whatever the storage type: a K = 0 system is
 // a Neumann chain pinned at one end whose condition number grows as nz^2, and
 // float arithmetic in them over a few hundred levels loses the digits the
 // transforms keep (rounding only the stored coefficients to float costs
-// ~1e-7).  Each level's coefficient goes into the real part of U and its d
+// ~1e-7).  Each level's coefficient goes into the real part of H and its d
 // into W, once that level's own values (and, going up, the w above it) have
 // been read; row h is written by the top thread only after the exchange.
 constexpr int kSolveModes = 128;    // modes per block; blockDim = 2 * kSolveModes
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_solve(ProjArgs<T> a, Cx<T>* __restrict__ U,
-                                               Cx<T>* __restrict__ V, Cx<T>* __restrict__ W) {
+__global__ void __launch_bounds__(256) k_solve(ProjArgs<T> a) {
     __shared__ double xs[8][kSolveModes];
+    Cx<T>* __restrict__ H = a.spec[0];
+    Cx<T>* __restrict__ W = a.spec[2];
     const int lane = (int)threadIdx.x % kSolveModes;
     const bool top = (int)threadIdx.x < kSolveModes;
     const long mode = (long)blockIdx.x * kSolveModes + lane;
@@ -279,29 +388,26 @@ __global__ void __launch_bounds__(256) k_solve(ProjArgs<T> a, Cx<T>* __restrict_
     const bool pin = K2 == 0.0;
     const long hp = a.hplane;
     const Cx<T> zero{T(0), T(0)};
-    // 2 / (3 dt) (i kx u + i ky v + (w[k+1] - w[k]) / dz)
-    auto rhs = [&](Cx<T> u, Cx<T> v, Cx<T> w, Cx<T> wu) {
-        return Cx<double>{a.f * (-(kx * (double)u.im) - ky * (double)v.im +
-                                 ((double)wu.re - (double)w.re) * invdz),
-                          a.f * (kx * (double)u.re + ky * (double)v.re +
-                                 ((double)wu.im - (double)w.im) * invdz)};
+    // 2 / (3 dt) (H + (w[k+1] - w[k]) / dz)
+    auto rhs = [&](Cx<T> hh, Cx<T> w, Cx<T> wu) {
+        return Cx<double>{a.f * ((double)hh.re + ((double)wu.re - (double)w.re) * invdz),
+                          a.f * ((double)hh.im + ((double)wu.im - (double)w.im) * invdz)};
     };
     if (top) {
         // rows 0 .. h-1, the next level's loads issued before this level's work
         double cT = 0.0;
         Cx<double> dT{0.0, 0.0};
         if (act && h > 0) {
-            Cx<T> un = U[mode], vn = V[mode], wn = W[mode], wun = W[hp + mode];
+            Cx<T> hn = H[mode], wn = W[mode], wun = W[hp + mode];
             for (int k = 0; k < h; ++k) {
                 const long q = (long)k * hp + mode;
-                const Cx<T> u = un, v = vn, w = wn, wu = wun;
+                const Cx<T> hh = hn, w = wn, wu = wun;
                 if (k + 1 < h) {
-                    un = U[q + hp];
-                    vn = V[q + hp];
+                    hn = H[q + hp];
                     wn = wu;
                     wun = W[q + 2 * hp];                    // k + 2 <= h < nz
                 }
-                Cx<double> r = rhs(u, v, w, wu);
+                Cx<double> r = rhs(hh, w, wu);
                 const double lo = k > 0 ? e : 0.0;
                 double up = e, b = -K2 - lo - e;            // k + 1 <= h < nz
                 if (pin && k == 0) {
@@ -313,7 +419,7 @@ __global__ void __launch_bounds__(256) k_solve(ProjArgs<T> a, Cx<T>* __restrict_
                 cT = up * rm;
                 dT = Cx<double>{(r.re - lo * dT.re) * rm, (r.im - lo * dT.im) * rm};
                 W[q] = Cx<T>{(T)dT.re, (T)dT.im};
-                U[q].re = (T)cT;
+                H[q].re = (T)cT;
             }
         }
         xs[0][lane] = cT;
@@ -326,24 +432,23 @@ __global__ void __launch_bounds__(256) k_solve(ProjArgs<T> a, Cx<T>* __restrict_
         if (act) {
             Cx<T> wu = zero;                                 // original w one level up
             const long qt = (long)(nz - 1) * hp + mode;
-            Cx<T> un = U[qt], vn = V[qt], wn = W[qt];
+            Cx<T> hn = H[qt], wn = W[qt];
             for (int k = nz - 1; k > h; --k) {
                 const long q = (long)k * hp + mode;
-                const Cx<T> u = un, v = vn, w = wn;
-                un = U[q - hp];                              // k - 1 >= h
-                vn = V[q - hp];
+                const Cx<T> hh = hn, w = wn;
+                hn = H[q - hp];                              // k - 1 >= h
                 wn = W[q - hp];
-                const Cx<double> r = rhs(u, v, w, wu);
+                const Cx<double> r = rhs(hh, w, wu);
                 const double up = k + 1 < nz ? e : 0.0;
                 const double b = -K2 - e - up;               // k >= 1
                 const double rm = 1.0 / (b - up * aB);
                 aB = e * rm;
                 dB = Cx<double>{(r.re - up * dB.re) * rm, (r.im - up * dB.im) * rm};
                 W[q] = Cx<T>{(T)dB.re, (T)dB.im};
-                U[q].re = (T)aB;
+                H[q].re = (T)aB;
                 wu = w;
             }
-            rh = rhs(un, vn, wn, wu);                        // row h, from the originals
+            rh = rhs(hn, wn, wu);                            // row h, from the originals
         }
         xs[3][lane] = aB;
         xs[4][lane] = dB.re;
@@ -367,20 +472,15 @@ __global__ void __launch_bounds__(256) k_solve(ProjArgs<T> a, Cx<T>* __restrict_
     }
     const double rm = 1.0 / (b - lo * cT - up * aB);
     const Cx<double> ph{(r.re - lo * dT.re - up * dB.re) * rm, (r.im - lo * dT.im - up * dB.im) * rm};
-    auto put = [&](long q, Cx<double> p) {
-        W[q] = Cx<T>{(T)p.re, (T)p.im};
-        U[q] = Cx<T>{(T)(-(kx * p.im)), (T)(kx * p.re)};
-        V[q] = Cx<T>{(T)(-(ky * p.im)), (T)(ky * p.re)};
-    };
     auto coef = [&](long q, Cx<double>& d, double& c) {
         const Cx<T> t = W[q];
         d = Cx<double>{(double)t.re, (double)t.im};
-        c = (double)U[q].re;
+        c = (double)H[q].re;
     };
     Cx<double> p = ph, dn;
     double cn;
     if (top) {
-        put((long)h * hp + mode, ph);
+        H[(long)h * hp + mode] = Cx<T>{(T)ph.re, (T)ph.im};
         if (h > 0) coef((long)(h - 1) * hp + mode, dn, cn);
         for (int k = h - 1; k >= 0; --k) {
             const long q = (long)k * hp + mode;
@@ -388,7 +488,7 @@ __global__ void __launch_bounds__(256) k_solve(ProjArgs<T> a, Cx<T>* __restrict_
             const double c = cn;
             if (k > 0) coef(q - hp, dn, cn);
             p = Cx<double>{d.re - c * p.re, d.im - c * p.im};
-            put(q, p);
+            H[q] = Cx<T>{(T)p.re, (T)p.im};
         }
     } else {
         if (h + 1 < nz) coef((long)(h + 1) * hp + mode, dn, cn);
@@ -398,7 +498,7 @@ __global__ void __launch_bounds__(256) k_solve(ProjArgs<T> a, Cx<T>* __restrict_
             const double c = cn;
             if (k + 1 < nz) coef(q + hp, dn, cn);
             p = Cx<double>{d.re - c * p.re, d.im - c * p.im};
-            put(q, p);
+            H[q] = Cx<T>{(T)p.re, (T)p.im};
         }
     }
 }
@@ -455,28 +555,25 @@ int project_t(ibm_ctx* c, const void* const ustar[3], double dt, void* const uo[
         a.in[i] = (const T*)ustar[i];
         a.spec[i] = spec[i];
     }
-    a.base[0] = (const T*)ustar[0];
-    a.base[1] = (const T*)ustar[1];
-    a.base[2] = nullptr;
-    a.scale[0] = a.scale[1] = -a.c;
-    a.scale[2] = T(1);
-    a.out[0] = (T*)uo[0];
-    a.out[1] = (T*)uo[1];
-    a.out[2] = (T*)p_out;
+    a.ub = (const T*)ustar[0];
+    a.vb = (const T*)ustar[1];
+    a.uo = (T*)uo[0];
+    a.vo = (T*)uo[1];
+    a.po = (T*)p_out;
+    a.kxs = (T)a.kx;
+    a.kys = (T)a.ky;
     const int tx = 256 / (a.nx >= 8 ? a.nx / 8 : 1);     // teams per block
     const int ty = 256 / (a.ny >= 8 ? a.ny / 8 : 1);
     const unsigned gx = (unsigned)(((a.rows + 1) / 2 + tx - 1) / tx);
     const unsigned gy = (unsigned)(((a.nhp / 2 + ty - 1) / ty) * a.nz);
-    const size_t lx = spectral_lds_bytes(c, a.nx, 1);
-    // float: the two columns of a team through LDS at once
-    const size_t ly = spectral_lds_bytes(c, a.ny, sizeof(T) == 4 ? 2 : 1);
-    hipLaunchKernelGGL(k_rows_fwd<T>, dim3(gx, 3), dim3(256), lx, s, a);
-    hipLaunchKernelGGL(k_cols<T>, dim3(gy, 3), dim3(256), ly, s, a, 0);
+    constexpr int G = sizeof(T) == 4 ? 2 : 1;            // columns per y-transform phase
+    hipLaunchKernelGGL(k_rows_fwd<T>, dim3(gx, 3), dim3(256), spectral_lds_bytes(c, a.nx, 1), s, a);
+    hipLaunchKernelGGL(k_cols_fwd<T>, dim3(gy), dim3(256), spectral_lds_bytes(c, a.ny, G), s, a);
     hipLaunchKernelGGL(k_solve<T>, dim3((unsigned)((a.hplane + kSolveModes - 1) / kSolveModes)),
-                       dim3(2 * kSolveModes), 0, s, a, U, V, W);
-    hipLaunchKernelGGL(k_cols<T>, dim3(gy, 3), dim3(256), ly, s, a, 1);
-    // u = u* - c d/dx p, v = v* - c d/dy p, and p itself
-    hipLaunchKernelGGL(k_rows_inv<T>, dim3(gx, 3), dim3(256), lx, s, a);
+                       dim3(2 * kSolveModes), 0, s, a);
+    hipLaunchKernelGGL(k_cols_inv<T>, dim3(gy), dim3(256), spectral_lds_bytes(c, a.ny, 1), s, a);
+    // p and u = u* - c d/dx p (blockIdx.y = 0), v = v* - c d/dy p (1)
+    hipLaunchKernelGGL(k_rows_inv<T>, dim3(gx, 2), dim3(256), spectral_lds_bytes(c, a.nx, 1), s, a);
     hipLaunchKernelGGL(k_wcorr<T>, dim3(nb256(c->n)), dim3(256), 0, s, a, (const T*)ustar[2],
                        (const T*)p_out, (T*)uo[2]);
     IBM_HIP(hipGetLastError());
