@@ -120,19 +120,30 @@ __global__ void __launch_bounds__(256) k_rows_fwd(ProjArgs<T> a) {
 // Inverse x transforms: a team per pair of rows builds Z_e = A_e + i B_e
 // over all e from the half spectra A (row r) and B (row r+1) (A_e = conj
 // A_{n-e} above nx / 2; the imaginary parts of modes 0 and nx / 2 are
-// dropped, as a real inverse does) and inverts it.  blockIdx.y = 0: from P,
-// p and, with the same loads, i kx P for u = u* - (3 dt / 2) d/dx p;
-// blockIdx.y = 1: from DY, v = v* - (3 dt / 2) d/dy p.
-template <typename T, int S>
-__device__ inline void rows_inv_body(const ProjArgs<T>& a, const Cx<T>* __restrict__ A,
-                                     const Team& tm, Cx<T>* xl, const Cx<T>* tw, long r0,
-                                     bool in0, bool in1, int ns) {
-    const int n = a.nx;
-    Cx<T> v[S][8];
+// dropped, as a real inverse does) and inverts it.  blockIdx.y = 0: p from
+// P; 1: u = u* - (3 dt / 2) d/dx p from i kx P; 2: v = v* - (3 dt / 2)
+// d/dy p from DY.  One transform per team keeps the registers, and with them
+// the waves per SIMD, of the forward x pass (two per team measured slower
+// despite reading P once).
+template <typename T>
+__global__ void __launch_bounds__(256) k_rows_inv(ProjArgs<T> a) {
+    extern __shared__ unsigned char lds_raw[];
+    Cx<T>* xl = reinterpret_cast<Cx<T>*>(lds_raw);
+    const int n = a.nx, logn = a.logx;
+    const int P = n >= 8 ? n >> 3 : 1, ns = n >= 8 ? 8 : n;
+    const int teams = (int)blockDim.x / P;
+    Cx<T>* tw = xl + team_lds_elems(blockDim.x);
+    stage_twiddles(tw, a.twx, n);
+    const int team = (int)threadIdx.x / P;
+    const Team tm = make_team(logn, (int)threadIdx.x - team * P, team, teams, false);
+    const int kind = (int)blockIdx.y;
+    const long r0 = 2 * ((long)blockIdx.x * teams + team);
+    const bool in0 = r0 < a.rows, in1 = r0 + 1 < a.rows;
+    const Cx<T>* __restrict__ A = kind < 2 ? a.spec[0] : a.spec[1];
+    Cx<T> v[1][8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-#pragma unroll
-        for (int s = 0; s < S; ++s) v[s][u] = Cx<T>{T(0), T(0)};
+        v[0][u] = Cx<T>{T(0), T(0)};
         if (u >= ns) continue;
         const int e = tm.elem(u);
         const bool upper = 2 * e > n;
@@ -147,51 +158,27 @@ __device__ inline void rows_inv_body(const ProjArgs<T>& a, const Cx<T>* __restri
             za.im = -za.im;
             zb.im = -zb.im;
         }
-        v[0][u] = Cx<T>{za.re - zb.im, za.im + zb.re};
-        if constexpr (S == 2) {
+        if (kind == 1) {
             // i kx A + i (i kx B), kx signed, 0 at the Nyquist mode
             const T k = a.kxs * T(mode_number(e, n));
-            v[1][u] = Cx<T>{-(k * za.im) - k * zb.re, k * za.re - k * zb.im};
+            v[0][u] = Cx<T>{-(k * za.im) - k * zb.re, k * za.re - k * zb.im};
+        } else {
+            v[0][u] = Cx<T>{za.re - zb.im, za.im + zb.re};
         }
     }
     __syncthreads();   // twiddles staged
-    team_ifft<T, S>(v, tm, xl, tw);
-    const T inv = T(1) / T(n), s = -a.c / T(n);
+    team_ifft<T, 1>(v, tm, xl, tw);
+    const T* base = kind == 1 ? a.ub : a.vb;
+    T* out = kind == 0 ? a.po : kind == 1 ? a.uo : a.vo;
+    const T s = kind == 0 ? T(1) / T(n) : -a.c / T(n);
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
         if (u >= ns) continue;
         const long o = r0 * n + tm.elem(u);
-        if constexpr (S == 2) {
-            if (in0) {
-                a.po[o] = v[0][u].re * inv;
-                a.uo[o] = a.ub[o] + v[1][u].re * s;
-            }
-            if (in1) {
-                a.po[o + n] = v[0][u].im * inv;
-                a.uo[o + n] = a.ub[o + n] + v[1][u].im * s;
-            }
-        } else {
-            if (in0) a.vo[o] = a.vb[o] + v[0][u].re * s;
-            if (in1) a.vo[o + n] = a.vb[o + n] + v[0][u].im * s;
-        }
+        const T va = v[0][u].re * s, vb = v[0][u].im * s;
+        if (in0) out[o] = kind ? base[o] + va : va;
+        if (in1) out[o + n] = kind ? base[o + n] + vb : vb;
     }
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) k_rows_inv(ProjArgs<T> a) {
-    extern __shared__ unsigned char lds_raw[];
-    Cx<T>* xl = reinterpret_cast<Cx<T>*>(lds_raw);
-    const int n = a.nx, logn = a.logx;
-    const int P = n >= 8 ? n >> 3 : 1, ns = n >= 8 ? 8 : n;
-    const int teams = (int)blockDim.x / P;
-    Cx<T>* tw = xl + team_lds_elems(blockDim.x);
-    stage_twiddles(tw, a.twx, n);
-    const int team = (int)threadIdx.x / P;
-    const Team tm = make_team(logn, (int)threadIdx.x - team * P, team, teams, false);
-    const long r0 = 2 * ((long)blockIdx.x * teams + team);
-    const bool in0 = r0 < a.rows, in1 = r0 + 1 < a.rows;
-    if (blockIdx.y == 0) rows_inv_body<T, 2>(a, a.spec[0], tm, xl, tw, r0, in0, in1, ns);
-    else rows_inv_body<T, 1>(a, a.spec[1], tm, xl, tw, r0, in0, in1, ns);
 }
 
 // y transforms of the half spectra: a team per pair of adjacent columns of
@@ -572,8 +559,8 @@ int project_t(ibm_ctx* c, const void* const ustar[3], double dt, void* const uo[
     hipLaunchKernelGGL(k_solve<T>, dim3((unsigned)((a.hplane + kSolveModes - 1) / kSolveModes)),
                        dim3(2 * kSolveModes), 0, s, a);
     hipLaunchKernelGGL(k_cols_inv<T>, dim3(gy), dim3(256), spectral_lds_bytes(c, a.ny, 1), s, a);
-    // p and u = u* - c d/dx p (blockIdx.y = 0), v = v* - c d/dy p (1)
-    hipLaunchKernelGGL(k_rows_inv<T>, dim3(gx, 2), dim3(256), spectral_lds_bytes(c, a.nx, 1), s, a);
+    // p, u = u* - c d/dx p, v = v* - c d/dy p
+    hipLaunchKernelGGL(k_rows_inv<T>, dim3(gx, 3), dim3(256), spectral_lds_bytes(c, a.nx, 1), s, a);
     hipLaunchKernelGGL(k_wcorr<T>, dim3(nb256(c->n)), dim3(256), 0, s, a, (const T*)ustar[2],
                        (const T*)p_out, (T*)uo[2]);
     IBM_HIP(hipGetLastError());
