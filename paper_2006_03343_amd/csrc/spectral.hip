@@ -5,7 +5,7 @@
 //   vertical staggered differences (eqs. dudz, dwdz), the forcing (eq.
 //   u-*-IBM) and the drag are those of the dense pass.
 //
-// Three launches:
+// Two launches (and the drag finalize):
 //   k_dx   a thread team per pair of rows (r, r+1) holds three complex
 //          sequences in registers: tau_xx + i tau_xy of each row and
 //          tau_xz of row r + i tau_xz of row r+1 (the derivative is a real
@@ -13,13 +13,15 @@
 //          transform, product with i k / nx with the Nyquist mode dropped
 //          (explicitly: with two fields packed its term would leak into the
 //          other field), inverse transform; writes div_x = d/dx tau_xx,
-//          div_y = d/dx tau_xy, div_z = d/dx tau_xz;
+//          div_y = d/dx tau_xy, div_z = d/dx tau_xz; the blocks after the row
+//          blocks force the forcing segments;
 //   k_dy   the same along y, a team per pair of columns of one plane, on
 //          tau_xy + i tau_yy and tau_yz, adding d/dy tau_xy, d/dy tau_yy,
-//          d/dy tau_yz;
-//   k_spec_z  adds the staggered vertical differences, leaves per-block drag
-//          partials (finalized in slot order), and forces the forcing
-//          segments in the blocks after the dense ones.
+//          d/dy tau_yz and the staggered vertical differences (d/dz tau_xz,
+//          tau_yz on uv nodes, d/dz tau_zz on w nodes, zero padded), loaded
+//          with the divergence it updates; with the final divergence in hand
+//          it leaves per-block drag partials over the fluid nodes, summed in
+//          slot order by k_spec_finalize.
 // Transforms: fft.h (register-resident Stockham passes of radix 8, thread
 // teams of n / 8).
 #include <algorithm>
@@ -41,7 +43,9 @@ struct SpecArgs {
     const Cx<T>* twy;
     int nx, ny, nz, logx, logy;
     long rows;               // ny * nz
+    long plane;              // nx * ny
     T kx, ky;                // 2 pi / Lx, 2 pi / Ly
+    T cz;                    // 1 / dz
 };
 
 // i k_m X_m / n for every slot (the Nyquist mode gets k = 0).
@@ -56,6 +60,35 @@ __device__ inline void derivative(Cx<T> (&v)[S][8], const Team& tm, int n, T two
     }
 }
 
+template <typename T>
+struct alignas(2 * sizeof(T)) Two {
+    T x, y;
+};
+
+// Staggered vertical difference of tau component c at node q of plane k:
+// on uv nodes (up) (tau[q + plane] - tau[q]) / dz, on w nodes (tau[q] -
+// tau[q - plane]) / dz, zero beyond the top and bottom planes.
+template <typename T>
+__device__ inline T zdiff(const SpecArgs<T>& a, int c, long q, int k, bool up) {
+    const T* t = a.tau[c];
+    if (up) return ((k + 1 < a.nz ? t[q + a.plane] : T(0)) - t[q]) * a.cz;
+    return (t[q] - (k > 0 ? t[q - a.plane] : T(0))) * a.cz;
+}
+
+// The same for the two nodes q, q + 1 (q even, fields 8-byte aligned).
+template <typename T>
+__device__ inline Two<T> zdiff2(const SpecArgs<T>& a, int c, long q, int k, bool up) {
+    const T* t = a.tau[c];
+    const Two<T> z{T(0), T(0)};
+    const Two<T> here = *reinterpret_cast<const Two<T>*>(t + q);
+    if (up) {
+        const Two<T> nb = k + 1 < a.nz ? *reinterpret_cast<const Two<T>*>(t + q + a.plane) : z;
+        return Two<T>{(nb.x - here.x) * a.cz, (nb.y - here.y) * a.cz};
+    }
+    const Two<T> nb = k > 0 ? *reinterpret_cast<const Two<T>*>(t + q - a.plane) : z;
+    return Two<T>{(here.x - nb.x) * a.cz, (here.y - nb.y) * a.cz};
+}
+
 // Sequences a team transforms at once: all three in float; one after another
 // in double, whose registers would spill otherwise.
 template <typename T>
@@ -65,7 +98,19 @@ constexpr int kSeqAtOnce = sizeof(T) == 4 ? 3 : 1;
 // sequence 0 = tau_xx + i tau_xy of row r, 1 = the same of row r+1, 2 =
 // tau_xz of row r + i tau_xz of row r+1.
 template <typename T, bool ALL>
-__global__ void __launch_bounds__(256) k_dx(SpecArgs<T> a) {
+__global__ void __launch_bounds__(256) k_dx(SpecArgs<T> a, ApplyArgs<T> z, unsigned nrowblocks) {
+    if (blockIdx.x >= nrowblocks) {
+        // forcing: quarters of the forcing segments
+        constexpr int kPiece = kSeg / 4;
+        for (long it = blockIdx.x - nrowblocks; it < 4 * z.nfsegs; it += z.nfblocks) {
+            const Seg sg = z.fsegs[it >> 2];
+            const int off = (int)(it & 3) * kPiece;
+            if (off < sg.len)
+                force_seg<T>(z, Seg{sg.q + off, min(kPiece, sg.len - off), 0, 0}, threadIdx.x,
+                             blockDim.x);
+        }
+        return;
+    }
     constexpr int G = kSeqAtOnce<T>;
     extern __shared__ unsigned char lds_raw[];
     Cx<T>* xl = reinterpret_cast<Cx<T>*>(lds_raw);
@@ -121,18 +166,24 @@ __global__ void __launch_bounds__(256) k_dx(SpecArgs<T> a) {
     }
 }
 
+// Drag over the fluid nodes: flag bit 0 marks a forced uv node (div_x,
+// div_y left out), bit 1 a forced w node (div_z left out).
+template <typename Acc, typename T>
+__device__ inline void drag_add(Acc (&acc)[3], uint32_t fb, T d0, T d1, T d2) {
+    if (!(fb & 1u)) {
+        acc[0] += (Acc)d0;
+        acc[1] += (Acc)d1;
+    }
+    if (!(fb & 2u)) acc[2] += (Acc)d2;
+}
+
 // A team per pair of columns (c, c+1) of plane k; the teams of a block are
 // interleaved across lanes (lane = j * teams + team), so a row's columns are
 // read together.  Sequences: tau_xy + i tau_yy of column c, of column c+1,
 // and tau_yz of column c + i tau_yz of column c+1.  PAIR (float, nx even,
 // fields 8-byte aligned): each field's two columns move as one 8-byte access.
-template <typename T>
-struct alignas(2 * sizeof(T)) Two {
-    T x, y;
-};
-
-template <typename T, bool ALL, bool PAIR>
-__global__ void __launch_bounds__(256) k_dy(SpecArgs<T> a) {
+template <typename T, bool ALL, bool PAIR, typename Acc>
+__global__ void __launch_bounds__(256) k_dy(SpecArgs<T> a, ApplyArgs<T> z) {
     constexpr int G = kSeqAtOnce<T>;
     static_assert(!PAIR || G == 3, "column pairs move together only with all sequences at once");
     extern __shared__ unsigned char lds_raw[];
@@ -150,6 +201,7 @@ __global__ void __launch_bounds__(256) k_dy(SpecArgs<T> a) {
     const int c0 = 2 * (gi * teams + team);
     const bool in[2] = {c0 < a.nx, c0 + 1 < a.nx};
     const long pk = (long)k * a.ny * a.nx;
+    Acc acc[3] = {Acc(0), Acc(0), Acc(0)};     // drag partials over the fluid nodes
     for (int s0 = 0; s0 < 3; s0 += G) {
         Cx<T> v[G][8];
 #pragma unroll
@@ -186,16 +238,28 @@ __global__ void __launch_bounds__(256) k_dy(SpecArgs<T> a) {
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             if (u >= ns) continue;
-            const long q = pk + (long)tm.elem(u) * a.nx + c0;
+            const int row = tm.elem(u);
+            const long q = pk + (long)row * a.nx + c0;
+            // forcing flags of columns c0, c0 + 1 (one word: c0 is even)
+            const uint32_t fw = (in[0] && s0 + G >= 3) ?
+                z.fmask[((long)k * a.ny + row) * z.wrow + (c0 >> 4)] >> (2 * (c0 & 15)) : 0u;
             if constexpr (PAIR) {
                 if (!in[0]) continue;
                 Two<T>* d0 = reinterpret_cast<Two<T>*>(a.div[0] + q);
                 Two<T>* d1 = reinterpret_cast<Two<T>*>(a.div[1] + q);
                 Two<T>* d2 = reinterpret_cast<Two<T>*>(a.div[2] + q);
                 const Two<T> o0 = *d0, o1 = *d1, o2 = *d2;
-                *d0 = Two<T>{o0.x + v[0][u].re, o0.y + v[1][u].re};
-                *d1 = Two<T>{o1.x + v[0][u].im, o1.y + v[1][u].im};
-                *d2 = Two<T>{o2.x + v[2][u].re, o2.y + v[2][u].im};
+                // staggered vertical differences, loaded with the divergence
+                const Two<T> zx = zdiff2(a, 4, q, k, true), zy = zdiff2(a, 5, q, k, true),
+                             zz = zdiff2(a, 2, q, k, false);
+                const Two<T> n0{o0.x + v[0][u].re + zx.x, o0.y + v[1][u].re + zx.y};
+                const Two<T> n1{o1.x + v[0][u].im + zy.x, o1.y + v[1][u].im + zy.y};
+                const Two<T> n2{o2.x + v[2][u].re + zz.x, o2.y + v[2][u].im + zz.y};
+                *d0 = n0;
+                *d1 = n1;
+                *d2 = n2;
+                drag_add(acc, fw, n0.x, n1.x, n2.x);
+                if (in[1]) drag_add(acc, fw >> 2, n0.y, n1.y, n2.y);
             } else {
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
@@ -210,60 +274,29 @@ __global__ void __launch_bounds__(256) k_dy(SpecArgs<T> a) {
                         if (in[1]) a.div[2][q + 1] += v[g][u].im;
                     }
                 }
+                if (s0 + G >= 3) {
+                    // the last group: add the vertical differences, then
+                    // every component of both columns is final
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        if (!in[h]) continue;
+                        const long qh = q + h;
+                        const T d0 = a.div[0][qh] + zdiff(a, 4, qh, k, true);
+                        const T d1 = a.div[1][qh] + zdiff(a, 5, qh, k, true);
+                        const T d2 = a.div[2][qh] + zdiff(a, 2, qh, k, false);
+                        a.div[0][qh] = d0;
+                        a.div[1][qh] = d1;
+                        a.div[2][qh] = d2;
+                        drag_add(acc, fw >> (2 * h), d0, d1, d2);
+                    }
+                }
             }
         }
     }
-}
-
-// Vertical staggered differences added to the horizontal parts, drag
-// partials per block (3 slots), then forcing in the blocks after the dense
-// ones (quarters of the forcing segments).
-constexpr int kZItems = 8;
-
-template <typename T, typename Acc>
-__global__ void __launch_bounds__(256) k_spec_z(ApplyArgs<T> a, int nzb) {
-    if ((int)blockIdx.x >= nzb) {
-        constexpr int kPiece = kSeg / 4;
-        for (long it = blockIdx.x - nzb; it < 4 * a.nfsegs; it += a.nfblocks) {
-            const Seg sg = a.fsegs[it >> 2];
-            const int off = (int)(it & 3) * kPiece;
-            if (off < sg.len)
-                force_seg<T>(a, Seg{sg.q + off, min(kPiece, sg.len - off), 0, 0}, threadIdx.x,
-                             blockDim.x);
-        }
-        return;
-    }
+    if (!z.drag) return;
     __shared__ double red[3][4];
-    // 32-bit offsets: a context holds fewer than 2^31 nodes
-    const int plane = (int)a.plane;
-    const int n = plane * a.nz;
-    Acc s0 = Acc(0), s1 = Acc(0), s2 = Acc(0);
-    const int q0 = blockIdx.x * blockDim.x * kZItems + threadIdx.x;
-    for (int it = 0; it < kZItems; ++it) {
-        const int q = q0 + it * blockDim.x;
-        if (q >= n) break;
-        const int k = q / plane;
-        const int rem = q - k * plane;
-        const int row = rem / a.nx;
-        const int xi = rem - row * a.nx;
-        const T xz_up = k + 1 < a.nz ? a.tau[4][q + plane] : T(0);
-        const T yz_up = k + 1 < a.nz ? a.tau[5][q + plane] : T(0);
-        const T zz_dn = k > 0 ? a.tau[2][q - plane] : T(0);
-        const T d0 = a.div[0][q] + (xz_up - a.tau[4][q]) * a.cz;
-        const T d1 = a.div[1][q] + (yz_up - a.tau[5][q]) * a.cz;
-        const T d2 = a.div[2][q] + (a.tau[2][q] - zz_dn) * a.cz;
-        a.div[0][q] = d0;
-        a.div[1][q] = d1;
-        a.div[2][q] = d2;
-        const uint32_t fb = a.fmask[(k * a.ny + row) * a.wrow + (xi >> 4)] >> (2 * (xi & 15));
-        if (!(fb & 1u)) {
-            s0 += (Acc)d0;
-            s1 += (Acc)d1;
-        }
-        if (!(fb & 2u)) s2 += (Acc)d2;
-    }
-    if (!a.drag) return;
-    const double w0 = wave_sum((double)s0), w1 = wave_sum((double)s1), w2 = wave_sum((double)s2);
+    const double w0 = wave_sum((double)acc[0]), w1 = wave_sum((double)acc[1]),
+                 w2 = wave_sum((double)acc[2]);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (lane == 0) {
         red[0][wv] = w0;
@@ -274,7 +307,7 @@ __global__ void __launch_bounds__(256) k_spec_z(ApplyArgs<T> a, int nzb) {
     if (threadIdx.x < 3) {
         double r = 0.0;
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += red[threadIdx.x][w];
-        a.partials[3L * blockIdx.x + threadIdx.x] = r;
+        z.partials[3L * blockIdx.x + threadIdx.x] = r;
     }
 }
 
@@ -327,38 +360,41 @@ int spectral_t(ibm_ctx* c, const void* const tau[6], void* const ustar[3],
     a.logx = lx;
     a.logy = ly;
     a.rows = (long)ny * nz;
+    a.plane = (long)nx * ny;
     a.kx = (T)(2.0 * M_PI / (nx * c->g.dx));
     a.ky = (T)(2.0 * M_PI / (ny * c->g.dy));
-    const int tx = 256 / (nx >= 8 ? nx / 8 : 1);            // teams per block
-    const long pairs = (a.rows + 1) / 2;
-    const dim3 gdx((unsigned)((pairs + tx - 1) / tx));
-    // one sequence's exchange space: exchanging all three at once measured
-    // slower here (more registers, fewer waves)
-    hipLaunchKernelGGL((k_dx<T, false>), gdx, dim3(256), spectral_lds_bytes(c, nx, 1), s, a);
+    a.cz = (T)(1.0 / c->g.dz);
+    ApplyArgs<T> z = make_apply_args<T>(c, c->cfg, tau, ustar, gradp, dt, div, drag);
     const int ty = 256 / (ny >= 8 ? ny / 8 : 1);
     const int groups = (nx + 2 * ty - 1) / (2 * ty);
-    const dim3 gdy((unsigned)(groups * nz));
+    const long nyb = (long)groups * nz;                     // y-pass blocks = drag slots
+    if (c->ap_cap < 3L * nyb) return fail(IBM_E_STATE, "apply_spectral: reduction slots not sized");
+    z.partials = c->ap_partials;
+    z.nfblocks = (int)std::min<long>((4 * c->nfsegs + 7) / 8 * 8, 2048);
+    const int tx = 256 / (nx >= 8 ? nx / 8 : 1);            // teams per block
+    const long pairs = (a.rows + 1) / 2;
+    const unsigned nrb = (unsigned)((pairs + tx - 1) / tx);
+    // one sequence's exchange space: exchanging all three at once measured
+    // slower here (more registers, fewer waves)
+    hipLaunchKernelGGL((k_dx<T, false>), dim3(nrb + (unsigned)z.nfblocks), dim3(256),
+                       spectral_lds_bytes(c, nx, 1), s, a, z, nrb);
     bool aligned = sizeof(T) == 4 && nx % 2 == 0;
     for (int i = 0; i < 6; ++i) aligned = aligned && (uintptr_t)tau[i] % (2 * sizeof(T)) == 0;
     for (int i = 0; i < 3; ++i) aligned = aligned && (uintptr_t)div[i] % (2 * sizeof(T)) == 0;
-    if (aligned)
-        hipLaunchKernelGGL((k_dy<T, false, sizeof(T) == 4>), gdy, dim3(256), spectral_lds_bytes(c, ny, 1), s, a);
+    const bool wide = c->precision == IBM_PREC_MIXED || sizeof(T) == 8;   // drag in double
+    const dim3 gdy((unsigned)nyb);
+    const size_t lds_y = spectral_lds_bytes(c, ny, 1);
+    if (aligned && wide)
+        hipLaunchKernelGGL((k_dy<T, false, sizeof(T) == 4, double>), gdy, dim3(256), lds_y, s, a, z);
+    else if (aligned)
+        hipLaunchKernelGGL((k_dy<T, false, sizeof(T) == 4, T>), gdy, dim3(256), lds_y, s, a, z);
+    else if (wide)
+        hipLaunchKernelGGL((k_dy<T, false, false, double>), gdy, dim3(256), lds_y, s, a, z);
     else
-        hipLaunchKernelGGL((k_dy<T, false, false>), gdy, dim3(256), spectral_lds_bytes(c, ny, 1), s, a);
-    ApplyArgs<T> z = make_apply_args<T>(c, c->cfg, tau, ustar, gradp, dt, div, drag);
-    const long n = c->n;
-    const int nzb = (int)((n + 256L * kZItems - 1) / (256L * kZItems));
-    if (c->ap_cap < 3L * nzb) return fail(IBM_E_STATE, "apply_spectral: reduction slots not sized");
-    z.partials = c->ap_partials;
-    z.nfblocks = (int)std::min<long>((4 * c->nfsegs + 7) / 8 * 8, 2048);
-    const unsigned grid = (unsigned)(nzb + z.nfblocks);
-    if (c->precision == IBM_PREC_MIXED || sizeof(T) == 8)
-        hipLaunchKernelGGL((k_spec_z<T, double>), dim3(grid), dim3(256), 0, s, z, nzb);
-    else
-        hipLaunchKernelGGL((k_spec_z<T, float>), dim3(grid), dim3(256), 0, s, z, nzb);
+        hipLaunchKernelGGL((k_dy<T, false, false, T>), gdy, dim3(256), lds_y, s, a, z);
     if (drag)
         hipLaunchKernelGGL(k_spec_finalize, dim3(1), dim3(256), 0, s, (const double*)z.partials,
-                           (long)nzb, z.dv, drag);
+                           nyb, z.dv, drag);
     IBM_HIP(hipGetLastError());
     return IBM_OK;
 }
@@ -402,7 +438,10 @@ size_t spectral_lds_bytes(const ibm_ctx* c, int n, int seqs) {
 }
 
 long spectral_slots(const ibm_ctx* c) {
-    return 3 * ((c->n + 256L * kZItems - 1) / (256L * kZItems));
+    // one per y-pass block and drag component
+    const int ny = c->g.ny, nx = c->g.nx;
+    const int ty = 256 / (ny >= 8 ? ny / 8 : 1);
+    return 3L * ((nx + 2 * ty - 1) / (2 * ty)) * c->g.nz;
 }
 
 void free_spectral(ibm_ctx* c) { free_spectral_tables(c); }

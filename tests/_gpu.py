@@ -21,10 +21,11 @@ def normwise(got, exp):
 
 
 def run_gpu(wl, dtype="f64", precision="plain", tile=None, stats=True, drag=True,
-            in_place=False, spectral=False):
+            in_place=False, spectral=False, offset=0):
     """One stage pass of the library (ibm_wall_stress then ibm_apply;
-    ``in_place``: ustar is u, v, w themselves); returns numpy outputs and the
-    context."""
+    ``in_place``: ustar is u, v, w themselves; ``offset`` > 0: the stacked
+    stresses, velocities, ustar and divergence start that many elements into
+    their buffers); returns numpy outputs and the context."""
     import paper_2006_03343_amd as ibm
     torch, dev = torch_dev()
     tdt = torch.float64 if dtype == "f64" else torch.float32
@@ -35,13 +36,20 @@ def run_gpu(wl, dtype="f64", precision="plain", tile=None, stats=True, drag=True
     if tile is not None:
         ctx.set_tile(*tile)
     ctx.prepare(T(wl.phi_uv), T(wl.phi_w), wl.band_width, wl.phi_c, wl.kappa)
-    tau = torch.stack([T(t) for t in wl.tau]).contiguous()
+    def stacked(arrs):
+        buf = torch.empty(len(arrs) * g.n + offset, dtype=tdt, device=dev)
+        view = buf[offset:].view(len(arrs), g.nz, g.ny, g.nx)
+        for i, a in enumerate(arrs):
+            view[i].copy_(a)
+        return view
+
+    tau = stacked([T(t) for t in wl.tau])
     st = torch.zeros(4, dtype=torch.float64, device=dev) if stats else None
     lz = T(wl.log_z0) if wl.log_z0 is not None else None
-    vel = torch.stack([T(wl.u), T(wl.v), T(wl.w)]).contiguous()
+    vel = stacked([T(wl.u), T(wl.v), T(wl.w)])
     u, v, w = vel
-    ustar = vel if in_place else vel.clone()
-    div = torch.empty_like(ustar)
+    ustar = vel if in_place else stacked(list(vel))
+    div = stacked([torch.zeros_like(u)] * 3)
     dr = torch.zeros(3, dtype=torch.float64, device=dev) if drag else None
     gp = [T(t) for t in wl.gradp] if wl.gradp is not None else None
     z0 = None if lz is not None else wl.z0

@@ -6,8 +6,10 @@ float64, 2e-5 for float32; masks and forcing exact).  The SGS stress inputs
 are white noise, so every case carries Nyquist-mode content: a leak of one
 packed field's Nyquist term into the other would show.  Cases: the cube,
 small hills in three precisions, per-node log z0, grids with one row, one
-column, one plane and two nodes, the 512 x 256 x 256 hill; a grid size that
-is not a power of two is refused.
+column, one plane and two nodes, the 512 x 256 x 256 hill, fields one
+element into their buffers (float32: the y pass then takes one column per
+access instead of 8-byte column pairs); a grid size that is not a power of
+two is refused.
 """
 import numpy as np
 import pytest
@@ -61,6 +63,18 @@ def test_degenerate_grids(ora):
         _say(f"spectral flat {shape} f64")
         out, _ = run_gpu(wl, "f64", spectral=True)
         compare(out, _ref(ora, wl), wl, TOL["f64"])
+
+
+def test_misaligned_views(ora):
+    wl = configs.hill(128, 64, 32, H=12.0, L=30.0, x0=40.0, y0=32.0).cast(np.float32)
+    _say("spectral hill 128x64x32 f32 mixed, fields one element into their buffers")
+    out, _ = run_gpu(wl, "f32", "mixed", spectral=True, offset=1)
+    ref = _ref(ora, wl)
+    errs = compare(out, ref, wl, TOL["f32"])
+    _say(f"errors {errs}")
+    base, _ = run_gpu(wl, "f32", "mixed", spectral=True)
+    for c in range(3):
+        assert np.abs(out["div"][c] - base["div"][c]).max() <= 1e-6 * np.abs(base["div"][c]).max()
 
 
 def test_not_a_power_of_two():
