@@ -289,7 +289,8 @@ def run_adjoint(steps, warmup):
 
 
 def run_sgs(wl, steps, warmup):
-    """ibm_sgs_stress on the hill (float32), alone and followed by the stage."""
+    """ibm_sgs_stress on the hill (float32), alone and followed by the stage;
+    the fused ibm_apply_sgs after the wall stress against that sequence."""
     import numpy as np
     import torch
 
@@ -328,9 +329,27 @@ def run_sgs(wl, steps, warmup):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / steps
 
+    fused = lambda: ctx.apply_sgs(pu, pw, u, v, w, taus, list(ustar), list(div), z0=wl.z0,
+                                  kappa=wl.kappa, gradp=gp, dt=wl.dt, drag=drag)
+
+    def fused_step():
+        ctx.wall_stress(u, v, w, taus, z0=wl.z0, stats=stats)
+        fused()
+
     ms_sgs = timed(sgs)
     ms_all = timed(step)
+    ms_fused_step = timed(fused_step)
+    ms_fused = timed(fused)
     gbs = g.n * 11 * 4 / (ms_sgs * 1e-3) / 1e9
+    # fused pass, algorithmic: u, v, w, phi_uv, phi_w and the class byte in,
+    # div out, the band stress at band nodes, forcing at forced nodes
+    mask = ctx.mask()
+    band_uv = int(((mask & 3) == 1).sum())
+    band_w = int((((mask >> 2) & 3) == 1).sum())
+    f_uv = int(((mask >> 4) & 1).sum())
+    f_w = int(((mask >> 5) & 1).sum())
+    fused_bytes = g.n * (5 * 4 + 1 + 3 * 4) + band_uv * 16 + band_w * 8 + f_uv * 16 + f_w * 8
+    fgbs = fused_bytes / (ms_fused * 1e-3) / 1e9
     del ctx, tau, ustar, div
     torch.cuda.empty_cache()
     return {"workload": f"hill {g.nx}x{g.ny}x{g.nz}, float32, cs 0.16, kappa {wl.kappa}",
@@ -339,7 +358,14 @@ def run_sgs(wl, steps, warmup):
                              "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
                              "bytes_per_launch": g.n * 11 * 4},
             "sgs_wall_stress_apply_ms": ms_all,
-            "sgs_wall_stress_apply_points_per_s": g.n / (ms_all * 1e-3)}
+            "sgs_wall_stress_apply_points_per_s": g.n / (ms_all * 1e-3),
+            "wall_stress_apply_sgs_ms": ms_fused_step,
+            "wall_stress_apply_sgs_points_per_s": g.n / (ms_fused_step * 1e-3),
+            "fused_over_sequence": ms_all / ms_fused_step,
+            "apply_sgs_ms": ms_fused,
+            "apply_sgs_roofline": {"bound": "hbm", "achieved": fgbs, "peak": HBM_PEAK_GBS,
+                                   "unit": "GB/s", "frac": fgbs / HBM_PEAK_GBS,
+                                   "bytes_per_launch": fused_bytes}}
 
 
 def run_spectral(wl, steps, warmup):
@@ -585,7 +611,10 @@ def main():
     if not args.no_sgs:
         out["sgs"] = run_sgs(wl, args.steps, args.warmup)
         log(f"sgs: {out['sgs']['sgs_ms']:.4f} ms ({out['sgs']['sgs_roofline']['frac'] * 100:.1f} % "
-            f"of HBM peak); sgs + stage {out['sgs']['sgs_wall_stress_apply_ms']:.4f} ms")
+            f"of HBM peak); sgs + stage {out['sgs']['sgs_wall_stress_apply_ms']:.4f} ms; "
+            f"wall stress + fused {out['sgs']['wall_stress_apply_sgs_ms']:.4f} ms (fused pass "
+            f"{out['sgs']['apply_sgs_ms']:.4f} ms, "
+            f"{out['sgs']['apply_sgs_roofline']['frac'] * 100:.1f} % of HBM peak)")
     if not args.no_spectral:
         out["spectral"] = run_spectral(wl, args.steps, args.warmup)
         log(f"spectral: {out['spectral']['ms']:.4f} ms per ibm_apply_spectral "

@@ -176,6 +176,24 @@ int ibm_sgs_stress(ibm_ctx* c, const void* phi_uv, const void* phi_w, const void
                    const void* v, const void* w, double z0, const void* log_z0, double cs,
                    double kappa, void* const tau[6], void* stream);
 
+/* ibm_sgs_stress and the dense pass of ibm_apply in one pass (§2.2 and §2.4,
+ * eq. u-*-IBM): the Smagorinsky stress is formed on the fly and never stored.
+ * The stress differentiated is, per node and node set, the band value in tau
+ * where the node is a band node of its grid (ibm_wall_stress must have filled
+ * tau there; tau is read nowhere else), 0 where it is solid, and the
+ * Smagorinsky stress of u, v, w elsewhere -- what ibm_sgs_stress followed by
+ * ibm_wall_stress leaves in tau, so div, the forcing of ustar and drag_dev are
+ * those of ibm_apply on that field.  Arguments as for ibm_sgs_stress and
+ * ibm_apply; needs a prepared context.  ustar, div and drag_dev are written
+ * while u, v, w, phi_uv, phi_w, log_z0 and tau are read by the same launch, so
+ * ustar and div may alias none of them.  Asynchronous on ``stream``.  Errors:
+ * IBM_E_STATE, IBM_E_ARG, IBM_E_RANGE. */
+int ibm_apply_sgs(ibm_ctx* c, const void* phi_uv, const void* phi_w, const void* u,
+                  const void* v, const void* w, double z0, const void* log_z0, double cs,
+                  double kappa, const void* const tau[6], void* const ustar[3],
+                  const void* const gradp[3], double dt, void* const div[3], double* drag_dev,
+                  void* stream);
+
 /* Reverse mode of one stage pass with respect to u, v, w and log z0, for a
  * single velocity state that is both sampled by the wall model and forced
  * (ustar == u).  Cotangents: g_tau[6] (array or entries may be NULL = 0) of

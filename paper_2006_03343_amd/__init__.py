@@ -232,6 +232,32 @@ class Context:
                                            float(cs), float(kappa), ptr_array(taus),
                                            self._stream()))
 
+    def apply_sgs(self, phi_uv, phi_w, u, v, w, tau, ustar, div, z0=None, log_z0=None, cs=0.16,
+                  kappa=0.4, gradp=None, dt=0.01, drag=None):
+        """``sgs_stress`` and ``apply`` in one pass: the Smagorinsky stress is
+        formed on the fly; ``tau`` supplies the band values written by
+        ``wall_stress``."""
+        if (z0 is None) == (log_z0 is None):
+            raise ValueError("give exactly one of z0 and log_z0")
+        taus = self._fields(tau, "tau", 6)
+        us = self._fields(ustar, "ustar", 3)
+        dv = self._fields(div, "div", 3)
+        gp = None
+        if gradp is not None:
+            gp = ptr_array([self._field(t, f"gradp[{i}]") for i, t in enumerate(gradp)])
+        dp = None
+        if drag is not None:
+            if drag.dtype != torch.float64 or drag.numel() < 3 or drag.device != self.device:
+                raise ValueError("drag must be a float64 device tensor with 3 elements")
+            dp = drag.data_ptr()
+        with torch.cuda.device(self.device):
+            check(self._lib.ibm_apply_sgs(self._h, self._field(phi_uv, "phi_uv"),
+                                          self._field(phi_w, "phi_w"), self._field(u, "u"),
+                                          self._field(v, "v"), self._field(w, "w"),
+                                          float(z0 or 0.0), self._field(log_z0, "log_z0"),
+                                          float(cs), float(kappa), ptr_array(taus), ptr_array(us),
+                                          gp, float(dt), ptr_array(dv), dp, self._stream()))
+
     def vjp(self, u, v, w, g_div, g_ustar, g_drag, z0=None, log_z0=None, g_tau=None):
         """Reverse mode of one pass (ustar == u): returns (gu, gv, gw, glog_z0 or None)."""
         if (z0 is None) == (log_z0 is None):

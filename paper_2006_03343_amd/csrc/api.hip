@@ -331,6 +331,47 @@ int ibm_sgs_stress(ibm_ctx* c, const void* phi_uv, const void* phi_w, const void
                       (hipStream_t)stream);
 }
 
+int ibm_apply_sgs(ibm_ctx* c, const void* phi_uv, const void* phi_w, const void* u,
+                  const void* v, const void* w, double z0, const void* log_z0, double cs,
+                  double kappa, const void* const tau[6], void* const ustar[3],
+                  const void* const gradp[3], double dt, void* const div[3], double* drag_dev,
+                  void* stream) {
+    g_err[0] = 0;
+    const char* fn = "ibm_apply_sgs";
+    int rc = check_ctx(c, true, fn);
+    if (rc) return rc;
+    if ((rc = check_field(c, phi_uv, fn, "phi_uv")) || (rc = check_field(c, phi_w, fn, "phi_w")) ||
+        (rc = check_field(c, u, fn, "u")) || (rc = check_field(c, v, fn, "v")) ||
+        (rc = check_field(c, w, fn, "w")))
+        return rc;
+    if (!tau || !ustar || !div) return fail(IBM_E_ARG, "%s: tau, ustar and div are required", fn);
+    if (!std::isfinite(dt)) return fail(IBM_E_ARG, "%s: dt must be finite", fn);
+    if (log_z0) {
+        if ((rc = check_field(c, log_z0, fn, "log_z0"))) return rc;
+    } else if (!finite_pos(z0)) {
+        return fail(IBM_E_RANGE, "%s: z0 must be finite and > 0 (got %g)", fn, z0);
+    }
+    if (!finite_pos(cs) || !finite_pos(kappa))
+        return fail(IBM_E_RANGE, "%s: cs and kappa must be finite and > 0", fn);
+    for (int i = 0; i < 6; ++i)
+        if ((rc = check_field(c, tau[i], fn, "tau[i]"))) return rc;
+    // read by the launch that writes ustar, div
+    const void* ins[12] = {u, v, w, phi_uv, phi_w, log_z0,
+                           tau[0], tau[1], tau[2], tau[3], tau[4], tau[5]};
+    for (int i = 0; i < 3; ++i) {
+        if ((rc = check_field(c, div[i], fn, "div[i]"))) return rc;
+        if ((rc = check_field(c, ustar[i], fn, "ustar[i]"))) return rc;
+        if (gradp && gradp[i] && (rc = check_field(c, gradp[i], fn, "gradp[i]"))) return rc;
+        for (const void* p : ins)
+            if (p && (p == div[i] || p == ustar[i]))
+                return fail(IBM_E_ARG, "%s: ustar and div may not alias an input", fn);
+    }
+    if (drag_dev && ((uintptr_t)drag_dev % 8)) return fail(IBM_E_ARG, "%s: drag_dev misaligned", fn);
+    DeviceScope dg(c->device);
+    return launch_sgs_apply(c, phi_uv, phi_w, u, v, w, z0, log_z0, cs, kappa, tau, ustar, gradp,
+                            dt, div, drag_dev, (hipStream_t)stream);
+}
+
 int ibm_set_tile(ibm_ctx* c, int vx, int ty, int kz, int wpb) {
     g_err[0] = 0;
     int rc = check_ctx(c, false, "ibm_set_tile");

@@ -180,6 +180,14 @@ int launch_ab2(ibm_ctx* c, const void* const u[3], const void* const rhs_now[3],
                const void* const rhs_prev[3], double dt, void* const ustar[3], hipStream_t s);
 void free_projection(ibm_ctx* c);
 
+// sgs_apply.hip
+long sgs_apply_blocks(const ibm_ctx* c);   // dense blocks = drag slots / 3
+int launch_sgs_apply(ibm_ctx* c, const void* phi_uv, const void* phi_w, const void* u,
+                     const void* v, const void* w, double z0, const void* log_z0, double cs,
+                     double kappa, const void* const tau[6], void* const ustar[3],
+                     const void* const gradp[3], double dt, void* const div[3], double* drag,
+                     hipStream_t s);
+
 // sgs.hip
 int launch_sgs(ibm_ctx* c, const TileCfg& cfg, const void* phi_uv, const void* phi_w,
                const void* u, const void* v, const void* w, double z0, const void* log_z0,

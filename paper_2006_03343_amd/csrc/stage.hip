@@ -143,8 +143,8 @@ int size_partials(ibm_ctx* c) {
     // views, so size its slots for vx = 1 at the current ty and kz
     TileCfg one = c->cfg;
     one.vx = 1;
-    const long need_ap = std::max(3 * std::max(apply_tiles(c, c->cfg), apply_tiles(c, one)),
-                                  spectral_slots(c));
+    const long need_ap = std::max({3 * std::max(apply_tiles(c, c->cfg), apply_tiles(c, one)),
+                                   spectral_slots(c), 3 * sgs_apply_blocks(c)});
     const long need_ws = 4 * band_blocks(c);
     if (need_ap <= c->ap_cap && need_ws <= c->ws_cap) return IBM_OK;
     IBM_HIP(hipDeviceSynchronize());
