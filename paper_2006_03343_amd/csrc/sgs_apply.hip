@@ -118,8 +118,14 @@ __device__ inline void load_plane(const FusedArgs<T>& a, int k, int rm, int r0, 
     in.pu = vload<T, VX>(a.phi_uv + q);
     in.pw = vload<T, VX>(a.phi_w + q);
     in.lz = a.log_z0 ? vload<T, VX>(a.log_z0 + q) : vzero<T, VX>();
+    if constexpr (VX == 2) {
+        const uint32_t two = *reinterpret_cast<const uint16_t*>(a.ap.mask + q);   // q is even
+        in.m[0] = two & 0xffu;
+        in.m[1] = two >> 8;
+    } else {
 #pragma unroll
-    for (int e = 0; e < VX; ++e) in.m[e] = a.ap.mask[q + e];
+        for (int e = 0; e < VX; ++e) in.m[e] = a.ap.mask[q + e];
+    }
 }
 
 template <typename T, typename Acc, int VX>
@@ -289,29 +295,54 @@ __global__ void __launch_bounds__(64 * kWaves) k_sgs_apply(FusedArgs<T> a) {
         if (k < kend) load_plane<T, VX>(a, k + 1, rm, r0, rp, x, in);
         const Vec<T, VX> dxz = xd(t[4]), dxx_p = xd(xx_p), dxy_p = xd(xy_p);
         const bool zout = k >= kb && k < ke, xyout = k >= 1 && k - 1 >= kb && k - 1 < ke;
+        if (row_out) {
+            bool all = true;
 #pragma unroll
-        for (int e = 0; e < VX; ++e) {
-            if (!outn[e]) continue;
-            const int n = VX * lane + e;
+            for (int e = 0; e < VX; ++e) all = all && outn[e];
             if (zout) {
                 // w divergence of plane k
-                const T dyz = sh[b][2][wv + 1][n] - sh[b][2][wv - 1][n];
-                const T dz = dxz.v[e] * a.cx + dyz * a.cy + (t[2].v[e] - zz_p.v[e]) * a.cz;
-                ap.div[2][q + e] = dz;
-                if (!(m[e] & 32u)) s2 += (Acc)dz;
+                Vec<T, VX> dz;
+#pragma unroll
+                for (int e = 0; e < VX; ++e) {
+                    const int n = VX * lane + e;
+                    const T dyz = sh[b][2][wv + 1][n] - sh[b][2][wv - 1][n];
+                    dz.v[e] = dxz.v[e] * a.cx + dyz * a.cy + (t[2].v[e] - zz_p.v[e]) * a.cz;
+                    if (outn[e] && !(m[e] & 32u)) s2 += (Acc)dz.v[e];
+                }
+                if (all) {
+                    vstore_nt<T, VX>(ap.div[2] + q, dz);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VX; ++e)
+                        if (outn[e]) ap.div[2][q + e] = dz.v[e];
+                }
             }
             if (xyout) {
                 // uv divergence of plane k-1 (tau_xz, tau_yz of w planes k-1 and k)
-                const int qp = q + e - plane;
-                const T dx = dxx_p.v[e] * a.cx + (sh[bp][0][wv + 1][n] - sh[bp][0][wv - 1][n]) * a.cy +
-                             (t[4].v[e] - xz_p.v[e]) * a.cz;
-                const T dy = dxy_p.v[e] * a.cx + (sh[bp][1][wv + 1][n] - sh[bp][1][wv - 1][n]) * a.cy +
-                             (t[5].v[e] - yz_p.v[e]) * a.cz;
-                ap.div[0][qp] = dx;
-                ap.div[1][qp] = dy;
-                if (!(m_p[e] & 16u)) {
-                    s0 += (Acc)dx;
-                    s1 += (Acc)dy;
+                Vec<T, VX> dx, dy;
+#pragma unroll
+                for (int e = 0; e < VX; ++e) {
+                    const int n = VX * lane + e;
+                    dx.v[e] = dxx_p.v[e] * a.cx + (sh[bp][0][wv + 1][n] - sh[bp][0][wv - 1][n]) * a.cy +
+                              (t[4].v[e] - xz_p.v[e]) * a.cz;
+                    dy.v[e] = dxy_p.v[e] * a.cx + (sh[bp][1][wv + 1][n] - sh[bp][1][wv - 1][n]) * a.cy +
+                              (t[5].v[e] - yz_p.v[e]) * a.cz;
+                    if (outn[e] && !(m_p[e] & 16u)) {
+                        s0 += (Acc)dx.v[e];
+                        s1 += (Acc)dy.v[e];
+                    }
+                }
+                const int qp = q - plane;
+                if (all) {
+                    vstore_nt<T, VX>(ap.div[0] + qp, dx);
+                    vstore_nt<T, VX>(ap.div[1] + qp, dy);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VX; ++e) {
+                        if (!outn[e]) continue;
+                        ap.div[0][qp + e] = dx.v[e];
+                        ap.div[1][qp + e] = dy.v[e];
+                    }
                 }
             }
         }
