@@ -524,6 +524,45 @@ def cpu_baseline(wl, budget_s=12.0, max_passes=40):
                        f"(wall stress, divergence, forcing, drag), {t_total:.1f} s")
 
 
+def _oracle_rate(fn, points, what, budget_s=3.0):
+    """The oracle timed beside a GPU leg: repeated calls within ``budget_s``."""
+    import oracle
+    calls, t = 0, 0.0
+    while calls < 20 and t < budget_s:
+        t0 = time.perf_counter()
+        fn()
+        t += time.perf_counter() - t0
+        calls += 1
+    return dict(value=points * calls / t, unit="grid-points/s", cores=oracle.num_threads(),
+                kind="oracle", sample=f"{calls} call(s) on {what}, {t:.1f} s")
+
+
+def cpu_oracle_rows(wl):
+    """The oracle of the Smagorinsky stress, the spectral stage and the
+    pressure projection, each on a bounded sample."""
+    import numpy as np
+
+    import oracle
+    from workloads import Grid, configs
+    g = wl.grid
+    out = {}
+    out["sgs"] = _oracle_rate(
+        lambda: oracle.smagorinsky(g, wl.phi_uv, wl.phi_w, wl.u, wl.v, wl.w, z0=wl.z0,
+                                   kappa=wl.kappa),
+        g.n, f"the {g.nx}x{g.ny}x{g.nz} hill (FP64 C, OpenMP)")
+    ws = configs.hill(256, 128, 128, H=16.0, L=40.0, x0=64.0, y0=64.0)
+    out["spectral"] = _oracle_rate(lambda: oracle.stage_spectral(ws), ws.grid.n,
+                                   "a 256x128x128 hill (wall stress, FFT divergence, forcing, "
+                                   "drag; FP64)")
+    gp = Grid(128, 64, 64)
+    vel = list(np.random.default_rng(1).standard_normal((3,) + gp.shape))
+    vel[2][0] = 0.0
+    out["projection"] = _oracle_rate(lambda: oracle.pressure_project(gp, vel, wl.dt), gp.n,
+                                     "a 128x64x64 grid (FP64 FFTs, a dense solve per mode: "
+                                     "its cost grows as nz^3)")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -630,6 +669,11 @@ def main():
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(wl)
         log(f"cpu: {out['cpu_baseline']}")
+        rows = cpu_oracle_rows(wl)
+        for leg in ("sgs", "spectral", "projection"):
+            if leg in out:
+                out[leg]["cpu_oracle"] = rows[leg]
+        log(f"cpu oracle beside the legs: {rows}")
     if args.calib_copy:
         src = torch.ones(3 << 25, dtype=torch.float32, device="cuda")    # 402,653,184 bytes
         dst = torch.empty_like(src)
