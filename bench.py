@@ -518,10 +518,34 @@ def cpu_baseline(wl, budget_s=12.0, max_passes=40):
         oracle.drag(g, wl.phi_uv, wl.phi_w, div)
         t_total += time.perf_counter() - t0
         passes += 1
-    return dict(value=g.n * passes / t_total, unit="grid-points/s", cores=oracle.num_threads(),
+    cores = oracle.num_threads()
+    # the same pass with one thread, on a 256 x 128 x 128 hill
+    from workloads import configs
+    ws = configs.hill(256, 128, 128, H=16.0, L=40.0, x0=64.0, y0=64.0)
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        tau1, _ = oracle.wall_stress(ws.grid, ws.band_width, ws.phi_c, ws.kappa, ws.phi_uv,
+                                     ws.phi_w, ws.u, ws.v, ws.w, ws.z0, ws.log_z0, ws.tau)
+        div1 = oracle.divergence(ws.grid, tau1)
+        oracle.forcing(ws.grid, ws.phi_uv, ws.phi_w, (ws.u, ws.v, ws.w), ws.gradp, ws.dt)
+        oracle.drag(ws.grid, ws.phi_uv, ws.phi_w, div1)
+        t1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(cores)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    return dict(value=g.n * passes / t_total, unit="grid-points/s", cores=cores,
                 kind="oracle",
                 sample=f"{passes} full FP64 pass(es) of the {g.nx}x{g.ny}x{g.nz} hill "
-                       f"(wall stress, divergence, forcing, drag), {t_total:.1f} s")
+                       f"(wall stress, divergence, forcing, drag), {t_total:.1f} s",
+                single_thread={"value": ws.grid.n / t1, "unit": "grid-points/s", "cores": 1,
+                               "sample": f"one pass of a 256x128x128 hill, {t1:.1f} s"},
+                host={"cpu": model, "nproc": os.cpu_count()})
 
 
 def _oracle_rate(fn, points, what, budget_s=3.0):

@@ -62,12 +62,18 @@ def lib():
         L.ora_smagorinsky.argtypes = [vp, c_double, c_double, vp, vp, vp, vp, vp, c_double, vp,
                                       vp]
         L.ora_num_threads.restype = c_int
+        L.ora_set_threads.argtypes = [c_int]
         _lib = L
     return _lib
 
 
 def num_threads():
     return lib().ora_num_threads()
+
+
+def set_threads(n):
+    """OpenMP threads of the following calls (for timing)."""
+    lib().ora_set_threads(int(n))
 
 
 # ------------------------------------------------------------------ helpers

@@ -41,6 +41,15 @@ int ora_num_threads(void) {
 #endif
 }
 
+/* Threads for the following parallel loops (timing with one thread). */
+void ora_set_threads(int n) {
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------- §3.3 classes */
 int ora_uv_class(double phi, double band_width) {
     if (phi < 0.0) return ORA_SOLID;

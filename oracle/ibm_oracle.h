@@ -128,6 +128,7 @@ void ora_smagorinsky(const ora_grid* g, double cs, double kappa, const double* p
                      double z0, const double* log_z0, double* const tau[6]);
 
 int ora_num_threads(void);
+void ora_set_threads(int n);
 
 #ifdef __cplusplus
 }
