@@ -7,7 +7,8 @@ divergence, forcing, drag).  Bars as for the stage: div normwise per component
 <= 1e-12 (float64) and 2e-5 (float32), ustar likewise, drag within tol * dV *
 sum |div|.  The tau buffers hold noise before ibm_wall_stress, so a read of
 tau anywhere but a band node would show.  Cases: the cube, a ragged ridge
-(several x segments of 62 nodes, the last one short), a small hill in three
+(several x segments, the last one short), the same with an odd nx (float, one
+node per lane), a small hill in three
 precisions, a per-node log z0 field, grids of one column, one row, one or
 two planes and two rows, the 512 x 256 x 256 hill; the fused pass against
 ibm_sgs_stress + ibm_wall_stress + ibm_apply on the GPU; error paths.
@@ -90,6 +91,14 @@ def test_cube_f64(ora):
 def test_ragged_ridge(ora):
     wl = configs.ridge(100, 36, 40, H=8.0, L=20.0, x0=30.0).cast(np.float32)
     _say("sgs+apply ridge 100x36x40 f32 mixed")
+    _, errs = _check(ora, wl, "f32", "mixed")
+    _say(f"errors {errs}")
+
+
+def test_odd_nx_float(ora):
+    """Float with an odd nx: one node per lane (the two-node path needs nx even)."""
+    wl = configs.ridge(99, 36, 40, H=8.0, L=20.0, x0=30.0).cast(np.float32)
+    _say("sgs+apply ridge 99x36x40 f32 mixed (one node per lane)")
     _, errs = _check(ora, wl, "f32", "mixed")
     _say(f"errors {errs}")
 
