@@ -456,10 +456,12 @@ def run_projection(wl, steps, warmup):
     # the projection reads u*, v*, w* and writes u, v, w, p
     ab2_bytes = g.n * 4 * 4 * 3
     proj_bytes = g.n * 4 * 7
-    # what the passes move: forward x (4 + 8) and y (8 + 8) per field, the
-    # solve (24 + 24 read, 24 + 24 written), inverse y (16 per field),
-    # inverse x (12 for p, 16 for u and v), the w correction (4 + 4 + 4)
-    pass_bytes = g.n * (3 * 12 + 3 * 16 + 96 + 3 * 16 + 12 + 2 * 16 + 12)
+    # what the passes move per node over half spectra (about 4 B per node per
+    # complex field): forward x 24 (u*, v*, w* in, three spectra out),
+    # forward y 20 (three in; H, w_hat out), the solve 24, inverse y 12 (p_hat
+    # in; P, DY out), inverse x 32 (P twice, DY, u*, v* in; p, u, v out), the
+    # w correction 12
+    pass_bytes = g.n * (24 + 20 + 24 + 12 + 32 + 12)
     del ctx, vel, rn, rp, ustar, uo, p
     torch.cuda.empty_cache()
     gbs = lambda b, ms: b / (ms * 1e-3) / 1e9
@@ -470,9 +472,9 @@ def run_projection(wl, steps, warmup):
             "project_algorithmic_GBs": gbs(proj_bytes, proj_ms),
             "project_algorithmic_frac": gbs(proj_bytes, proj_ms) / HBM_PEAK_GBS,
             "project_pass_GBs": gbs(pass_bytes, proj_ms),
-            "note": "projection: 12 launches (6 forward transforms, solve, 3 inverse y, "
-                    "3 inverse x, w correction); algorithmic bytes 28 per node, the passes "
-                    f"move {pass_bytes // g.n} per node"}
+            "note": "projection: 6 launches (x forward, y forward, solve, y inverse, x "
+                    "inverse, w correction) over half spectra; algorithmic bytes 28 per node, "
+                    f"the passes move {pass_bytes // g.n} per node"}
 
 
 def run_terrains(steps, warmup):
