@@ -167,7 +167,9 @@ int ibm_pressure_project(ibm_ctx* c, const void* const ustar[3], double dt, void
  * outside 0 <= k < nz taken as 0); |S| = sqrt(2 S:S) with the components of
  * the other node set averaged from its two neighbouring planes; 1/lambda^2 =
  * 1/(cs (dx dy dz)^(1/3))^2 + 1/(kappa (phi + z0))^2, lambda = 0 where
- * phi + z0 <= 0; tau = -2 lambda^2 |S| S, all six components written.
+ * phi + z0 <= 0; tau = -2 lambda^2 |S| S, all six components written.  In
+ * float the reciprocal in lambda^2 and the square root are the hardware's
+ * (1 ulp), in double correctly rounded.
  * z0: scalar (> 0), used when log_z0 == NULL; log_z0: per-node ln z0 field
  * or NULL.  Needs a context, not a prepare.  tau may alias no input.
  * Asynchronous on ``stream``.  Errors: IBM_E_ARG (NULL or aliased fields),
@@ -187,7 +189,9 @@ int ibm_sgs_stress(ibm_ctx* c, const void* phi_uv, const void* phi_w, const void
  * ibm_apply; needs a prepared context.  ustar, div and drag_dev are written
  * while u, v, w, phi_uv, phi_w, log_z0 and tau are read by the same launch, so
  * ustar and div may alias none of them.  Asynchronous on ``stream``.  Errors:
- * IBM_E_STATE, IBM_E_ARG, IBM_E_RANGE. */
+ * IBM_E_STATE, IBM_E_ARG (also: an x-y plane of more than (2^32 - 1) / 5
+ * bytes, beyond the pass's 32-bit offsets within a block's planes),
+ * IBM_E_RANGE. */
 int ibm_apply_sgs(ibm_ctx* c, const void* phi_uv, const void* phi_w, const void* u,
                   const void* v, const void* w, double z0, const void* log_z0, double cs,
                   double kappa, const void* const tau[6], void* const ustar[3],

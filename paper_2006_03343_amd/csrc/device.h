@@ -63,6 +63,47 @@ __device__ inline Vec<T, VX> vzero() {
     return r;
 }
 
+// A raw buffer resource (stride 0, no range limit) whose base is a
+// wave-uniform pointer: loads through it take the lane's byte offset in a
+// vector register and a uniform byte offset in a scalar register, so a wave
+// that marches through rows and planes adds offsets in scalar registers only.
+// Offsets are 32-bit: base + offsets must stay within 4 GiB of the base.
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+
+__device__ inline Rsrc buffer_rsrc(const void* base) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, -1, 0x00020000);
+}
+
+template <typename T, int VX>
+__device__ inline Vec<T, VX> bload(Rsrc r, unsigned lane_off, unsigned uniform_off) {
+    constexpr int B = (int)sizeof(T) * VX;
+    static_assert(B == 4 || B == 8 || B == 16, "bload: 4, 8 or 16 bytes per lane");
+    Vec<T, VX> out;
+    if constexpr (B == 4) {
+        const auto x = __builtin_amdgcn_raw_buffer_load_b32(r, (int)lane_off, (int)uniform_off, 0);
+        __builtin_memcpy(out.v, &x, 4);
+    } else if constexpr (B == 8) {
+        const auto x = __builtin_amdgcn_raw_buffer_load_b64(r, (int)lane_off, (int)uniform_off, 0);
+        __builtin_memcpy(out.v, &x, 8);
+    } else {
+        const auto x = __builtin_amdgcn_raw_buffer_load_b128(r, (int)lane_off, (int)uniform_off, 0);
+        __builtin_memcpy(out.v, &x, 16);
+    }
+    return out;
+}
+
+__device__ inline uint32_t bload_u8(Rsrc r, unsigned lane_off, unsigned uniform_off) {
+    return __builtin_amdgcn_raw_buffer_load_b8(r, (int)lane_off, (int)uniform_off, 0);
+}
+
+// n / d and sqrt(x) for the eddy viscosity: in float the hardware's reciprocal
+// and square root (1 ulp each, a few instructions fewer than the correctly
+// rounded sequences), in double the correctly rounded operations.
+__device__ inline float quot_fast(float n, float d) { return n * __builtin_amdgcn_rcpf(d); }
+__device__ inline double quot_fast(double n, double d) { return n / d; }
+__device__ inline float sqrt_fast(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ inline double sqrt_fast(double x) { return __builtin_sqrt(x); }
+
 // Butterfly sum / max over the 64 lanes of a wave (fixed order: deterministic).
 __device__ inline double wave_sum(double x) {
 #pragma unroll

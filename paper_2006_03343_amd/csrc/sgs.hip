@@ -74,13 +74,15 @@ __device__ inline Rows<T, VX> zero_rows() {
     return r;
 }
 
-// lambda^2 of eq. smag-1 (n = 2)
+// lambda^2 of eq. smag-1 (n = 2): 1 / (1/lambda_0^2 + 1/w^2) written as
+// w^2 / (w^2/lambda_0^2 + 1), one quotient, with w = kappa (phi + z0)
 template <typename T>
 __device__ inline T mixing_sq(const SgsArgs<T>& a, T d, T z0) {
     const T s = d + z0;
     if (!(s > T(0))) return T(0);
     const T wl = a.kappa * s;
-    return T(1) / (a.inv_l0sq + T(1) / (wl * wl));
+    const T w2 = wl * wl;
+    return quot_fast(w2, a.inv_l0sq * w2 + T(1));
 }
 
 template <typename T, int VX>
@@ -193,7 +195,7 @@ __device__ inline void sgs_tile(const SgsArgs<T>& a, long tile, int lane) {
             const T s23 = half * (Wst[1].v[e] + N[1].v[e]);
             const T ss = S[0].v[e] * S[0].v[e] + S[1].v[e] * S[1].v[e] + S[2].v[e] * S[2].v[e] +
                          T(2) * (S[3].v[e] * S[3].v[e] + s13 * s13 + s23 * s23);
-            const T nu = mixing_sq(a, pu.v[e], z0) * sqrt(T(2) * ss);
+            const T nu = mixing_sq(a, pu.v[e], z0) * sqrt_fast(T(2) * ss);
 #pragma unroll
             for (int c = 0; c < 4; ++c) t[c].v[e] = T(-2) * nu * S[c].v[e];
             // w node k: S11, S22, S33, S12 from the uv nodes k-1 and k
@@ -202,7 +204,7 @@ __device__ inline void sgs_tile(const SgsArgs<T>& a, long tile, int lane) {
             for (int c = 0; c < 4; ++c) m[c] = half * (P[c].v[e] + S[c].v[e]);
             const T sw = m[0] * m[0] + m[1] * m[1] + m[2] * m[2] +
                          T(2) * (m[3] * m[3] + Wst[0].v[e] * Wst[0].v[e] + Wst[1].v[e] * Wst[1].v[e]);
-            const T nuw = mixing_sq(a, pw.v[e], z0) * sqrt(T(2) * sw);
+            const T nuw = mixing_sq(a, pw.v[e], z0) * sqrt_fast(T(2) * sw);
             t[4].v[e] = T(-2) * nuw * Wst[0].v[e];
             t[5].v[e] = T(-2) * nuw * Wst[1].v[e];
         }

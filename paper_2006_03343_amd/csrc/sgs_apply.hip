@@ -10,19 +10,24 @@
 // followed by ibm_wall_stress leaves in tau.
 //
 // A block of kWaves waves owns kRows rows j0 .. j0+kRows-1 of an x segment
-// and a chunk of kz planes.  Wave wv computes the stress of row j0-1+wv (the
-// two outer waves: the y halo) on 64 * VX consecutive nodes, the segment and
-// H nodes on either side (H = max(2, VX)), exactly as the Smagorinsky kernel
-// does for one row.  The strain, and with it the stress, is wrong on the
-// outermost node of each side, which no output needs: x differences come
-// from the adjacent lanes without edge loads.  Per plane the components
-// differenced in y (tau_xy, tau_yy on uv nodes, tau_yz on w nodes) go
-// through LDS (three plane buffers, so one barrier per plane suffices), z
+// and a chunk of planes.  Wave wv computes the stress of row j0-1+wv (the
+// two outer waves: the y halo) on 64 consecutive nodes, one per lane: the
+// segment's 60 and 2 on either side.  The strain, and with it the stress, is
+// wrong on the outermost node of each side, which no output needs: x
+// differences come from the adjacent lanes without edge loads.  Per plane the
+// components differenced in y (tau_xy, tau_yy on uv nodes, tau_yz on w nodes)
+// go through LDS (three plane buffers, so one barrier per plane suffices), z
 // differences stay in registers.  The uv divergence of plane k needs tau_xz,
 // tau_yz on w plane k+1, which the march reaches one plane later, so it is
 // formed one plane behind the w divergence; a chunk starts one plane below
 // its first (the march state rebuilt from the velocities there) and, unless
 // it is the top one, ends one plane above its last.
+//
+// Loads go through buffer resources based at the block's slab of planes, so
+// a wave adds row and plane offsets in scalar registers; in float a plane's
+// loads are issued two planes ahead of its arithmetic.  The work is the
+// Smagorinsky arithmetic of 8 rows for 6 and 64 nodes for 60: the pass is
+// bound by vector-ALU issue, not by HBM.
 //
 // Bytes per node: u, v, w, phi_uv, phi_w (log z0) in, the class byte, the
 // band stress where there is one, div out; the halo rows and columns of a
@@ -41,7 +46,7 @@ namespace {
 
 constexpr int kRows = 6;             // divergence rows per block (8 waves: two blocks per CU)
 constexpr int kWaves = kRows + 2;    // one stress row per wave: rows j0-1 .. j0+kRows
-constexpr int kChunk = 32;           // planes per block
+constexpr int kChunk = 32;           // planes per block (fewer where a slab passes 4 GiB)
 
 template <int VX>
 constexpr int halo() { return VX > 2 ? VX : 2; }
@@ -56,18 +61,21 @@ struct FusedArgs {
     T inv_l0sq;              // 1 / lambda_0^2
     T kappa, z0;
     int nxs, njb;            // x segments, row blocks
+    int kc;                  // planes per block
     int nblocks;             // dense blocks (nxs * njb * z chunks)
     int per_xcd;             // logical dense blocks per XCD
     ApplyArgs<T> ap;         // tau (band values), ustar, gradp, div, mask, forcing segments, drag
 };
 
-// lambda^2 of eq. smag-1 (n = 2)
+// lambda^2 of eq. smag-1 (n = 2): 1 / (1/lambda_0^2 + 1/w^2) written as
+// w^2 / (w^2/lambda_0^2 + 1), one quotient, with w = kappa (phi + z0)
 template <typename T>
 __device__ inline T mixing_sq(const FusedArgs<T>& a, T d, T z0) {
     const T s = d + z0;
     if (!(s > T(0))) return T(0);
     const T wl = a.kappa * s;
-    return T(1) / (a.inv_l0sq + T(1) / (wl * wl));
+    const T w2 = wl * wl;
+    return quot_fast(w2, a.inv_l0sq * w2 + T(1));
 }
 
 __device__ inline int wrap(int i, int n) {
@@ -81,12 +89,23 @@ struct Row3 {
     Vec<T, VX> m, c, p;
 };
 
+// The input fields over a block's slab -- its chunk of planes, two planes
+// below and one above -- as buffer resources based at the slab's first plane
+// kbase: a load takes the lane's byte offset and a uniform byte offset within
+// the slab (32-bit; the host keeps a slab under 4 GiB).
+struct SlabIn {
+    Rsrc u, v, w, pu, pw, lz, mask;
+};
+
+// rows rm, r0, rp of the slab plane starting at node pk, at the lane's byte offset xo
 template <typename T, int VX>
-__device__ inline Row3<T, VX> load3(const T* __restrict__ f, int pk, int rm, int r0, int rp, int x) {
+__device__ inline Row3<T, VX> load3(Rsrc f, unsigned pk, unsigned rm, unsigned r0, unsigned rp,
+                                   unsigned xo) {
+    constexpr unsigned S = sizeof(T);
     Row3<T, VX> r;
-    r.m = vload<T, VX>(f + pk + rm + x);
-    r.c = vload<T, VX>(f + pk + r0 + x);
-    r.p = vload<T, VX>(f + pk + rp + x);
+    r.m = bload<T, VX>(f, xo, (pk + rm) * S);
+    r.c = bload<T, VX>(f, xo, (pk + r0) * S);
+    r.p = bload<T, VX>(f, xo, (pk + rp) * S);
     return r;
 }
 
@@ -106,30 +125,31 @@ struct PlaneIn {
 };
 
 template <typename T, int VX>
-__device__ inline void load_plane(const FusedArgs<T>& a, int k, int rm, int r0, int rp, int x,
+__device__ inline void load_plane(const FusedArgs<T>& a, const SlabIn& sl, int k, int kbase,
+                                  unsigned rm, unsigned r0, unsigned rp, unsigned x,
                                   PlaneIn<T, VX>& in) {
-    const int pk = k * a.plane, q = pk + r0 + x;
+    static_assert(VX == 1, "one node per lane");
+    constexpr unsigned S = sizeof(T);
+    const unsigned pk = (unsigned)(k - kbase) * (unsigned)a.plane;   // plane k in the slab
+    const unsigned pn = pk + (unsigned)a.plane;
+    const unsigned xo = x * S;
     const bool up = k + 1 < a.nz;
-    in.U = load3<T, VX>(a.u, pk, rm, r0, rp, x);
-    in.V = load3<T, VX>(a.v, pk, rm, r0, rp, x);
-    in.Wn = up ? load3<T, VX>(a.w, pk + a.plane, rm, r0, rp, x) : zero3<T, VX>();
-    in.un = up ? vload<T, VX>(a.u + q + a.plane) : vzero<T, VX>();
-    in.vn = up ? vload<T, VX>(a.v + q + a.plane) : vzero<T, VX>();
-    in.pu = vload<T, VX>(a.phi_uv + q);
-    in.pw = vload<T, VX>(a.phi_w + q);
-    in.lz = a.log_z0 ? vload<T, VX>(a.log_z0 + q) : vzero<T, VX>();
-    if constexpr (VX == 2) {
-        const uint32_t two = *reinterpret_cast<const uint16_t*>(a.ap.mask + q);   // q is even
-        in.m[0] = two & 0xffu;
-        in.m[1] = two >> 8;
-    } else {
-#pragma unroll
-        for (int e = 0; e < VX; ++e) in.m[e] = a.ap.mask[q + e];
-    }
+    in.U = load3<T, VX>(sl.u, pk, rm, r0, rp, xo);
+    in.V = load3<T, VX>(sl.v, pk, rm, r0, rp, xo);
+    in.Wn = up ? load3<T, VX>(sl.w, pn, rm, r0, rp, xo) : zero3<T, VX>();
+    in.un = up ? bload<T, VX>(sl.u, xo, (pn + r0) * S) : vzero<T, VX>();
+    in.vn = up ? bload<T, VX>(sl.v, xo, (pn + r0) * S) : vzero<T, VX>();
+    in.pu = bload<T, VX>(sl.pu, xo, (pk + r0) * S);
+    in.pw = bload<T, VX>(sl.pw, xo, (pk + r0) * S);
+    in.lz = a.log_z0 ? bload<T, VX>(sl.lz, xo, (pk + r0) * S) : vzero<T, VX>();
+    in.m[0] = bload_u8(sl.mask, x, pk + r0);
 }
 
-template <typename T, typename Acc, int VX>
-__global__ void __launch_bounds__(64 * kWaves) k_sgs_apply(FusedArgs<T> a) {
+// PF: how many planes ahead of the march a plane's loads are issued
+template <typename T, typename Acc, int VX, int PF>
+__global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(4)))
+k_sgs_apply(FusedArgs<T> a) {
+    static_assert(PF == 1 || PF == 2, "loads one or two planes ahead");
     constexpr int H = halo<VX>(), SPAN = span<VX>();
     const ApplyArgs<T>& ap = a.ap;
     const int dense = 8 * a.per_xcd;
@@ -156,17 +176,29 @@ __global__ void __launch_bounds__(64 * kWaves) k_sgs_apply(FusedArgs<T> a) {
     const int nx = a.nx, ny = a.ny, nz = a.nz, plane = a.plane;
     const int xs = lb % a.nxs, t2 = lb / a.nxs;
     const int jb = t2 % a.njb, kc = t2 / a.njb;
-    const int kb = kc * kChunk, ke = min(kb + kChunk, nz);
+    const int kb = kc * a.kc, ke = min(kb + a.kc, nz);
     const int x0 = xs * SPAN;
     const int jr = jb * kRows - 1 + wv;                  // this wave's row, unwrapped
     const int j = wrap(jr, ny);
     const int xb = x0 - H + VX * lane;                   // this lane's first node, unwrapped
-    const int x = wrap(xb, nx);                          // nx % VX == 0: no wrap inside the lane
+    const unsigned x = wrap(xb, nx);                     // nx % VX == 0: no wrap inside the lane
+    const unsigned xo = x * (unsigned)sizeof(T);        // its byte offset in a row (loads)
     const bool row_out = wv >= 1 && wv <= kRows && jr < ny;
     bool outn[VX];
 #pragma unroll
     for (int e = 0; e < VX; ++e) outn[e] = row_out && xb + e >= x0 && xb + e < min(x0 + SPAN, nx);
     const int rm = wrap(j - 1, ny) * nx, r0 = j * nx, rp = wrap(j + 1, ny) * nx;
+    // the slab: planes kbase .. ke + 1 of every input field
+    const int kbase = max(kb - 2, 0);
+    const long sb = (long)kbase * plane;
+    SlabIn sl;
+    sl.u = buffer_rsrc(a.u + sb);
+    sl.v = buffer_rsrc(a.v + sb);
+    sl.w = buffer_rsrc(a.w + sb);
+    sl.pu = buffer_rsrc(a.phi_uv + sb);
+    sl.pw = buffer_rsrc(a.phi_w + sb);
+    sl.lz = buffer_rsrc(a.log_z0 ? a.log_z0 + sb : a.u + sb);
+    sl.mask = buffer_rsrc(ap.mask + sb);
     const bool last = lane == 63;
     const T half = T(0.5);
     const T* __restrict__ tb[6] = {ap.tau[0], ap.tau[1], ap.tau[2], ap.tau[3], ap.tau[4], ap.tau[5]};
@@ -202,14 +234,16 @@ __global__ void __launch_bounds__(64 * kWaves) k_sgs_apply(FusedArgs<T> a) {
     const int kend = ke < nz ? ke : nz - 1;              // last plane marched
     Vec<T, VX> P[4], Wst[2], wc;
     {
-        const int p0 = ks * plane;
-        const Row3<T, VX> Wk = load3<T, VX>(a.w, p0, rm, r0, rp, x);
-        const Vec<T, VX> uk = vload<T, VX>(a.u + p0 + r0 + x), vk = vload<T, VX>(a.v + p0 + r0 + x);
+        constexpr unsigned S = sizeof(T);
+        const unsigned p0 = (unsigned)(ks - kbase) * (unsigned)plane;
+        const Row3<T, VX> Wk = load3<T, VX>(sl.w, p0, rm, r0, rp, xo);
+        const Vec<T, VX> uk = bload<T, VX>(sl.u, xo, (p0 + r0) * S),
+                         vk = bload<T, VX>(sl.v, xo, (p0 + r0) * S);
         if (ks > 0) {
-            const int pb = p0 - plane;
-            const Row3<T, VX> Ub = load3<T, VX>(a.u, pb, rm, r0, rp, x);
-            const Row3<T, VX> Vb = load3<T, VX>(a.v, pb, rm, r0, rp, x);
-            const Vec<T, VX> wb = vload<T, VX>(a.w + pb + r0 + x);
+            const unsigned pb = p0 - (unsigned)plane;          // ks - 1 >= kbase
+            const Row3<T, VX> Ub = load3<T, VX>(sl.u, pb, rm, r0, rp, xo);
+            const Row3<T, VX> Vb = load3<T, VX>(sl.v, pb, rm, r0, rp, xo);
+            const Vec<T, VX> wb = bload<T, VX>(sl.w, xo, (pb + r0) * S);
             uv_strain(Ub, Vb, wb, Wk.c, P);
             w_strain(uk, Ub.c, vk, Vb.c, Wk, Wst);
         } else {
@@ -228,18 +262,26 @@ __global__ void __launch_bounds__(64 * kWaves) k_sgs_apply(FusedArgs<T> a) {
     Acc s0 = Acc(0), s1 = Acc(0), s2 = Acc(0);
     // the plane's loads go out one plane ahead: right after the barrier, so
     // they are in flight while the divergence of the plane is formed
-    PlaneIn<T, VX> in;
-    load_plane<T, VX>(a, ks, rm, r0, rp, x, in);
+    // (PF = 2: plane k+2's loads go out before plane k's arithmetic)
+    PlaneIn<T, VX> in, in2;
+    load_plane<T, VX>(a, sl, ks, kbase, rm, r0, rp, x, in);
+    if constexpr (PF == 2)
+        if (ks + 1 <= kend) load_plane<T, VX>(a, sl, ks + 1, kbase, rm, r0, rp, x, in2);
     for (int k = ks; k <= kend; ++k) {
         const bool up = k + 1 < nz;
-        const int q = k * plane + r0 + x;
-        const Row3<T, VX>& U = in.U;
-        const Row3<T, VX>& V = in.V;
-        const Row3<T, VX> Wn = in.Wn;
-        const Vec<T, VX> un = in.un, vn = in.vn, pu = in.pu, pw = in.pw, lz = in.lz;
+        const int row = k * plane + r0;                  // uniform; the lane adds x
+        const PlaneIn<T, VX> cur = in;
+        if constexpr (PF == 2) {
+            in = in2;
+            if (k + 2 <= kend) load_plane<T, VX>(a, sl, k + 2, kbase, rm, r0, rp, x, in2);
+        }
+        const Row3<T, VX>& U = cur.U;
+        const Row3<T, VX>& V = cur.V;
+        const Row3<T, VX>& Wn = cur.Wn;
+        const Vec<T, VX> un = cur.un, vn = cur.vn, pu = cur.pu, pw = cur.pw, lz = cur.lz;
         uint32_t m[VX];
 #pragma unroll
-        for (int e = 0; e < VX; ++e) m[e] = in.m[e];
+        for (int e = 0; e < VX; ++e) m[e] = cur.m[e];
         // ---- strain: uv nodes of plane k, w nodes of plane k+1
         Vec<T, VX> S[4], N[2];
         uv_strain(U, V, wc, Wn.c, S);
@@ -257,7 +299,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_sgs_apply(FusedArgs<T> a) {
             const T s23 = half * (Wst[1].v[e] + N[1].v[e]);
             const T ss = S[0].v[e] * S[0].v[e] + S[1].v[e] * S[1].v[e] + S[2].v[e] * S[2].v[e] +
                          T(2) * (S[3].v[e] * S[3].v[e] + s13 * s13 + s23 * s23);
-            const T nu = mixing_sq(a, pu.v[e], z0) * sqrt(T(2) * ss);
+            const T nu = mixing_sq(a, pu.v[e], z0) * sqrt_fast(T(2) * ss);
 #pragma unroll
             for (int c = 0; c < 4; ++c) t[c].v[e] = T(-2) * nu * S[c].v[e];
             T mm[4];
@@ -265,20 +307,20 @@ __global__ void __launch_bounds__(64 * kWaves) k_sgs_apply(FusedArgs<T> a) {
             for (int c = 0; c < 4; ++c) mm[c] = half * (P[c].v[e] + S[c].v[e]);
             const T sw = mm[0] * mm[0] + mm[1] * mm[1] + mm[2] * mm[2] +
                          T(2) * (mm[3] * mm[3] + Wst[0].v[e] * Wst[0].v[e] + Wst[1].v[e] * Wst[1].v[e]);
-            const T nuw = mixing_sq(a, pw.v[e], z0) * sqrt(T(2) * sw);
+            const T nuw = mixing_sq(a, pw.v[e], z0) * sqrt_fast(T(2) * sw);
             t[4].v[e] = T(-2) * nuw * Wst[0].v[e];
             t[5].v[e] = T(-2) * nuw * Wst[1].v[e];
             const uint32_t cuv = m[e] & 3u, cw = (m[e] >> 2) & 3u;
             if (cuv == 1u) {
 #pragma unroll
-                for (int c = 0; c < 4; ++c) t[c].v[e] = tb[c][q + e];
+                for (int c = 0; c < 4; ++c) t[c].v[e] = tb[c][row + x + e];
             } else if (cuv == 2u) {
 #pragma unroll
                 for (int c = 0; c < 4; ++c) t[c].v[e] = T(0);
             }
             if (cw == 1u) {
-                t[4].v[e] = tb[4][q + e];
-                t[5].v[e] = tb[5][q + e];
+                t[4].v[e] = tb[4][row + x + e];
+                t[5].v[e] = tb[5][row + x + e];
             } else if (cw == 2u) {
                 t[4].v[e] = t[5].v[e] = T(0);
             }
@@ -292,7 +334,8 @@ __global__ void __launch_bounds__(64 * kWaves) k_sgs_apply(FusedArgs<T> a) {
             sh[b][2][wv][VX * lane + e] = t[5].v[e];
         }
         __syncthreads();
-        if (k < kend) load_plane<T, VX>(a, k + 1, rm, r0, rp, x, in);
+        if constexpr (PF == 1)
+            if (k < kend) load_plane<T, VX>(a, sl, k + 1, kbase, rm, r0, rp, x, in);
         const Vec<T, VX> dxz = xd(t[4]), dxx_p = xd(xx_p), dxy_p = xd(xy_p);
         const bool zout = k >= kb && k < ke, xyout = k >= 1 && k - 1 >= kb && k - 1 < ke;
         if (row_out) {
@@ -310,11 +353,11 @@ __global__ void __launch_bounds__(64 * kWaves) k_sgs_apply(FusedArgs<T> a) {
                     if (outn[e] && !(m[e] & 32u)) s2 += (Acc)dz.v[e];
                 }
                 if (all) {
-                    vstore_nt<T, VX>(ap.div[2] + q, dz);
+                    vstore_nt<T, VX>(ap.div[2] + row + x, dz);
                 } else {
 #pragma unroll
                     for (int e = 0; e < VX; ++e)
-                        if (outn[e]) ap.div[2][q + e] = dz.v[e];
+                        if (outn[e]) ap.div[2][row + x + e] = dz.v[e];
                 }
             }
             if (xyout) {
@@ -332,16 +375,16 @@ __global__ void __launch_bounds__(64 * kWaves) k_sgs_apply(FusedArgs<T> a) {
                         s1 += (Acc)dy.v[e];
                     }
                 }
-                const int qp = q - plane;
+                const int rowp = row - plane;
                 if (all) {
-                    vstore_nt<T, VX>(ap.div[0] + qp, dx);
-                    vstore_nt<T, VX>(ap.div[1] + qp, dy);
+                    vstore_nt<T, VX>(ap.div[0] + rowp + x, dx);
+                    vstore_nt<T, VX>(ap.div[1] + rowp + x, dy);
                 } else {
 #pragma unroll
                     for (int e = 0; e < VX; ++e) {
                         if (!outn[e]) continue;
-                        ap.div[0][qp + e] = dx.v[e];
-                        ap.div[1][qp + e] = dy.v[e];
+                        ap.div[0][rowp + x + e] = dx.v[e];
+                        ap.div[1][rowp + x + e] = dy.v[e];
                     }
                 }
             }
@@ -364,7 +407,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_sgs_apply(FusedArgs<T> a) {
         // uv divergence of the top plane: tau_xz, tau_yz above it are 0
         const Vec<T, VX> dxx_p = xd(xx_p), dxy_p = xd(xy_p);
         const int bp = (nz - 1) % 3;
-        const int qt = (nz - 1) * plane + r0 + x;
+        const int rowt = (nz - 1) * plane + r0;
 #pragma unroll
         for (int e = 0; e < VX; ++e) {
             if (!outn[e]) continue;
@@ -373,8 +416,8 @@ __global__ void __launch_bounds__(64 * kWaves) k_sgs_apply(FusedArgs<T> a) {
                          (T(0) - xz_p.v[e]) * a.cz;
             const T dy = dxy_p.v[e] * a.cx + (sh[bp][1][wv + 1][n] - sh[bp][1][wv - 1][n]) * a.cy +
                          (T(0) - yz_p.v[e]) * a.cz;
-            ap.div[0][qt + e] = dx;
-            ap.div[1][qt + e] = dy;
+            ap.div[0][rowt + x + e] = dx;
+            ap.div[1][rowt + x + e] = dy;
             if (!(m_p[e] & 16u)) {
                 s0 += (Acc)dx;
                 s1 += (Acc)dy;
@@ -402,6 +445,14 @@ __global__ void __launch_bounds__(256) k_sgs_apply_finalize(const double* __rest
     finalize_slots(p, nslots, 3, 0u, scale, out);
 }
 
+// Planes per block: kChunk, fewer where a block's slab (its planes, two below
+// and one above) would pass 4 GiB; below 1 when a single plane is that large.
+int chunk_planes(const ibm_ctx* c) {
+    const double plane_bytes = (double)c->g.nx * c->g.ny * (c->dtype == IBM_F64 ? 8 : 4);
+    const double fit = std::floor(4294967295.0 / plane_bytes) - 4;
+    return (int)std::min<double>(kChunk, fit);
+}
+
 template <typename T>
 int sgs_apply_t(ibm_ctx* c, const T* phi_uv, const T* phi_w, const T* u, const T* v, const T* w,
                 double z0, const T* log_z0, double cs, double kappa, const void* const tau[6],
@@ -425,19 +476,14 @@ int sgs_apply_t(ibm_ctx* c, const T* phi_uv, const T* phi_w, const T* u, const T
     a.inv_l0sq = (T)(1.0 / (l0 * l0));
     a.kappa = (T)kappa;
     a.z0 = (T)z0;
-    // two nodes per lane (float: in double the registers would spill) when no
-    // lane's pair straddles the periodic end and every field allows 8-byte
-    // access
-    bool pair = sizeof(T) == 4 && c->g.nx % 2 == 0;
-    for (const void* p : {(const void*)phi_uv, (const void*)phi_w, (const void*)u, (const void*)v,
-                          (const void*)w, (const void*)log_z0})
-        pair = pair && (!p || (uintptr_t)p % (2 * sizeof(T)) == 0);
-    for (int i = 0; i < 6; ++i) pair = pair && (uintptr_t)tau[i] % (2 * sizeof(T)) == 0;
-    for (int i = 0; i < 3; ++i) pair = pair && (uintptr_t)div[i] % (2 * sizeof(T)) == 0;
-    const int sp = pair ? span<2>() : span<1>();
+    const int sp = span<1>();
     a.nxs = (c->g.nx + sp - 1) / sp;
     a.njb = (c->g.ny + kRows - 1) / kRows;
-    a.nblocks = (int)((long)a.nxs * a.njb * ((c->g.nz + kChunk - 1) / kChunk));
+    a.kc = chunk_planes(c);
+    if (a.kc < 1)
+        return fail(IBM_E_ARG, "apply_sgs: an x-y plane of %ld nodes passes the 4 GiB reach of "
+                    "the fused pass's 32-bit offsets", (long)a.plane);
+    a.nblocks = (int)((long)a.nxs * a.njb * ((c->g.nz + a.kc - 1) / a.kc));
     a.per_xcd = (a.nblocks + 7) / 8;
     a.ap = make_apply_args<T>(c, c->cfg, tau, ustar, gradp, dt, div, drag);
     if (c->ap_cap < 3L * a.nblocks) return fail(IBM_E_STATE, "apply_sgs: reduction slots not sized");
@@ -446,13 +492,15 @@ int sgs_apply_t(ibm_ctx* c, const T* phi_uv, const T* phi_w, const T* u, const T
     const unsigned grid = (unsigned)(8 * a.per_xcd + a.ap.nfblocks);
     const bool wide = c->precision == IBM_PREC_MIXED || sizeof(T) == 8;   // drag in double
     const dim3 g3(grid), b3(64 * kWaves);
+    // One node per lane.  In float the loads go out two planes ahead; in
+    // double the third plane's registers would spill.  (Two nodes per lane
+    // needed more registers than four waves per SIMD allow and measured
+    // slower.)
     if constexpr (sizeof(T) == 4) {
-        if (pair && wide) hipLaunchKernelGGL((k_sgs_apply<T, double, 2>), g3, b3, 0, s, a);
-        else if (pair) hipLaunchKernelGGL((k_sgs_apply<T, T, 2>), g3, b3, 0, s, a);
-        else if (wide) hipLaunchKernelGGL((k_sgs_apply<T, double, 1>), g3, b3, 0, s, a);
-        else hipLaunchKernelGGL((k_sgs_apply<T, T, 1>), g3, b3, 0, s, a);
+        if (wide) hipLaunchKernelGGL((k_sgs_apply<T, double, 1, 2>), g3, b3, 0, s, a);
+        else hipLaunchKernelGGL((k_sgs_apply<T, T, 1, 2>), g3, b3, 0, s, a);
     } else {
-        hipLaunchKernelGGL((k_sgs_apply<T, double, 1>), g3, b3, 0, s, a);
+        hipLaunchKernelGGL((k_sgs_apply<T, double, 1, 1>), g3, b3, 0, s, a);
     }
     if (drag)
         hipLaunchKernelGGL(k_sgs_apply_finalize, dim3(1), dim3(256), 0, s,
@@ -465,8 +513,9 @@ int sgs_apply_t(ibm_ctx* c, const T* phi_uv, const T* phi_w, const T* u, const T
 
 long sgs_apply_blocks(const ibm_ctx* c) {
     // the most blocks either node width can take (one node per lane)
+    const int kc = std::max(chunk_planes(c), 1);
     return (long)((c->g.nx + span<1>() - 1) / span<1>()) * ((c->g.ny + kRows - 1) / kRows) *
-           ((c->g.nz + kChunk - 1) / kChunk);
+           ((c->g.nz + kc - 1) / kc);
 }
 
 int launch_sgs_apply(ibm_ctx* c, const void* phi_uv, const void* phi_w, const void* u,
