@@ -104,6 +104,16 @@ __device__ inline double quot_fast(double n, double d) { return n / d; }
 __device__ inline float sqrt_fast(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ inline double sqrt_fast(double x) { return __builtin_sqrt(x); }
 
+// XCD-aware block order.  Blocks are dealt round-robin over the 8 XCDs
+// (block b on XCD b % 8); block b takes logical block (b % 8) * per_xcd + b / 8,
+// so each XCD runs a contiguous range of logical blocks and neighbours share
+// its L2.  The grid holds 8 * per_xcd blocks; -1 for the padding blocks.
+__device__ inline int xcd_block(int nblocks) {
+    const int per_xcd = (nblocks + 7) >> 3;
+    const int lb = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+    return lb < nblocks ? lb : -1;
+}
+
 // Butterfly sum / max over the 64 lanes of a wave (fixed order: deterministic).
 __device__ inline double wave_sum(double x) {
 #pragma unroll

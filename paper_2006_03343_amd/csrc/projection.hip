@@ -183,7 +183,8 @@ __global__ void __launch_bounds__(256) k_rows_inv(ProjArgs<T> a) {
 
 // y transforms of the half spectra: a team per pair of adjacent columns of
 // one plane, teams interleaved across lanes (lane = j * teams + team) so a
-// row's columns are read together.  Float moves both columns of a pair as
+// row's columns are read together; a block's row segments straddle lines that
+// the next block reads too, so the block order is XCD-aware.  Float moves both columns of a pair as
 // one 16-byte access and transforms them together; double takes one column
 // at a time (two would spill registers).
 template <typename T>
@@ -247,8 +248,10 @@ __global__ void __launch_bounds__(256) k_cols_fwd(ProjArgs<T> a) {
     stage_twiddles(tw, a.twy, n);
     const int cpairs = a.nhp / 2;
     const int groups = (cpairs + teams - 1) / teams;
-    const int k = (int)blockIdx.x / groups;
-    const int gi = (int)blockIdx.x - k * groups;
+    const int lb = xcd_block(groups * a.nz);
+    if (lb < 0) return;                                   // the whole block
+    const int k = lb / groups;
+    const int gi = lb - k * groups;
     const int team = (int)threadIdx.x % teams;
     const Team tm = make_team(logn, (int)threadIdx.x / teams, team, teams, true);
     const int cp = gi * teams + team;
@@ -297,8 +300,10 @@ __global__ void __launch_bounds__(256) k_cols_inv(ProjArgs<T> a) {
     stage_twiddles(tw, a.twy, n);
     const int cpairs = a.nhp / 2;
     const int groups = (cpairs + teams - 1) / teams;
-    const int k = (int)blockIdx.x / groups;
-    const int gi = (int)blockIdx.x - k * groups;
+    const int lb = xcd_block(groups * a.nz);
+    if (lb < 0) return;                                   // the whole block
+    const int k = lb / groups;
+    const int gi = lb - k * groups;
     const int team = (int)threadIdx.x % teams;
     const Team tm = make_team(logn, (int)threadIdx.x / teams, team, teams, true);
     const int cp = gi * teams + team;
@@ -552,7 +557,8 @@ int project_t(ibm_ctx* c, const void* const ustar[3], double dt, void* const uo[
     const int tx = 256 / (a.nx >= 8 ? a.nx / 8 : 1);     // teams per block
     const int ty = 256 / (a.ny >= 8 ? a.ny / 8 : 1);
     const unsigned gx = (unsigned)(((a.rows + 1) / 2 + tx - 1) / tx);
-    const unsigned gy = (unsigned)(((a.nhp / 2 + ty - 1) / ty) * a.nz);
+    const long ncb = (long)((a.nhp / 2 + ty - 1) / ty) * a.nz;   // column blocks
+    const unsigned gy = (unsigned)(8 * ((ncb + 7) / 8));          // dealt per XCD
     constexpr int G = sizeof(T) == 4 ? 2 : 1;            // columns per y-transform phase
     hipLaunchKernelGGL(k_rows_fwd<T>, dim3(gx, 3), dim3(256), spectral_lds_bytes(c, a.nx, 1), s, a);
     hipLaunchKernelGGL(k_cols_fwd<T>, dim3(gy), dim3(256), spectral_lds_bytes(c, a.ny, G), s, a);

@@ -179,7 +179,10 @@ __device__ inline void drag_add(Acc (&acc)[3], uint32_t fb, T d0, T d1, T d2) {
 
 // A team per pair of columns (c, c+1) of plane k; the teams of a block are
 // interleaved across lanes (lane = j * teams + team), so a row's columns are
-// read together.  Sequences: tau_xy + i tau_yy of column c, of column c+1,
+// read together.  A block's row segment (16 float columns, 64 B) is half a
+// cache line whose other half the next block reads, and the vertical
+// differences read the neighbouring planes' blocks' stresses: with the
+// XCD-aware block order blocks that share lines run on one XCD's L2.  Sequences: tau_xy + i tau_yy of column c, of column c+1,
 // and tau_yz of column c + i tau_yz of column c+1.  PAIR (float, nx even,
 // fields 8-byte aligned): each field's two columns move as one 8-byte access.
 template <typename T, bool ALL, bool PAIR, typename Acc>
@@ -191,11 +194,13 @@ __global__ void __launch_bounds__(256) k_dy(SpecArgs<T> a, ApplyArgs<T> z) {
     const int n = a.ny, logn = a.logy;
     const int P = n >= 8 ? n >> 3 : 1, ns = n >= 8 ? 8 : n;
     const int teams = (int)blockDim.x / P;
+    const int groups = (a.nx + 2 * teams - 1) / (2 * teams);
+    const int lb = xcd_block(groups * a.nz);
+    if (lb < 0) return;                                   // the whole block
     Cx<T>* tw = xl + team_lds_elems(blockDim.x) * (ALL ? G : 1);
     stage_twiddles(tw, a.twy, n);
-    const int groups = (a.nx + 2 * teams - 1) / (2 * teams);
-    const int k = (int)blockIdx.x / groups;
-    const int gi = (int)blockIdx.x - k * groups;
+    const int k = lb / groups;
+    const int gi = lb - k * groups;
     const int team = (int)threadIdx.x % teams;
     const Team tm = make_team(logn, (int)threadIdx.x / teams, team, teams, true);
     const int c0 = 2 * (gi * teams + team);
@@ -307,7 +312,7 @@ __global__ void __launch_bounds__(256) k_dy(SpecArgs<T> a, ApplyArgs<T> z) {
     if (threadIdx.x < 3) {
         double r = 0.0;
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += red[threadIdx.x][w];
-        z.partials[3L * blockIdx.x + threadIdx.x] = r;
+        z.partials[3L * lb + threadIdx.x] = r;
     }
 }
 
@@ -382,7 +387,7 @@ int spectral_t(ibm_ctx* c, const void* const tau[6], void* const ustar[3],
     for (int i = 0; i < 6; ++i) aligned = aligned && (uintptr_t)tau[i] % (2 * sizeof(T)) == 0;
     for (int i = 0; i < 3; ++i) aligned = aligned && (uintptr_t)div[i] % (2 * sizeof(T)) == 0;
     const bool wide = c->precision == IBM_PREC_MIXED || sizeof(T) == 8;   // drag in double
-    const dim3 gdy((unsigned)nyb);
+    const dim3 gdy((unsigned)(8 * ((nyb + 7) / 8)));     // logical blocks dealt per XCD
     const size_t lds_y = spectral_lds_bytes(c, ny, 1);
     if (aligned && wide)
         hipLaunchKernelGGL((k_dy<T, false, sizeof(T) == 4, double>), gdy, dim3(256), lds_y, s, a, z);
