@@ -175,8 +175,8 @@ k_sgs_apply(FusedArgs<T> a) {
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nx = a.nx, ny = a.ny, nz = a.nz, plane = a.plane;
     const int xs = lb % a.nxs, t2 = lb / a.nxs;
-    const int jb = t2 % a.njb, kc = t2 / a.njb;
-    const int kb = kc * a.kc, ke = min(kb + a.kc, nz);
+    const int jb = t2 % a.njb, chunk = t2 / a.njb;
+    const int kb = chunk * a.kc, ke = min(kb + a.kc, nz);
     const int x0 = xs * SPAN;
     const int jr = jb * kRows - 1 + wv;                  // this wave's row, unwrapped
     const int j = wrap(jr, ny);
