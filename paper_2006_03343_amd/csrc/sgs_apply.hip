@@ -27,7 +27,7 @@
 // a wave adds row and plane offsets in scalar registers; in float a plane's
 // loads are issued two planes ahead of its arithmetic.  The work is the
 // Smagorinsky arithmetic of 8 rows for 6 and 64 nodes for 60: the pass is
-// bound by vector-ALU issue, not by HBM.
+// bound by that arithmetic and the barrier per plane, not by HBM.
 //
 // Bytes per node: u, v, w, phi_uv, phi_w (log z0) in, the class byte, the
 // band stress where there is one, div out; the halo rows and columns of a
