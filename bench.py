@@ -458,10 +458,11 @@ def run_projection(wl, steps, warmup):
     proj_bytes = g.n * 4 * 7
     # what the passes move per node over half spectra (about 4 B per node per
     # complex field): forward x 24 (u*, v*, w* in, three spectra out),
-    # forward y 20 (three in; H, w_hat out), the solve 24, inverse y 12 (p_hat
-    # in; P, DY out), inverse x 32 (P twice, DY, u*, v* in; p, u, v out), the
-    # w correction 12
-    pass_bytes = g.n * (24 + 20 + 24 + 12 + 32 + 12)
+    # forward y 20 (three in; H, w_hat out), the solve 28 (its workspace, p_hat
+    # and the vertical difference out), inverse y 20 (p_hat and the difference
+    # in; P, DY, DZ out), inverse x 44 (P twice, DY, DZ, u*, v*, w* in; p, u,
+    # v, w out)
+    pass_bytes = g.n * (24 + 20 + 28 + 20 + 44)
     del ctx, vel, rn, rp, ustar, uo, p
     torch.cuda.empty_cache()
     gbs = lambda b, ms: b / (ms * 1e-3) / 1e9
@@ -472,8 +473,8 @@ def run_projection(wl, steps, warmup):
             "project_algorithmic_GBs": gbs(proj_bytes, proj_ms),
             "project_algorithmic_frac": gbs(proj_bytes, proj_ms) / HBM_PEAK_GBS,
             "project_pass_GBs": gbs(pass_bytes, proj_ms),
-            "note": "projection: 6 launches (x forward, y forward, solve, y inverse, x "
-                    "inverse, w correction) over half spectra; algorithmic bytes 28 per node, "
+            "note": "projection: 5 launches (x forward, y forward, solve, y inverse, x "
+                    "inverse) over half spectra; algorithmic bytes 28 per node, "
                     f"the passes move {pass_bytes // g.n} per node"}
 
 

@@ -141,7 +141,10 @@ int ibm_apply_spectral(ibm_ctx* c, const void* const tau[6], void* const ustar[3
  * the top w node taken as 0; G: pseudo-spectral d/dx, d/dy of p on uv nodes
  * and (p[k] - p[k-1]) / dz on w nodes k >= 1, no correction on the bottom w
  * node.  Each horizontal mode is a tridiagonal system in z (Thomas, its
- * recurrences in double for either storage type); a mode
+ * recurrences in double for either storage type; the vertical differences of
+ * p that correct w are formed there in double and transformed back, not
+ * taken from the stored p, whose small-wavenumber part is large and nearly
+ * constant in z); a mode
  * without horizontal wavenumber (the mean and the Nyquist modes) is singular
  * and takes p = 0 at k = 0 in place of its first row, so u_out is discretely
  * divergence-free when w is 0 on the bottom plane.  u_out may alias ustar;

@@ -25,11 +25,13 @@
 // H = i kx u_hat + i ky v_hat and w_hat; k_solve -- two threads per
 // horizontal mode for the right-hand side 2 / (3 dt) (H + (w_hat[k+1] -
 // w_hat[k]) / dz) and the tridiagonal system in z, eliminated from both ends
-// (recurrences in double), leaving p_hat; k_cols_inv -- inverse y transforms
-// of p_hat and i ky p_hat from one read; k_rows_inv -- inverse x transforms
-// from the Hermitian extension, two rows per transform, returning p and u =
-// u* - (3 dt / 2) d/dx p (i kx formed in the same pass) and v = v* - (3 dt /
-// 2) d/dy p; k_wcorr -- the vertical correction of w.  Transforms: fft.h.
+// (recurrences in double), leaving p_hat and its vertical difference
+// p_hat[k] - p_hat[k-1]; k_cols_inv -- inverse y transforms of p_hat and
+// i ky p_hat from one read, and of the vertical difference; k_rows_inv --
+// inverse x transforms from the Hermitian extension, two rows per transform,
+// returning p, u = u* - (3 dt / 2) d/dx p (i kx formed in the same pass),
+// v = v* - (3 dt / 2) d/dy p and w = w* - (3 dt / 2) (p[k] - p[k-1]) / dz.
+// Transforms: fft.h.
 #include <algorithm>
 #include <cmath>
 
@@ -49,11 +51,14 @@ struct ProjArgs {
     const Cx<T>* twx;
     const Cx<T>* twy;
     const T* in[3];          // u*, v*, w*
-    Cx<T>* spec[3];          // their x spectra; then H and w_hat, p_hat; P and DY
-    const T* ub;             // u*, v*: bases of the horizontal corrections
+    Cx<T>* spec[3];          // their x spectra; then H and w_hat; p_hat and its vertical
+                             // difference; P, DY and DZ
+    const T* ub;             // u*, v*, w*: bases of the corrections
     const T* vb;
-    T* uo;                   // u, v, p
+    const T* wb;
+    T* uo;                   // u, v, w, p
     T* vo;
+    T* wo;
     T* po;
     double kx, ky;           // 2 pi / Lx, 2 pi / Ly
     T kxs, kys;              // the same in the storage type
@@ -122,7 +127,8 @@ __global__ void __launch_bounds__(256) k_rows_fwd(ProjArgs<T> a) {
 // A_{n-e} above nx / 2; the imaginary parts of modes 0 and nx / 2 are
 // dropped, as a real inverse does) and inverts it.  blockIdx.y = 0: p from
 // P; 1: u = u* - (3 dt / 2) d/dx p from i kx P; 2: v = v* - (3 dt / 2)
-// d/dy p from DY.  One transform per team keeps the registers, and with them
+// d/dy p from DY; 3: w = w* - (3 dt / 2) (p[k] - p[k-1]) / dz from DZ (zero
+// on the bottom plane, which keeps w*).  One transform per team keeps the registers, and with them
 // the waves per SIMD, of the forward x pass (two per team measured slower
 // despite reading P once).
 template <typename T>
@@ -139,7 +145,7 @@ __global__ void __launch_bounds__(256) k_rows_inv(ProjArgs<T> a) {
     const int kind = (int)blockIdx.y;
     const long r0 = 2 * ((long)blockIdx.x * teams + team);
     const bool in0 = r0 < a.rows, in1 = r0 + 1 < a.rows;
-    const Cx<T>* __restrict__ A = kind < 2 ? a.spec[0] : a.spec[1];
+    const Cx<T>* __restrict__ A = a.spec[kind < 2 ? 0 : kind - 1];
     Cx<T> v[1][8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -168,9 +174,9 @@ __global__ void __launch_bounds__(256) k_rows_inv(ProjArgs<T> a) {
     }
     __syncthreads();   // twiddles staged
     team_ifft<T, 1>(v, tm, xl, tw);
-    const T* base = kind == 1 ? a.ub : a.vb;
-    T* out = kind == 0 ? a.po : kind == 1 ? a.uo : a.vo;
-    const T s = kind == 0 ? T(1) / T(n) : -a.c / T(n);
+    const T* base = kind == 1 ? a.ub : kind == 2 ? a.vb : a.wb;
+    T* out = kind == 0 ? a.po : kind == 1 ? a.uo : kind == 2 ? a.vo : a.wo;
+    const T s = kind == 0 ? T(1) / T(n) : kind < 3 ? -a.c / T(n) : -a.c / (T(n) * a.dzs);
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
         if (u >= ns) continue;
@@ -287,7 +293,8 @@ __global__ void __launch_bounds__(256) k_cols_fwd(ProjArgs<T> a) {
 }
 
 // Inverse: p_hat (spec[0]) -> P = its inverse y transform (in place) and
-// DY = that of i ky p_hat (into spec[1]), both with 1 / ny.
+// DY = that of i ky p_hat (into spec[1]); then the vertical difference of
+// p_hat (spec[2]) -> DZ, its inverse y transform (in place); all with 1 / ny.
 template <typename T>
 __global__ void __launch_bounds__(256) k_cols_inv(ProjArgs<T> a) {
     constexpr int G = sizeof(T) == 4 ? 2 : 1;
@@ -336,6 +343,9 @@ __global__ void __launch_bounds__(256) k_cols_inv(ProjArgs<T> a) {
 #pragma unroll
             for (int u = 0; u < 8; ++u) o[g][u] = v[G + g][u];
         col_store<T, G>(o, inv, a.spec[1] + off + c, tm, a.nhp, ns, act);
+        col_load<T, G>(o, a.spec[2] + off + c, tm, a.nhp, ns, act);
+        team_ifft<T, G>(o, tm, xl, tw);   // its first exchange waits for the block
+        col_store<T, G>(o, inv, a.spec[2] + off + c, tm, a.nhp, ns, act);
     }
 }
 
@@ -469,6 +479,14 @@ __global__ void __launch_bounds__(256) k_solve(ProjArgs<T> a) {
         d = Cx<double>{(double)t.re, (double)t.im};
         c = (double)H[q].re;
     };
+    // Back substitution.  Besides p_hat (into H) each level leaves the
+    // vertical difference p_hat[k] - p_hat[k-1] of the w correction, formed
+    // here in double (into W, whose d' it has read): the small-K modes carry a
+    // large part nearly constant in z that a difference of stored float
+    // pressures would cancel badly.  W at level 0 (no correction there) is 0.
+    auto diff = [&](long q, const Cx<double>& hi, const Cx<double>& lo_) {
+        W[q] = Cx<T>{(T)(hi.re - lo_.re), (T)(hi.im - lo_.im)};
+    };
     Cx<double> p = ph, dn;
     double cn;
     if (top) {
@@ -479,9 +497,12 @@ __global__ void __launch_bounds__(256) k_solve(ProjArgs<T> a) {
             const Cx<double> d = dn;
             const double c = cn;
             if (k > 0) coef(q - hp, dn, cn);
-            p = Cx<double>{d.re - c * p.re, d.im - c * p.im};
-            H[q] = Cx<T>{(T)p.re, (T)p.im};
+            const Cx<double> pk{d.re - c * p.re, d.im - c * p.im};
+            H[q] = Cx<T>{(T)pk.re, (T)pk.im};
+            diff(q + hp, p, pk);                             // level k + 1 <= h
+            p = pk;
         }
+        W[mode] = zero;                                      // level 0
     } else {
         if (h + 1 < nz) coef((long)(h + 1) * hp + mode, dn, cn);
         for (int k = h + 1; k < nz; ++k) {
@@ -489,19 +510,12 @@ __global__ void __launch_bounds__(256) k_solve(ProjArgs<T> a) {
             const Cx<double> d = dn;
             const double c = cn;
             if (k + 1 < nz) coef(q + hp, dn, cn);
-            p = Cx<double>{d.re - c * p.re, d.im - c * p.im};
-            H[q] = Cx<T>{(T)p.re, (T)p.im};
+            const Cx<double> pk{d.re - c * p.re, d.im - c * p.im};
+            H[q] = Cx<T>{(T)pk.re, (T)pk.im};
+            diff(q, pk, p);                                  // level k > h
+            p = pk;
         }
     }
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) k_wcorr(ProjArgs<T> a, const T* __restrict__ ws,
-                                               const T* __restrict__ p, T* __restrict__ wo) {
-    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= a.plane * a.nz) return;
-    const T v = ws[q];
-    wo[q] = q >= a.plane ? v - a.c * ((p[q] - p[q - a.plane]) / a.dzs) : v;
 }
 
 inline unsigned nb256(long n) { return (unsigned)((n + 255) / 256); }
@@ -549,8 +563,10 @@ int project_t(ibm_ctx* c, const void* const ustar[3], double dt, void* const uo[
     }
     a.ub = (const T*)ustar[0];
     a.vb = (const T*)ustar[1];
+    a.wb = (const T*)ustar[2];
     a.uo = (T*)uo[0];
     a.vo = (T*)uo[1];
+    a.wo = (T*)uo[2];
     a.po = (T*)p_out;
     a.kxs = (T)a.kx;
     a.kys = (T)a.ky;
@@ -565,10 +581,8 @@ int project_t(ibm_ctx* c, const void* const ustar[3], double dt, void* const uo[
     hipLaunchKernelGGL(k_solve<T>, dim3((unsigned)((a.hplane + kSolveModes - 1) / kSolveModes)),
                        dim3(2 * kSolveModes), 0, s, a);
     hipLaunchKernelGGL(k_cols_inv<T>, dim3(gy), dim3(256), spectral_lds_bytes(c, a.ny, 1), s, a);
-    // p, u = u* - c d/dx p, v = v* - c d/dy p
-    hipLaunchKernelGGL(k_rows_inv<T>, dim3(gx, 3), dim3(256), spectral_lds_bytes(c, a.nx, 1), s, a);
-    hipLaunchKernelGGL(k_wcorr<T>, dim3(nb256(c->n)), dim3(256), 0, s, a, (const T*)ustar[2],
-                       (const T*)p_out, (T*)uo[2]);
+    // p, u = u* - c d/dx p, v = v* - c d/dy p, w = w* - c (p[k] - p[k-1]) / dz
+    hipLaunchKernelGGL(k_rows_inv<T>, dim3(gx, 4), dim3(256), spectral_lds_bytes(c, a.nx, 1), s, a);
     IBM_HIP(hipGetLastError());
     return IBM_OK;
 }

@@ -423,14 +423,27 @@ int ensure_twiddles(ibm_ctx* c) {
     return IBM_OK;
 }
 
+namespace {
+
+// The longest transform of the storage type: a team of n / 8 threads within a
+// 256-thread block; LDS for the teams' exchanges and the twiddle table within
+// 64 KiB.
+int max_length(const ibm_ctx* c) { return c->dtype == IBM_F64 ? 1024 : 2048; }
+
+// Whether the transforms take this grid (spectral_check without the message).
+bool spectral_fits(const ibm_ctx* c) {
+    return ilog2_exact(c->g.nx) >= 0 && ilog2_exact(c->g.ny) >= 0 && c->g.nx <= max_length(c) &&
+           c->g.ny <= max_length(c);
+}
+
+}  // namespace
+
 int spectral_check(const ibm_ctx* c) {
     const int nx = c->g.nx, ny = c->g.ny;
     if (ilog2_exact(nx) < 0 || ilog2_exact(ny) < 0)
         return fail(IBM_E_UNSUPPORTED, "spectral transforms: nx and ny must be powers of two (%d, %d)",
                     nx, ny);
-    // a team of n / 8 threads within a 256-thread block; LDS for the teams'
-    // exchanges and the twiddle table within 64 KiB
-    const int nmax = c->dtype == IBM_F64 ? 1024 : 2048;
+    const int nmax = max_length(c);
     if (nx > nmax || ny > nmax)
         return fail(IBM_E_UNSUPPORTED, "spectral transforms: nx, ny <= %d for this storage type (%d, %d)",
                     nmax, nx, ny);
@@ -443,7 +456,9 @@ size_t spectral_lds_bytes(const ibm_ctx* c, int n, int seqs) {
 }
 
 long spectral_slots(const ibm_ctx* c) {
-    // one per y-pass block and drag component
+    // one per y-pass block and drag component; none for a grid the
+    // transforms refuse (its y pass would have no teams per block)
+    if (!spectral_fits(c)) return 0;
     const int ny = c->g.ny, nx = c->g.nx;
     const int ty = 256 / (ny >= 8 ? ny / 8 : 1);
     return 3L * ((nx + 2 * ty - 1) / (2 * ty)) * c->g.nz;

@@ -1,8 +1,10 @@
 """GPU parity of the AB2 update and the pressure projection
 (ibm_ab2_predict, ibm_pressure_project) against the oracle.
 
-* small grids (float64 and float32): u, v, w after the projection and the
-  pressure, normwise per field <= 1e-12 (float64) and 2e-5 (float32);
+* small grids (float64 and float32), among them the longest transforms along
+  x and along y of each type (2048 points in float, 1024 in double): u, v, w
+  after the projection and the pressure, normwise per field <= 1e-12
+  (float64) and 2e-5 (float32);
 * with w = 0 on the bottom plane the projected field is discretely
   divergence-free (the oracle's D applied to the GPU's output);
 * output in place of the input;
@@ -11,7 +13,8 @@
   the oracle's dense solve of those modes' systems (normwise over the
   sampled modes: float32 rounding of the transforms scales with the whole
   field, not with one high mode's small amplitude);
-* AB2 against its formula; error paths.
+* AB2 against its formula; error paths (lengths beyond the longest transform
+  refused).
 """
 import numpy as np
 import pytest
@@ -52,7 +55,12 @@ def _project(g, vel, dt, dtype, in_place=False):
                                             ((16, 8, 9), (0.7, 1.3, 0.9), "f64"),
                                             ((32, 16, 12), (1.0, 1.0, 1.0), "f32"),
                                             ((4, 2, 1), (1.0, 1.0, 1.0), "f64"),
-                                            ((1, 8, 5), (1.0, 1.0, 1.0), "f64")])
+                                            ((1, 8, 5), (1.0, 1.0, 1.0), "f64"),
+                                            # the longest transforms each type takes
+                                            ((2048, 4, 3), (1.0, 1.0, 1.0), "f32"),
+                                            ((4, 2048, 3), (1.0, 1.0, 1.0), "f32"),
+                                            ((1024, 4, 3), (1.0, 1.0, 1.0), "f64"),
+                                            ((4, 1024, 3), (1.0, 1.0, 1.0), "f64")])
 def test_projection_matches_oracle(ora, shape, sp, dtype):
     g = Grid(*shape, *sp)
     vel = _fields(g, sum(shape), wall=False)
@@ -156,3 +164,11 @@ def test_errors():
     with pytest.raises(ibm.IbmError) as e:
         ctx.pressure_project(f[:3], 0.01, f[:3], f[0])
     assert e.value.code == _lib.IBM_E_ARG
+    for shape, tdt in (((3, 2, 4096), torch.float32), ((3, 4096, 2), torch.float32),
+                       ((3, 2, 2048), torch.float64), ((3, 2048, 2), torch.float64)):
+        # beyond the longest transform of the storage type
+        ctx = ibm.Context(shape[2], shape[1], shape[0], dtype=tdt, device=dev)
+        f = [torch.zeros(shape, dtype=tdt, device=dev) for _ in range(4)]
+        with pytest.raises(ibm.IbmError) as e:
+            ctx.pressure_project(f[:3], 0.01, [torch.empty_like(f[0]) for _ in range(3)], f[3])
+        assert e.value.code == _lib.IBM_E_UNSUPPORTED

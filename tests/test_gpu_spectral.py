@@ -8,8 +8,9 @@ packed field's Nyquist term into the other would show.  Cases: the cube,
 small hills in three precisions, per-node log z0, grids with one row, one
 column, one plane and two nodes, the 512 x 256 x 256 hill, fields one
 element into their buffers (float32: the y pass then takes one column per
-access instead of 8-byte column pairs); a grid size that is not a power of
-two is refused.
+access instead of 8-byte column pairs), the longest transforms along x and
+along y in both precisions; a grid size that is not a power of two, or one
+beyond the longest transform, is refused.
 """
 import numpy as np
 import pytest
@@ -101,3 +102,41 @@ def test_hill_full_size(ora):
     out, _ = run_gpu(wl, "f32", "mixed", spectral=True)
     errs = compare(out, _ref(ora, wl), wl, TOL["f32"])
     _say(f"errors {errs}")
+
+
+@pytest.mark.parametrize("shape,dtype", [((2048, 4, 6), "f32"), ((4, 2048, 6), "f32"),
+                                         ((1024, 4, 6), "f64"), ((4, 1024, 6), "f64")])
+def test_maximum_lengths(ora, shape, dtype):
+    """The longest transforms each storage type takes (2048 points in float,
+    1024 in double), along x and along y."""
+    g = Grid(*shape)
+    wl = configs.flat(g, 1.25, theta=0.4, z0=1e-3, noise=0.2, tau_std=0.01, gp_std=0.1,
+                      seed=shape[0] + 3 * shape[1])
+    if dtype == "f32":
+        wl = wl.cast(np.float32)
+    _say(f"spectral flat {shape} {dtype} (maximum transform length)")
+    out, _ = run_gpu(wl, dtype, "mixed" if dtype == "f32" else "plain", spectral=True)
+    errs = compare(out, _ref(ora, wl), wl, TOL[dtype])
+    _say(f"errors {errs}")
+
+
+@pytest.mark.parametrize("shape,dtype", [((4096, 2, 3), "f32"), ((2, 4096, 3), "f32"),
+                                         ((2048, 2, 3), "f64"), ((2, 2048, 3), "f64")])
+def test_beyond_maximum_length(shape, dtype):
+    import torch
+    import paper_2006_03343_amd as ibm
+    from paper_2006_03343_amd import _lib
+    _, dev = torch_dev()
+    g = Grid(*shape)
+    wl = configs.flat(g, 1.25, theta=0.4, z0=1e-3, noise=0.2, tau_std=0.01, gp_std=0.1, seed=1)
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev, tdt)
+    ctx = ibm.Context(g.nx, g.ny, g.nz, dtype=tdt, device=dev)
+    ctx.prepare(T(wl.phi_uv), T(wl.phi_w), 1.25)
+    f = [T(t) for t in wl.tau]
+    u = [T(wl.u).clone() for _ in range(3)]
+    d = [torch.empty_like(u[0]) for _ in range(3)]
+    _say(f"spectral {shape} {dtype}: refused")
+    with pytest.raises(ibm.IbmError) as e:
+        ctx.apply_spectral(f, u, d)
+    assert e.value.code == _lib.IBM_E_UNSUPPORTED
