@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 
 from _gpu import TOL, compare, torch_dev
-from workloads import configs
+from workloads import Grid, configs
 
 pytestmark = pytest.mark.gpu
 
@@ -226,3 +226,38 @@ def test_autotune_cache(tmp_path):
         tile = b.case(i).get_tile()
         assert tile[1] <= 2
         _same(f.snapshot(), _plain(w, tile, torch.float32, "mixed", dev), f"tuned case {i}")
+
+
+DEGENERATE = [(1, 1, 12), (7, 1, 9), (1, 6, 9), (33, 5, 1), (20, 2, 2), (130, 9, 8)]
+DEGENERATE_TILES = {"f32": [(1, 1, 4, 1), (1, 2, 3, 1), (1, 1, 16, 1), (1, 1, 1, 1), (4, 1, 2, 1),
+                            (2, 2, 5, 1)],
+                    "f64": [(1, 1, 4, 1), (1, 1, 5, 1), (1, 2, 2, 1), (1, 2, 1, 1), (2, 2, 3, 1),
+                            (2, 1, 5, 1)]}
+
+
+@pytest.mark.parametrize("dtype,prec", [("f32", "mixed"), ("f64", "plain")])
+def test_degenerate_cases(ora, dtype, prec):
+    """Cases of one column, one row, one or two planes and a ragged grid in one
+    batch, each with its own tile: every case equals its plain calls bit for
+    bit, and one of them the oracle.  (Cases with vx > 1 keep their stacked
+    stress and divergence components 16-byte aligned, as binding requires.)"""
+    torch, dev = torch_dev()
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    wls = []
+    for i, shape in enumerate(DEGENERATE):
+        wl = configs.flat(Grid(*shape), 1.25, theta=0.4, z0=1e-3, noise=0.3, tau_std=0.01,
+                          gp_std=0.1, seed=7 + i)
+        assert wl.band_width == 1.5 and wl.phi_c == 1.5      # as the batch prepares them
+        wls.append(wl.cast(np.float32) if dtype == "f32" else wl)
+    tiles = DEGENERATE_TILES[dtype]
+    _say(f"batch of degenerate cases {DEGENERATE} {dtype} {prec}")
+    b, fs = _batch(wls, tiles, tdt, prec, dev)
+    b.run()
+    torch.cuda.synchronize()
+    for i, (w, f) in enumerate(zip(wls, fs)):
+        _same(f.snapshot(), _plain(w, tiles[i], tdt, prec, dev), f"case {i} {DEGENERATE[i]}")
+    ref = ora.stage(wls[5])
+    out = dict(tau=fs[5].tau.cpu().numpy(), div=fs[5].div.cpu().numpy(),
+               ustar=fs[5].ustar.cpu().numpy(), drag=fs[5].drag.cpu().numpy(),
+               stats=fs[5].stats.cpu().numpy(), mask=b.case(5).mask(), counts=b.case(5).counts())
+    compare(out, ref, wls[5], TOL[dtype])
