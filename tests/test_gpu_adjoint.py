@@ -4,7 +4,8 @@ Check loss J = D_x + 1/2 sum(div^2) + 1/2 sum(ustar_ib^2) over every node and
 component, with one velocity state that is sampled and forced (ustar = u),
 differentiated with respect to u, v, w and a per-node log z0 field.
 
-* float64 GPU adjoint vs the oracle's reverse mode: <= 1e-11 normwise;
+* float64 GPU adjoint vs the oracle's reverse mode: <= 1e-11 normwise, also
+  on grids of one column, one row, one or two planes and a ragged one;
 * float32 (mixed) adjoint vs float64 central finite differences of J along
   32 seeded random directions (seeds 200603343 + 1000 + d): <= 1e-4 relative
   per direction, on the 256 x 128 x 128 fractal terrain;
@@ -176,3 +177,32 @@ def test_autograd_gradcheck_tiny():
         return t, d, s, dr
 
     assert torch.autograd.gradcheck(f, args, eps=1e-6, atol=1e-7, rtol=1e-6, fast_mode=True)
+
+
+def test_vjp_degenerate_grids(ora):
+    """float64 adjoint against the oracle's reverse mode on grids of one
+    column, one row, one or two planes and a ragged one (a flat wall, wind at
+    an angle, scalar z0, random cotangents of every output).  Over a flat wall
+    w is the normal component and never reaches the wall stress; the fractal
+    case covers that path."""
+    from workloads import Grid
+    for i, shape in enumerate(((1, 1, 12), (7, 1, 9), (1, 6, 9), (33, 5, 1), (20, 2, 2),
+                               (130, 9, 7))):
+        wl = configs.flat(Grid(*shape), 1.25, theta=0.4, z0=1e-3, noise=0.3, tau_std=0.01,
+                          gp_std=0.1, seed=20 + i)
+        _say(f"adjoint flat {shape} f64 vs oracle")
+        st = Stage(wl, "f64")
+        T = st.T
+        rng = np.random.default_rng(30 + i)
+        g_tau = [rng.standard_normal(wl.grid.shape) for _ in range(6)]
+        g_div = [rng.standard_normal(wl.grid.shape) for _ in range(3)]
+        g_us = [rng.standard_normal(wl.grid.shape) for _ in range(3)]
+        g_drag = [0.7, -1.3, 0.4]
+        gu, gv, gw, glz = st.ctx.vjp(T(wl.u), T(wl.v), T(wl.w), [T(a) for a in g_div],
+                                     [T(a) for a in g_us], g_drag, z0=wl.z0,
+                                     g_tau=[T(a) for a in g_tau])
+        assert glz is None
+        ref = ora.stage_vjp(wl, g_tau, g_div, g_us, g_drag)
+        errs = [normwise(a.cpu().numpy(), b) for a, b in zip((gu, gv, gw), ref[:3])]
+        _say(f"normwise errors gu gv gw: {errs}")
+        assert max(errs) <= 1e-11, errs
