@@ -219,8 +219,10 @@ int ibm_stage_vjp(ibm_ctx* c, const void* u, const void* v, const void* w, doubl
  * and must divide nx; ty in {1,2,4,8}; kz >= 1; wpb in 1..4.  A batch accepts
  * ty <= 2.  The shape only
  * changes speed and the summation order of the drag, never the divergence or
- * forcing values.  ibm_get_tile reports the shape in use (the default comes
- * from the grid size).  Errors: IBM_E_ARG for an unsupported shape. */
+ * forcing values.  ibm_sgs_stress then runs on it too (one row per wave), in
+ * place of a shape the autotuner chose for it.  ibm_get_tile reports the
+ * dense pass's shape (the default comes from the grid size).  Errors:
+ * IBM_E_ARG for an unsupported shape. */
 int ibm_set_tile(ibm_ctx* c, int vx, int ty, int kz, int wpb);
 int ibm_get_tile(const ibm_ctx* c, int out[4]);
 
@@ -230,7 +232,10 @@ int ibm_get_tile(const ibm_ctx* c, int out[4]);
  * and keep the fastest.  cache_path (nullable): a JSON file, one entry per
  * grid shape, dtype, precision and GPU architecture; a cached shape is reused
  * without timing unless IBM_TUNE_FORCE.  IBM_TUNE_BATCH restricts the search
- * to shapes the batched kernels accept (ty <= 2).  Synchronises ``stream``. */
+ * to shapes the batched kernels accept (ty <= 2).  Without it the Smagorinsky
+ * kernel of ibm_sgs_stress gets a tile of its own the same way (one row per
+ * wave; cached under the key ending in "sgs"); otherwise, and after
+ * ibm_set_tile, it runs on the dense pass's tile.  Synchronises ``stream``. */
 enum { IBM_TUNE_FORCE = 1, IBM_TUNE_BATCH = 2 };
 int ibm_autotune(ibm_ctx* c, const char* cache_path, int flags, void* stream);
 

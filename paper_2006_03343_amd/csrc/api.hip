@@ -319,7 +319,7 @@ int ibm_sgs_stress(ibm_ctx* c, const void* phi_uv, const void* phi_w, const void
     }
     if (!finite_pos(cs) || !finite_pos(kappa))
         return fail(IBM_E_RANGE, "%s: cs and kappa must be finite and > 0", fn);
-    TileCfg cfg = c->cfg;
+    TileCfg cfg = c->sgs_tuned ? c->sgs_cfg : c->cfg;
     cfg.ty = 1;
     bool vec = cfg.vx > 1;
     const void* vecs[6] = {phi_uv, phi_w, u, v, w, log_z0};
@@ -386,6 +386,7 @@ int ibm_set_tile(ibm_ctx* c, int vx, int ty, int kz, int wpb) {
                     kz, wpb);
     DeviceScope dg(c->device);
     c->cfg = t;
+    c->sgs_tuned = false;   // an explicit tile governs the Smagorinsky kernel too
     ++c->gen;
     return c->prepared ? size_partials(c) : IBM_OK;
 }

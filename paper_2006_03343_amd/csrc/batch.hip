@@ -312,11 +312,13 @@ std::string arch_name(int dev) {
     return a.substr(0, a.find(':'));
 }
 
-std::string tune_key(const ibm_ctx* c, bool batch) {
+// what: "plain" (the dense pass), "batch" (its batched kernel) or "sgs" (the
+// Smagorinsky kernel)
+std::string tune_key(const ibm_ctx* c, const char* what) {
     char buf[256];
     snprintf(buf, sizeof(buf), "%s|%s|%s|%dx%dx%d|%s", arch_name(c->device).c_str(),
              c->dtype == IBM_F64 ? "f64" : "f32", c->precision == IBM_PREC_MIXED ? "mixed" : "plain",
-             c->g.nx, c->g.ny, c->g.nz, batch ? "batch" : "plain");
+             c->g.nx, c->g.ny, c->g.nz, what);
     return buf;
 }
 
@@ -360,6 +362,16 @@ void write_cache(const char* path, const std::map<std::string, std::vector<doubl
     std::rename(tmp.c_str(), path);
 }
 
+bool cached(const std::map<std::string, std::vector<double>>& m, const std::string& key, TileCfg& t) {
+    auto it = m.find(key);
+    if (it == m.end()) return false;
+    t.vx = (int)it->second[0];
+    t.ty = (int)it->second[1];
+    t.kz = (int)it->second[2];
+    t.wpb = (int)it->second[3];
+    return true;
+}
+
 int set_cfg(ibm_ctx* c, const TileCfg& t) {
     c->cfg = t;
     ++c->gen;
@@ -369,21 +381,28 @@ int set_cfg(ibm_ctx* c, const TileCfg& t) {
 }  // namespace
 
 // Time candidate tile shapes of the dense pass on this context's grid (scratch
-// fields, so caller data is untouched) and keep the fastest.
+// fields, so caller data is untouched) and keep the fastest; outside batch
+// tuning also those of the Smagorinsky kernel (one row per wave), whose best
+// shape differs from the dense pass's (it reads five fields and writes six).
 int autotune(ibm_ctx* c, const char* cache_path, int flags, hipStream_t s) {
     const bool batch = flags & IBM_TUNE_BATCH;
-    const std::string key = tune_key(c, batch);
+    const std::string key = tune_key(c, batch ? "batch" : "plain");
+    const std::string skey = tune_key(c, "sgs");
+    bool dense = true, sgs = !batch;
     if (cache_path && !(flags & IBM_TUNE_FORCE)) {
-        auto m = read_cache(cache_path);
-        auto it = m.find(key);
-        if (it != m.end()) {
-            TileCfg t;
-            t.vx = (int)it->second[0];
-            t.ty = (int)it->second[1];
-            t.kz = (int)it->second[2];
-            t.wpb = (int)it->second[3];
-            if (tile_supported(c, t)) return set_cfg(c, t);
+        const auto m = read_cache(cache_path);
+        TileCfg t;
+        if (cached(m, key, t) && tile_supported(c, t)) {
+            const int rc = set_cfg(c, t);
+            if (rc) return rc;
+            dense = false;
         }
+        if (sgs && cached(m, skey, t) && t.ty == 1 && tile_supported(c, t)) {
+            c->sgs_cfg = t;
+            c->sgs_tuned = true;
+            sgs = false;
+        }
+        if (!dense && !sgs) return IBM_OK;
     }
     const size_t ts = tsize(c);
     const size_t fb = ((size_t)c->n * ts + 255) / 256 * 256;
@@ -406,37 +425,68 @@ int autotune(ibm_ctx* c, const char* cache_path, int flags, hipStream_t s) {
     IBM_HIP(hipEventCreate(&e0));
     IBM_HIP(hipEventCreate(&e1));
     const TileCfg keep = c->cfg;
-    TileCfg best = keep;
-    float best_ms = 1e30f;
+    TileCfg best = keep, sbest = c->cfg;
+    float best_ms = 1e30f, sbest_ms = 1e30f;
     const int vxs[3] = {4, 2, 1};
     const int tys[3] = {1, 2, 4};
     const int kzs[6] = {4, 8, 16, 32, 64, 128};
+    const int skzs[5] = {16, 32, 64, 128, 256};
     const int wpbs[3] = {1, 2, 4};
     int rc = IBM_OK;
-    for (int vx : vxs)
-        for (int ty : tys)
-            for (int kz : kzs)
+    // mean of 5 launches after one untimed
+    auto timed = [&](auto launch, float& ms) -> int {
+        int r = launch();
+        if (r) return r;
+        IBM_HIP(hipEventRecord(e0, s));
+        for (int k = 0; k < 5 && r == IBM_OK; ++k) r = launch();
+        if (r) return r;
+        IBM_HIP(hipEventRecord(e1, s));
+        IBM_HIP(hipEventSynchronize(e1));
+        IBM_HIP(hipEventElapsedTime(&ms, e0, e1));
+        ms /= 5.f;
+        return IBM_OK;
+    };
+    if (dense)
+        for (int vx : vxs)
+            for (int ty : tys)
+                for (int kz : kzs)
+                    for (int wpb : wpbs) {
+                        TileCfg t;
+                        t.vx = vx;
+                        t.ty = ty;
+                        t.kz = kz;
+                        t.wpb = wpb;
+                        if (!tile_supported(c, t) || (batch && ty > 2)) continue;
+                        if (kz > 2 * c->g.nz && kz != kzs[0]) continue;
+                        if ((rc = set_cfg(c, t))) goto done;
+                        float ms = 0.f;
+                        rc = timed([&] { return launch_apply(c, t, tau, us, gp, 0.01, dv, drag, s); }, ms);
+                        if (rc) goto done;
+                        if (ms < best_ms) {
+                            best_ms = ms;
+                            best = t;
+                        }
+                    }
+    if (sgs)
+        for (int vx : vxs)
+            for (int kz : skzs)
                 for (int wpb : wpbs) {
                     TileCfg t;
                     t.vx = vx;
-                    t.ty = ty;
+                    t.ty = 1;
                     t.kz = kz;
                     t.wpb = wpb;
-                    if (!tile_supported(c, t) || (batch && ty > 2)) continue;
-                    if (kz > 2 * c->g.nz && kz != kzs[0]) continue;
-                    if ((rc = set_cfg(c, t))) goto done;
-                    if ((rc = launch_apply(c, t, tau, us, gp, 0.01, dv, drag, s))) goto done;
-                    IBM_HIP(hipEventRecord(e0, s));
-                    for (int r = 0; r < 5 && rc == IBM_OK; ++r)
-                        rc = launch_apply(c, t, tau, us, gp, 0.01, dv, drag, s);
-                    if (rc) goto done;
-                    IBM_HIP(hipEventRecord(e1, s));
-                    IBM_HIP(hipEventSynchronize(e1));
+                    if (!tile_supported(c, t)) continue;
+                    if (kz > 2 * c->g.nz && kz != skzs[0]) continue;
                     float ms = 0.f;
-                    IBM_HIP(hipEventElapsedTime(&ms, e0, e1));
-                    if (ms < best_ms) {
-                        best_ms = ms;
-                        best = t;
+                    rc = timed([&] {
+                        return launch_sgs(c, t, gp[0], gp[1], us[0], us[1], us[2], 1e-3, nullptr, 0.16,
+                                          0.4, tau, s);
+                    }, ms);
+                    if (rc) goto done;
+                    if (ms < sbest_ms) {
+                        sbest_ms = ms;
+                        sbest = t;
                     }
                 }
 done:
@@ -449,10 +499,15 @@ done:
         set_cfg(c, keep);
         return rc;
     }
-    rc = set_cfg(c, best);
+    if (dense) rc = set_cfg(c, best);
+    if (rc == IBM_OK && sgs) {
+        c->sgs_cfg = sbest;
+        c->sgs_tuned = true;
+    }
     if (rc == IBM_OK && cache_path) {
         auto m = read_cache(cache_path);
-        m[key] = {(double)best.vx, (double)best.ty, (double)best.kz, (double)best.wpb, best_ms / 5.0};
+        if (dense) m[key] = {(double)best.vx, (double)best.ty, (double)best.kz, (double)best.wpb, best_ms};
+        if (sgs) m[skey] = {(double)sbest.vx, 1.0, (double)sbest.kz, (double)sbest.wpb, sbest_ms};
         write_cache(cache_path, m);
     }
     return rc;

@@ -126,6 +126,8 @@ struct ibm_ctx {
     double* ap_partials = nullptr;      // apply wave slots (3 per tile)
     long ap_cap = 0;                    // in doubles
     ibm::TileCfg cfg;
+    ibm::TileCfg sgs_cfg;               // the Smagorinsky kernel's tile (ty = 1) ...
+    bool sgs_tuned = false;             // ... when the autotuner chose one; else cfg's
     ibm::AdjointMap adj;
     ibm::SpectralTw spec;
     ibm::ProjWs proj;

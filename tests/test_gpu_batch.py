@@ -208,14 +208,28 @@ def test_autotune_cache(tmp_path):
     ctx = ibm.Context(g.nx, g.ny, g.nz, dtype=torch.float32, precision="mixed", device=dev)
     ctx.prepare(T(wl.phi_uv), T(wl.phi_w), 1.5, 1.5)
     path = str(tmp_path / "tune.json")
+    vel = [T(wl.u), T(wl.v), T(wl.w)]
+    pu, pw = T(wl.phi_uv), T(wl.phi_w)
+
+    def sgs():
+        tau = [torch.empty_like(vel[0]) for _ in range(6)]
+        ctx.sgs_stress(pu, pw, *vel, tau, z0=1e-3)
+        return [t.cpu().numpy() for t in tau]
+
+    before = sgs()                                 # on the default tile
     t1 = ctx.autotune(path)
     entries = json.load(open(path))
-    assert len(entries) == 1 and list(entries.values())[0][:4] == list(t1)
+    assert len(entries) == 2                       # the dense pass's shape and the Smagorinsky kernel's
+    dense = [v for k, v in entries.items() if k.endswith("|plain")]
+    own = [v for k, v in entries.items() if k.endswith("|sgs")]
+    assert len(dense) == 1 and dense[0][:4] == list(t1) and len(own) == 1 and own[0][1] == 1
+    after = sgs()                                  # on its own tuned tile
+    assert all(np.array_equal(x, y) for x, y in zip(before, after))
     ctx.set_tile(1, 1, 4, 1)
     t2 = ctx.autotune(path)                        # read back from the cache
     assert t2 == t1
     t3 = ctx.autotune(path, force=True, batch=True)
-    assert t3[1] <= 2 and len(json.load(open(path))) == 2
+    assert t3[1] <= 2 and len(json.load(open(path))) == 3
     # the divergence does not depend on the tile shape
     wls = _cases("f32")[:3]
     b, fs = _batch(wls, None, torch.float32, "mixed", dev)
