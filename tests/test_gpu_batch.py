@@ -3,7 +3,10 @@
 * every case of a batch equals a plain per-case call (ibm_wall_stress then
   ibm_apply) with the same tile shape, bit for bit: stress, divergence,
   forced velocity, drag and band statistics; one case is also held to the
-  oracle;
+  oracle; also a batch of one-column, one-row, one- and two-plane and ragged
+  cases;
+* the 64-case ensemble the benchmark times (105.6 M points, one graph
+  launch): one case of each grid shape against the oracle, every node;
 * replays of the captured hipGraph, with eager work and synchronisations in
   between, each equal the eager result;
 * the autotuner writes and re-reads its cache and keeps a valid shape.
@@ -275,3 +278,31 @@ def test_degenerate_cases(ora, dtype, prec):
                ustar=fs[5].ustar.cpu().numpy(), drag=fs[5].drag.cpu().numpy(),
                stats=fs[5].stats.cpu().numpy(), mask=b.case(5).mask(), counts=b.case(5).counts())
     compare(out, ref, wls[5], TOL[dtype])
+
+
+def test_ensemble_full_size(ora, tmp_path):
+    """The 64-case ensemble as the benchmark times it (105.6 M points, float32
+    mixed, tiles from the shipped autotuner cache, one graph launch): one case
+    of each grid shape against the oracle's stage, every node."""
+    import shutil
+    import paper_2006_03343_amd as ibm
+    torch, dev = torch_dev()
+    shapes = configs.ensemble_shapes(64)
+    wls = [configs.bumps_case(i, s).cast(np.float32) for i, s in enumerate(shapes)]
+    _say(f"ensemble of {len(wls)} cases, {sum(a * b * c for a, b, c in shapes)} points, f32 mixed")
+    cache = str(tmp_path / "tune.json")
+    shutil.copy(os.path.join(os.path.dirname(ibm.__file__), "tune_gfx950.json"), cache)
+    b, fs = _batch(wls, None, torch.float32, "mixed", dev)
+    b.tune(cache)
+    b.capture()
+    b.launch()
+    torch.cuda.synchronize()
+    picked = sorted({s: i for i, s in reversed(list(enumerate(shapes)))}.values())
+    for i in picked:
+        _say(f"case {i} {shapes[i]} tile {b.case(i).get_tile()} vs the oracle")
+        out = dict(tau=fs[i].tau.cpu().numpy(), div=fs[i].div.cpu().numpy(),
+                   ustar=fs[i].ustar.cpu().numpy(), drag=fs[i].drag.cpu().numpy(),
+                   stats=fs[i].stats.cpu().numpy(), mask=b.case(i).mask(),
+                   counts=b.case(i).counts())
+        errs = compare(out, ora.stage(wls[i]), wls[i], TOL["f32"])
+        _say(f"errors {errs}")
