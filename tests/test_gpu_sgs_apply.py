@@ -11,7 +11,9 @@ tau anywhere but a band node would show.  Cases: the cube, a ragged ridge
 hill in three
 precisions, a per-node log z0 field, grids of one column, one row, one or
 two planes and two rows, the 512 x 256 x 256 hill; the fused pass against
-ibm_sgs_stress + ibm_wall_stress + ibm_apply on the GPU (div and ustar bit for bit);
+ibm_sgs_stress + ibm_wall_stress + ibm_apply on the GPU (div and ustar bit for bit),
+also on 4096 x 4096 x 30 float64 and 8192 x 4096 x 30 float32 grids whose planes
+shrink the chunks to 27;
 error paths.
 """
 from dataclasses import replace
@@ -178,3 +180,53 @@ def test_errors():
     with pytest.raises(ibm.IbmError) as e:
         ctx.apply_sgs(phi, phi, f[0], f[1], f[2], f[3:9], [f[9], f[10], f[11]], div, z0=0.0)
     assert e.value.code == _lib.IBM_E_RANGE
+
+
+@pytest.mark.parametrize("dtype,nx,ny", [("f64", 4096, 4096), ("f32", 8192, 4096)])
+def test_large_plane_chunks(dtype, nx, ny):
+    """x-y planes so large that a block's slab of 32 planes would pass the
+    4 GiB reach of the fused pass's 32-bit offsets: 4096 x 4096 x 30 in float64
+    and 8192 x 4096 x 30 in float32 mixed (503 M and 1007 M nodes, 4 GB per
+    field) march in chunks of 27 planes and a ragged 3 (in float the loads run
+    two planes ahead).  Against ibm_sgs_stress + ibm_wall_stress + ibm_apply,
+    div and ustar bit for bit, drag to rounding."""
+    import torch
+    import paper_2006_03343_amd as ibm
+    _, dev = torch_dev()
+    if torch.cuda.get_device_properties(dev).total_memory < 150 * 2 ** 30:
+        pytest.skip("needs about 110 GiB of device memory")
+    nz = 30
+    _say(f"sgs+apply {nx}x{ny}x{nz} {dtype} wavy wall, chunks of 27 planes")
+    f64 = torch.float64
+    tdt = f64 if dtype == "f64" else torch.float32
+    k = torch.arange(nz, dtype=f64, device=dev).view(nz, 1, 1)
+    zs = 1.25 + 0.5 * torch.sin(torch.arange(nx, dtype=f64, device=dev) * (6.283185307179586 / nx))
+    phi_uv = ((k + 0.5) - zs.view(1, 1, nx)).to(tdt).expand(nz, ny, nx).contiguous()
+    phi_w = (k - zs.view(1, 1, nx)).to(tdt).expand(nz, ny, nx).contiguous()
+    ctx = ibm.Context(nx, ny, nz, dtype=tdt, precision="plain" if dtype == "f64" else "mixed",
+                      device=dev)
+    ctx.prepare(phi_uv, phi_w, 1.5, None, KAPPA)
+    assert ctx.band_size(0) > 0 and ctx.band_size(1) > 0
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(11)
+    vel = [torch.randn((nz, ny, nx), generator=gen, dtype=tdt, device=dev) + (3.0 if c == 0 else 0.0)
+           for c in range(3)]
+    tau = [torch.empty_like(vel[0]) for _ in range(6)]
+    ust = [[v.clone() for v in vel] for _ in range(2)]
+    div = [[torch.empty_like(vel[0]) for _ in range(3)] for _ in range(2)]
+    drag = [torch.zeros(3, dtype=f64, device=dev) for _ in range(2)]
+    ctx.sgs_stress(phi_uv, phi_w, *vel, tau, z0=1e-3, cs=CS, kappa=KAPPA)
+    ctx.wall_stress(*vel, tau, z0=1e-3)
+    ctx.apply(tau, ust[0], div[0], dt=0.01, drag=drag[0])
+    # tau's band values are the wall stress either way; the fused pass reads no other
+    ctx.apply_sgs(phi_uv, phi_w, *vel, tau, ust[1], div[1], z0=1e-3, cs=CS, kappa=KAPPA,
+                  dt=0.01, drag=drag[1])
+    torch.cuda.synchronize()
+    for c in range(3):
+        assert torch.equal(div[0][c], div[1][c]), f"div component {c}"
+        assert torch.equal(ust[0][c], ust[1][c]), f"ustar component {c}"
+        assert bool(torch.isfinite(div[1][c]).all())
+    assert torch.allclose(drag[0], drag[1], rtol=1e-12 if dtype == "f64" else 1e-6, atol=0.0)
+    _say("div and ustar identical to the three-call path")
+    del vel, tau, ust, div, phi_uv, phi_w, ctx
+    torch.cuda.empty_cache()
