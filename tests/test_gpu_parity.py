@@ -5,6 +5,8 @@ float64 storage, 2e-5 for float32 (plain and mixed); masks, band lists and
 class counts identical; stress values off the band identical (copied or
 zeroed); drag within tol * dV * sum |div|.  The oracle is always fed the
 exact stored values the GPU sees (float32 inputs widened to float64).
+The largest case, 4096 x 4096 x 127 (2.13e9 nodes, near the 2^31 - 1 node limit
+of a context), is built from copies of a periodic cell and checked copy by copy.
 """
 import numpy as np
 import pytest
@@ -250,3 +252,78 @@ def test_hill_full_size_mixed(ora):
     _say(f"tile {ctx.get_tile()}")
     errs = compare(out, _ref(ora, wl), wl, TOL["f32"])
     _say(f"errors {errs}")
+
+
+def test_maximum_size_periodic_copies(ora):
+    """The largest grid a context takes, near its 2^31 - 1 node limit: 4096 x 4096
+    x 127 in float32 mixed (2.13e9 nodes), built as 64 x 64 copies of a 64 x 64 x
+    127 hill cell.  The grid is periodic in x and y, so each copy's outputs are
+    the cell's own: every copy must equal the first bit for bit (tau, div, ustar,
+    class bytes), the first must meet the parity bar against the oracle's stage
+    on the cell, and class counts, drag and band statistics are 4096 times the
+    cell's (the maximum |U_r| the cell's)."""
+    import torch
+    import paper_2006_03343_amd as ibm
+    _, dev = torch_dev()
+    if torch.cuda.get_device_properties(dev).total_memory < 200 * 2 ** 30:
+        pytest.skip("needs about 180 GiB of device memory")
+    cell = configs.hill(64, 64, 127, H=8.0, L=24.0, x0=32.0, y0=32.0).cast(np.float32)
+    g = cell.grid
+    rx = ry = 64
+    nx, ny, nz = g.nx * rx, g.ny * ry, g.nz
+    reps = rx * ry
+    assert nx * ny * nz <= 2 ** 31 - 1
+    _say(f"stage {nx}x{ny}x{nz} f32 mixed: {rx}x{ry} copies of a {g.nx}x{g.ny}x{g.nz} hill cell")
+
+    def big(a):
+        small = torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+        return small.repeat(1, ry, rx)
+
+    def copies(f):
+        return f.view(nz, ry, g.ny, rx, g.nx)
+
+    ctx = ibm.Context(nx, ny, nz, g.dx, g.dy, g.dz, dtype=torch.float32, precision="mixed",
+                      device=dev)
+    pu, pw = big(cell.phi_uv), big(cell.phi_w)
+    ctx.prepare(pu, pw, cell.band_width, cell.phi_c, cell.kappa)
+    del pu, pw
+    u, v, w = big(cell.u), big(cell.v), big(cell.w)
+    tau = [big(t) for t in cell.tau]
+    ustar = [u.clone(), v.clone(), w.clone()]
+    div = [torch.empty_like(u) for _ in range(3)]
+    gp = [big(t) for t in cell.gradp]
+    drag = torch.zeros(3, dtype=torch.float64, device=dev)
+    st = torch.zeros(4, dtype=torch.float64, device=dev)
+    ctx.wall_stress(u, v, w, tau, z0=cell.z0, stats=st)
+    ctx.apply(tau, ustar, div, gradp=gp, dt=cell.dt, drag=drag)
+    torch.cuda.synchronize()
+    _say("stage done; comparing the copies")
+    first = {}
+    for name, fs in (("tau", tau), ("div", div), ("ustar", ustar)):
+        out = []
+        for c, f in enumerate(fs):
+            cv = copies(f)
+            assert bool((cv == cv[:, :1, :, :1, :]).all()), f"{name}[{c}]: copies differ"
+            out.append(cv[:, 0, :, 0, :].cpu().numpy())
+        first[name] = np.stack(out)
+    del u, v, w, tau, ustar, div, gp
+    ref = ora.stage(cell)
+    mask = ctx.mask().reshape(nz, ry, g.ny, rx, g.nx)
+    for k in range(nz):
+        assert (mask[k] == ref["mask"][k][None, :, None, :]).all(), f"class bytes, plane {k}"
+    del mask
+    assert list(ctx.counts()) == [reps * int(c) for c in ref["counts"]]
+    first.update(mask=ref["mask"], counts=ref["counts"], drag=None, stats=None)
+    errs = compare(first, ref, cell, TOL["f32"])
+    # drag and statistics over all copies
+    scale = reps * g.dv * np.array([np.abs(d).sum() for d in ref["div"]])
+    errs["drag"] = float(np.max(np.abs(drag.cpu().numpy() - reps * ref["drag"]) / scale))
+    s, got = ref["stats"], st.cpu().numpy()
+    errs["stats_sum"] = float(np.abs(got[:2] - reps * s[:2]).max() / (reps * np.abs(s[:2]).max()))
+    errs["stats_max"] = abs(got[2] - s[2]) / s[2]
+    band = int(((ref["mask"] & 3) == 1).sum() + (((ref["mask"] >> 2) & 3) == 1).sum())
+    assert got[3] == reps * band
+    _say(f"errors {errs}")
+    assert max(errs.values()) <= TOL["f32"], errs
+    del ctx
+    torch.cuda.empty_cache()
