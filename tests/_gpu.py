@@ -93,3 +93,21 @@ def compare(out, ref, wl, tol, check_masks=True):
     bad = {k: v for k, v in errs.items() if not v <= tol}
     assert not bad, f"above {tol}: {bad}"
     return errs
+
+
+def tiled(a, dtype, ry, rx):
+    """A cell's field (nz, cy, cx) repeated ry times along y and rx times along x
+    on the GPU: the field of a grid that is ry x rx periodic copies of the cell."""
+    import torch
+    _, dev = torch_dev()
+    small = torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev, dtype)
+    return small.repeat(1, ry, rx)
+
+
+def first_copy(f, cell_shape, ry, rx):
+    """Assert that every copy of the cell in the periodic field f equals the
+    first bit for bit; return the first as a numpy array."""
+    nz, cy, cx = cell_shape
+    cv = f.view(nz, ry, cy, rx, cx)
+    assert bool((cv == cv[:, :1, :, :1, :]).all()), "periodic copies differ"
+    return cv[:, 0, :, 0, :].cpu().numpy()

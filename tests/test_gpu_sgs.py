@@ -5,14 +5,16 @@ Bars (normwise per component: max |gpu - oracle| / max |oracle|): 1e-12 for
 float64 storage, 2e-5 for float32; the oracle reads exactly the stored values.
 Cases: the cube, a ragged ridge (no tile dimension divides the grid), a
 small hill, a per-node log z0 field, one-column / one-row / one-plane and
-anisotropic grids, the 512 x 256 x 256 hill; tile shapes change nothing
+anisotropic grids, the 512 x 256 x 256 hill, and 4096 x 4096 x 127 grids (near
+the 2^31 - 1 node limit of a context) made of periodic copies of a hill cell,
+each copy equal to the first; tile shapes change nothing
 (bit for bit); views that are not 16-byte aligned take the one-node-per-lane
 path and agree too.
 """
 import numpy as np
 import pytest
 
-from _gpu import TOL, normwise, torch_dev
+from _gpu import TOL, first_copy, normwise, tiled, torch_dev
 from workloads import Grid, configs
 
 pytestmark = pytest.mark.gpu
@@ -147,3 +149,41 @@ def test_hill_full_size(ora):
     _say("sgs hill 512x256x256 f32")
     _, errs = _check(ora, wl, "f32")
     _say(f"errors {errs}")
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_maximum_size_periodic_copies(ora, dtype):
+    """4096 x 4096 x 127 (2.13e9 nodes) as 64 x 64 copies of a 64 x 64 x 127 hill
+    cell: the grid is periodic in x and y, so every copy's stress must equal the
+    first's bit for bit, and the first must meet the bar against the oracle's
+    Smagorinsky stress on the cell."""
+    import torch
+    import paper_2006_03343_amd as ibm
+    _, dev = torch_dev()
+    need = 200 if dtype == "f64" else 110
+    if torch.cuda.get_device_properties(dev).total_memory < need * 2 ** 30:
+        pytest.skip(f"needs about {need - 10} GiB of device memory")
+    torch.cuda.empty_cache()
+    cell = configs.hill(64, 64, 127, H=8.0, L=24.0, x0=32.0, y0=32.0)
+    if dtype == "f32":
+        cell = cell.cast(np.float32)
+    g = cell.grid
+    rx = ry = 64
+    nx, ny, nz = g.nx * rx, g.ny * ry, g.nz
+    assert nx * ny * nz <= 2 ** 31 - 1
+    _say(f"sgs {nx}x{ny}x{nz} {dtype}: {rx}x{ry} copies of a {g.nx}x{g.ny}x{g.nz} hill cell")
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    big = lambda a: tiled(a, tdt, ry, rx)
+    ctx = ibm.Context(nx, ny, nz, g.dx, g.dy, g.dz, dtype=tdt, device=dev)
+    tau = [torch.empty((nz, ny, nx), dtype=tdt, device=dev) for _ in range(6)]
+    ctx.sgs_stress(big(cell.phi_uv), big(cell.phi_w), big(cell.u), big(cell.v), big(cell.w), tau,
+                   z0=cell.z0, cs=CS, kappa=KAPPA)
+    torch.cuda.synchronize()
+    got = [first_copy(t, g.shape, ry, rx) for t in tau]
+    del tau, ctx
+    torch.cuda.empty_cache()
+    ref = ora.smagorinsky(g, cell.phi_uv, cell.phi_w, cell.u, cell.v, cell.w, z0=cell.z0,
+                          cs=CS, kappa=KAPPA)
+    errs = [normwise(a, b) for a, b in zip(got, ref)]
+    _say(f"errors {errs}")
+    assert max(errs) <= TOL[dtype], errs

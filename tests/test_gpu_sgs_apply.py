@@ -13,15 +13,16 @@ precisions, a per-node log z0 field, grids of one column, one row, one or
 two planes and two rows, the 512 x 256 x 256 hill; the fused pass against
 ibm_sgs_stress + ibm_wall_stress + ibm_apply on the GPU (div and ustar bit for bit),
 also on 4096 x 4096 x 30 float64 and 8192 x 4096 x 30 float32 grids whose planes
-shrink the chunks to 27;
-error paths.
+shrink the chunks to 27; a 4096 x 4096 x 127 grid (near the 2^31 - 1 node limit
+of a context) made of periodic copies of a hill cell, each copy equal to the
+first and the first against the oracle; error paths.
 """
 from dataclasses import replace
 
 import numpy as np
 import pytest
 
-from _gpu import TOL, normwise, torch_dev
+from _gpu import TOL, first_copy, normwise, tiled, torch_dev
 from workloads import Grid, configs
 
 pytestmark = pytest.mark.gpu
@@ -230,3 +231,52 @@ def test_large_plane_chunks(dtype, nx, ny):
     _say("div and ustar identical to the three-call path")
     del vel, tau, ust, div, phi_uv, phi_w, ctx
     torch.cuda.empty_cache()
+
+
+def test_maximum_size_periodic_copies(ora):
+    """4096 x 4096 x 127 in float32 mixed (2.13e9 nodes) as 64 x 64 copies of a
+    64 x 64 x 127 hill cell: every copy's div and ustar must equal the first's
+    bit for bit, the first must meet the bar against the oracle's Smagorinsky
+    stress fed to its stage on the cell, and the drag is 4096 times the cell's."""
+    import torch
+    import paper_2006_03343_amd as ibm
+    _, dev = torch_dev()
+    if torch.cuda.get_device_properties(dev).total_memory < 200 * 2 ** 30:
+        pytest.skip("needs about 190 GiB of device memory")
+    torch.cuda.empty_cache()
+    cell = configs.hill(64, 64, 127, H=8.0, L=24.0, x0=32.0, y0=32.0).cast(np.float32)
+    g = cell.grid
+    rx = ry = 64
+    nx, ny, nz = g.nx * rx, g.ny * ry, g.nz
+    reps = rx * ry
+    assert nx * ny * nz <= 2 ** 31 - 1
+    _say(f"sgs+apply {nx}x{ny}x{nz} f32 mixed: {rx}x{ry} copies of a {g.nx}x{g.ny}x{g.nz} hill cell")
+    big = lambda a: tiled(a, torch.float32, ry, rx)
+    ctx = ibm.Context(nx, ny, nz, g.dx, g.dy, g.dz, dtype=torch.float32, precision="mixed",
+                      device=dev)
+    pu, pw = big(cell.phi_uv), big(cell.phi_w)
+    ctx.prepare(pu, pw, cell.band_width, cell.phi_c, cell.kappa)
+    u, v, w = big(cell.u), big(cell.v), big(cell.w)
+    noise = np.random.default_rng(3).standard_normal((6,) + g.shape) * 50.0
+    tau = [big(a) for a in noise]
+    ustar = [u.clone(), v.clone(), w.clone()]
+    div = [torch.empty_like(u) for _ in range(3)]
+    gp = [big(t) for t in cell.gradp]
+    drag = torch.zeros(3, dtype=torch.float64, device=dev)
+    ctx.wall_stress(u, v, w, tau, z0=cell.z0)
+    ctx.apply_sgs(pu, pw, u, v, w, tau, ustar, div, z0=cell.z0, cs=CS, kappa=KAPPA, gradp=gp,
+                  dt=cell.dt, drag=drag)
+    torch.cuda.synchronize()
+    got = {name: [first_copy(f, g.shape, ry, rx) for f in fs]
+           for name, fs in (("div", div), ("ustar", ustar))}
+    del pu, pw, u, v, w, tau, ustar, div, gp, ctx
+    torch.cuda.empty_cache()
+    ref = _ref(ora, cell)
+    errs = {}
+    for c, nm in enumerate("xyz"):
+        errs["div_" + nm] = normwise(got["div"][c], ref["div"][c])
+        errs["ustar_" + nm] = normwise(got["ustar"][c], ref["ustar"][c])
+    scale = reps * g.dv * np.array([np.abs(d).sum() for d in ref["div"]])
+    errs["drag"] = float(np.max(np.abs(drag.cpu().numpy() - reps * ref["drag"]) / scale))
+    _say(f"errors {errs}")
+    assert max(errs.values()) <= TOL["f32"], errs
