@@ -13,13 +13,16 @@
   the oracle's dense solve of those modes' systems (normwise over the
   sampled modes: float32 rounding of the transforms scales with the whole
   field, not with one high mode's small amplitude);
+* 2048 x 2048 x 511 in float32 (near the 2^31 - 1 node limit of a context, at
+  the longest float transforms), made of periodic copies of a small cell:
+  every node of every copy against the oracle's projection of the cell;
 * AB2 against its formula; error paths (lengths beyond the longest transform
   refused).
 """
 import numpy as np
 import pytest
 
-from _gpu import TOL, normwise, torch_dev
+from _gpu import TOL, normwise, tiled, torch_dev
 from workloads import Grid
 
 pytestmark = pytest.mark.gpu
@@ -172,3 +175,46 @@ def test_errors():
         with pytest.raises(ibm.IbmError) as e:
             ctx.pressure_project(f[:3], 0.01, [torch.empty_like(f[0]) for _ in range(3)], f[3])
         assert e.value.code == _lib.IBM_E_UNSUPPORTED
+
+
+def test_maximum_size_periodic_copies(ora):
+    """2048 x 2048 x 511 in float32 (2.14e9 nodes) as 128 x 128 copies of a
+    16 x 16 x 511 cell of random velocities.  The data hold only the modes
+    whose wavenumbers the cell has (its Nyquist modes land on the grid's), so
+    the projected velocity and the pressure are the cell's, copied: every node
+    of every copy against the oracle's projection of the cell, normwise per
+    field within the float32 bar."""
+    import torch
+    import paper_2006_03343_amd as ibm
+    _, dev = torch_dev()
+    if torch.cuda.get_device_properties(dev).total_memory < 200 * 2 ** 30:
+        pytest.skip("needs about 150 GiB of device memory")
+    torch.cuda.empty_cache()
+    cell = Grid(16, 16, 511)
+    vel = [a.astype(np.float32).astype(np.float64) for a in _fields(cell, 21, wall=False)]
+    rx = ry = 128
+    nx, ny, nz = cell.nx * rx, cell.ny * ry, cell.nz
+    assert nx * ny * nz <= 2 ** 31 - 1
+    dt = 0.013
+    _say(f"projection {nx}x{ny}x{nz} f32: {rx}x{ry} copies of a {cell.nx}x{cell.ny}x{nz} cell")
+    ctx = ibm.Context(nx, ny, nz, cell.dx, cell.dy, cell.dz, dtype=torch.float32, device=dev)
+    us = [tiled(a, torch.float32, ry, rx) for a in vel]
+    out = [torch.empty_like(us[0]) for _ in range(3)]
+    p = torch.empty_like(us[0])
+    ctx.pressure_project(us, dt, out, p)
+    torch.cuda.synchronize()
+    del us, ctx
+    ref = ora.pressure_project(cell, vel, dt)
+    errs = []
+    for f, r in zip(out + [p], ref):
+        rt = torch.from_numpy(np.ascontiguousarray(r, dtype=np.float64)).to(dev)
+        cv = f.view(nz, ry, cell.ny, rx, cell.nx)
+        num = 0.0
+        for k0 in range(0, nz, 32):
+            d = (cv[k0:k0 + 32].double() - rt[k0:k0 + 32, None, :, None, :]).abs().max()
+            num = max(num, float(d))
+        errs.append(num / float(np.abs(r).max()))
+    del out, p
+    torch.cuda.empty_cache()
+    _say(f"errors u v w p {errs}")
+    assert max(errs) <= TOL["f32"], errs
