@@ -9,13 +9,15 @@ small hills in three precisions, per-node log z0, grids with one row, one
 column, one plane and two nodes, the 512 x 256 x 256 hill, fields one
 element into their buffers (float32: the y pass then takes one column per
 access instead of 8-byte column pairs), the longest transforms along x and
-along y in both precisions; a grid size that is not a power of two, or one
-beyond the longest transform, is refused.
+along y in both precisions, 2048 x 2048 x 511 (near the 2^31 - 1 node limit
+of a context) as periodic copies of a hill cell, every copy against the
+oracle on the cell; a grid size that is not a power of two, or one beyond the
+longest transform, is refused.
 """
 import numpy as np
 import pytest
 
-from _gpu import TOL, compare, run_gpu, torch_dev
+from _gpu import TOL, compare, first_copy, normwise, run_gpu, tiled, torch_dev
 from workloads import Grid, configs
 
 pytestmark = pytest.mark.gpu
@@ -140,3 +142,72 @@ def test_beyond_maximum_length(shape, dtype):
     with pytest.raises(ibm.IbmError) as e:
         ctx.apply_spectral(f, u, d)
     assert e.value.code == _lib.IBM_E_UNSUPPORTED
+
+
+def test_maximum_size_periodic_copies(ora):
+    """2048 x 2048 x 511 in float32 mixed (2.14e9 nodes, at the longest float
+    transforms) as 128 x 128 copies of a 16 x 16 x 511 hill cell.  The fields
+    hold only the cell's wavenumbers (its Nyquist modes land on the grid's), so
+    each copy's outputs are the cell's: the wall stress, a local operation,
+    equal in every copy bit for bit; div and ustar at every node of every copy
+    against the oracle's spectral stage on the cell; class bytes in every copy
+    and counts 16384 times the cell's; the drag 16384 times the cell's."""
+    import torch
+    import paper_2006_03343_amd as ibm
+    _, dev = torch_dev()
+    if torch.cuda.get_device_properties(dev).total_memory < 200 * 2 ** 30:
+        pytest.skip("needs about 180 GiB of device memory")
+    torch.cuda.empty_cache()
+    cell = configs.hill(16, 16, 511, H=4.0, L=6.0, x0=8.0, y0=8.0).cast(np.float32)
+    g = cell.grid
+    rx = ry = 128
+    nx, ny, nz = g.nx * rx, g.ny * ry, g.nz
+    reps = rx * ry
+    assert nx * ny * nz <= 2 ** 31 - 1
+    _say(f"spectral {nx}x{ny}x{nz} f32 mixed: {rx}x{ry} copies of a {g.nx}x{g.ny}x{nz} hill cell")
+    big = lambda a: tiled(a, torch.float32, ry, rx)
+    ctx = ibm.Context(nx, ny, nz, g.dx, g.dy, g.dz, dtype=torch.float32, precision="mixed",
+                      device=dev)
+    pu, pw = big(cell.phi_uv), big(cell.phi_w)
+    ctx.prepare(pu, pw, cell.band_width, cell.phi_c, cell.kappa)
+    del pu, pw
+    u, v, w = big(cell.u), big(cell.v), big(cell.w)
+    tau = [big(t) for t in cell.tau]
+    ustar = [u.clone(), v.clone(), w.clone()]
+    div = [torch.empty_like(u) for _ in range(3)]
+    gp = [big(t) for t in cell.gradp]
+    drag = torch.zeros(3, dtype=torch.float64, device=dev)
+    ctx.wall_stress(u, v, w, tau, z0=cell.z0)
+    ctx.apply_spectral(tau, ustar, div, gradp=gp, dt=cell.dt, drag=drag)
+    torch.cuda.synchronize()
+    ref = _ref(ora, cell)
+    got_tau = [first_copy(t, g.shape, ry, rx) for t in tau]
+    del u, v, w, tau, gp
+    errs = {}
+    band_uv = (ref["mask"] & 3) == 1
+    band_w = ((ref["mask"] >> 2) & 3) == 1
+    for c in range(6):
+        sel = band_uv if c < 4 else band_w
+        errs[f"tau{c}"] = normwise(got_tau[c][sel], ref["tau"][c][sel])
+        assert (got_tau[c][~sel] == ref["tau"][c][~sel]).all(), f"tau {c} off the band"
+    for name, fs in (("div", div), ("ustar", ustar)):
+        for c, f in enumerate(fs):
+            rt = torch.from_numpy(np.ascontiguousarray(ref[name][c], dtype=np.float64)).to(dev)
+            cv = f.view(nz, ry, g.ny, rx, g.nx)
+            num = 0.0
+            for k0 in range(0, nz, 32):
+                d = (cv[k0:k0 + 32].double() - rt[k0:k0 + 32, None, :, None, :]).abs().max()
+                num = max(num, float(d))
+            errs[f"{name}{c}"] = num / float(np.abs(ref[name][c]).max())
+    del div, ustar
+    mask = ctx.mask().reshape(nz, ry, g.ny, rx, g.nx)
+    for k in range(nz):
+        assert (mask[k] == ref["mask"][k][None, :, None, :]).all(), f"class bytes, plane {k}"
+    del mask
+    assert list(ctx.counts()) == [reps * int(c) for c in ref["counts"]]
+    scale = reps * g.dv * np.array([np.abs(d).sum() for d in ref["div"]])
+    errs["drag"] = float(np.max(np.abs(drag.cpu().numpy() - reps * ref["drag"]) / scale))
+    del ctx
+    torch.cuda.empty_cache()
+    _say(f"errors {errs}")
+    assert max(errs.values()) <= TOL["f32"], errs
