@@ -37,6 +37,8 @@ __global__ void k_vjp_dense(const T* __restrict__ g0, const T* __restrict__ g1,
                             const T* __restrict__ g2, const uint32_t* __restrict__ fmask, int nx,
                             long rows, int wrow, T* __restrict__ gu, T* __restrict__ gv,
                             T* __restrict__ gw, T* __restrict__ glz) {
+    // launched in blocks of 256 over n < 2^31 nodes: 256 divides 2^31, so
+    // every thread index, padding included, fits in an int
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= rows * nx) return;
     const int row = q / nx;
