@@ -221,7 +221,10 @@ int ibm_stage_vjp(ibm_ctx* c, const void* u, const void* v, const void* w, doubl
  * changes speed and the summation order of the drag, never the divergence or
  * forcing values.  ibm_sgs_stress then runs on it too (one row per wave), in
  * place of a shape the autotuner chose for it.  ibm_get_tile reports the
- * dense pass's shape (the default comes from the grid size).  Errors:
+ * dense pass's shape.  The default, from the grid size: the longest z march
+ * (at most 64 planes) that still gives 1024 wave-tiles, one row per wave (two
+ * in double while 1024 tiles remain), four waves per block below 2048 tiles.
+ * Errors:
  * IBM_E_ARG for an unsupported shape. */
 int ibm_set_tile(ibm_ctx* c, int vx, int ty, int kz, int wpb);
 int ibm_get_tile(const ibm_ctx* c, int out[4]);

@@ -185,11 +185,24 @@ TileCfg default_tile(const ibm_ctx* c) {
             t.vx = vx;
             break;
         }
-    // measured on the 512x256x256 hill (float32): two rows per wave, 32 planes
-    // per tile, one wave per block
-    t.ty = 2;
-    t.kz = 32;
+    // Enough wave-tiles to fill the GPU (1024 SIMDs) with the longest z march
+    // that allows: a short march re-reads its halo planes, too few waves leave
+    // SIMDs idle.  Float takes one row per wave; double two while that still
+    // leaves 1024 waves (rows j-1 and j+1 are then shared by the wave's rows),
+    // at most two so the tile stays batchable; four waves per block below 2048
+    // waves.  Fitted to tuned tiles of the 512x256x256 hill, the 256x128x128
+    // ridge (float and double) and a 128x64x64 hill (double); ibm_autotune
+    // times the candidates for a grid.
+    constexpr long kFill = 1024;
+    t.ty = 1;
+    t.kz = 64;
     t.wpb = 1;
+    if (ts == 8) {
+        t.ty = 2;
+        if (apply_tiles(c, t) < kFill) t.ty = 1;
+    }
+    while (t.kz > 1 && apply_tiles(c, t) < kFill) t.kz /= 2;
+    if (apply_tiles(c, t) < 2 * kFill) t.wpb = 4;
     return t;
 }
 
