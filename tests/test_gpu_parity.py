@@ -61,6 +61,23 @@ def test_tile_shapes_bitwise_identical(ora):
         compare(out, ref, wl, TOL["f64"])
 
 
+@pytest.mark.parametrize("shape,dtype,tile", [
+    ((512, 256, 256), "f32", (4, 1, 64, 1)), ((512, 256, 256), "f64", (2, 2, 64, 1)),
+    ((256, 128, 128), "f32", (4, 1, 16, 4)), ((256, 128, 128), "f64", (2, 1, 32, 4)),
+    ((128, 64, 64), "f64", (2, 1, 4, 4)), ((64, 32, 32), "f64", (1, 1, 1, 4)),
+    ((8, 4, 1), "f32", (1, 1, 1, 4))])
+def test_default_tile(shape, dtype, tile):
+    """The tile an untuned context takes: the longest z march (at most 64
+    planes) that leaves 1024 wave-tiles, one row per wave (two in double while
+    1024 tiles remain), four waves per block below 2048 tiles."""
+    import torch
+    import paper_2006_03343_amd as ibm
+    _, dev = torch_dev()
+    ctx = ibm.Context(*shape, dtype=torch.float64 if dtype == "f64" else torch.float32,
+                      device=dev)
+    assert ctx.get_tile() == tile
+
+
 @pytest.mark.parametrize("dtype,prec,tile", [
     ("f64", "plain", (2, 4, 16, 4)), ("f64", "plain", (1, 8, 5, 2)),
     ("f32", "plain", (4, 4, 16, 4)), ("f32", "mixed", (4, 2, 9, 4)), ("f32", "mixed", (1, 8, 3, 1)),
