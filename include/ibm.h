@@ -208,7 +208,11 @@ int ibm_apply_sgs(ibm_ctx* c, const void* phi_uv, const void* phi_w, const void*
  * forced velocity, g_drag[3] (host doubles) of the drag.  Outputs gu, gv,
  * gw (overwritten) and glog_z0 (overwritten; NULL allowed, required NULL
  * when log_z0 is NULL).  The first call after a prepare builds the transposed
- * stencil map (synchronous); later calls are asynchronous on ``stream``. */
+ * stencil map (synchronous); later calls are asynchronous on ``stream``.
+ * Errors: IBM_E_STATE before prepare; IBM_E_ARG for a missing or misaligned
+ * field, glog_z0 without log_z0, or 2^28 or more band records (uv and w
+ * together), beyond the map's 32-bit entry offsets; IBM_E_RANGE for z0 outside
+ * (0, phi_c). */
 int ibm_stage_vjp(ibm_ctx* c, const void* u, const void* v, const void* w, double z0,
                   const void* log_z0, const void* const g_tau[6], const void* const g_div[3],
                   const void* const g_ustar[3], const double g_drag[3], void* gu, void* gv,

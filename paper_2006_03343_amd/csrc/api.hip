@@ -432,6 +432,11 @@ int ibm_stage_vjp(ibm_ctx* c, const void* u, const void* v, const void* w, doubl
             return fail(IBM_E_RANGE, "%s: z0 must satisfy 0 < z0 < phi_c (got %g)", fn, z0);
     }
     if (glog_z0 && (rc = check_field(c, glog_z0, fn, "glog_z0"))) return rc;
+    // the transposed stencil map keys a record in 29 bits and offsets its
+    // eight corners per record in 32-bit signed integers
+    const long nrec = c->rec[0].n + c->rec[1].n;
+    if (nrec >= (1L << 28))
+        return fail(IBM_E_ARG, "%s: %ld band records; the adjoint takes fewer than 2^28", fn, nrec);
     DeviceScope dg(c->device);
     return stage_vjp(c, u, v, w, z0, log_z0, g_tau, g_div, g_ustar, g_drag, gu, gv, gw, glog_z0,
                      (hipStream_t)stream);

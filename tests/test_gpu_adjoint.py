@@ -9,7 +9,10 @@ differentiated with respect to u, v, w and a per-node log z0 field.
 * float32 (mixed) adjoint vs float64 central finite differences of J along
   32 seeded random directions (seeds 200603343 + 1000 + d): <= 1e-4 relative
   per direction, on the 256 x 128 x 128 fractal terrain;
-* the autograd wrapper returns the same gradients as the direct call.
+* the autograd wrapper returns the same gradients as the direct call;
+* a context with 2^28 or more band records (a 4096 x 2048 x 32 grid whose
+  nodes are nearly all band nodes) is refused with IBM_E_ARG before anything
+  is built.
 """
 import numpy as np
 import pytest
@@ -206,3 +209,30 @@ def test_vjp_degenerate_grids(ora):
         errs = [normwise(a.cpu().numpy(), b) for a, b in zip((gu, gv, gw), ref[:3])]
         _say(f"normwise errors gu gv gw: {errs}")
         assert max(errs) <= 1e-11, errs
+
+
+def test_vjp_refuses_too_many_band_records():
+    """The transposed stencil map keys a record in 29 bits and offsets its
+    entries (eight per record) in 32-bit signed integers: 2^28 records or more
+    are refused.  A wall at height 0.25 with a band 40 nodes wide on a 32-plane
+    grid makes every uv node and all but the bottom w nodes band nodes:
+    about 5.3e8 records."""
+    import torch
+    import paper_2006_03343_amd as ibm
+    from paper_2006_03343_amd import _lib
+    _, dev = torch_dev()
+    nx, ny, nz = 4096, 2048, 32
+    _say(f"adjoint refused: {nx}x{ny}x{nz} f32, all-band grid")
+    k = torch.arange(nz, dtype=torch.float32, device=dev).view(nz, 1, 1)
+    ctx = ibm.Context(nx, ny, nz, dtype=torch.float32, precision="mixed", device=dev)
+    ctx.prepare((k + 0.25).expand(nz, ny, nx).contiguous(), (k - 0.25).expand(nz, ny, nx).contiguous(),
+                40.0, None, 0.4)
+    nrec = ctx.band_size(0) + ctx.band_size(1)
+    assert nrec >= 2 ** 28
+    f = torch.zeros((nz, ny, nx), dtype=torch.float32, device=dev)
+    with pytest.raises(_lib.IbmError) as e:
+        ctx.vjp(f, f, f, [f] * 3, [f] * 3, [0.0] * 3, z0=1e-3)
+    assert e.value.code == _lib.IBM_E_ARG and "2^28" in str(e.value)
+    _say(f"{nrec} records: {e.value}")
+    del ctx, f
+    torch.cuda.empty_cache()
