@@ -15,7 +15,8 @@ ibm_sgs_stress + ibm_wall_stress + ibm_apply on the GPU (div and ustar bit for b
 also on 4096 x 4096 x 30 float64 and 8192 x 4096 x 30 float32 grids whose planes
 shrink the chunks to 27; a 4096 x 4096 x 127 grid (near the 2^31 - 1 node limit
 of a context) made of periodic copies of a hill cell, each copy equal to the
-first and the first against the oracle; error paths.
+first and the first against the oracle; error paths, among them an x-y plane
+beyond the pass's 32-bit reach.
 """
 from dataclasses import replace
 
@@ -181,6 +182,27 @@ def test_errors():
     with pytest.raises(ibm.IbmError) as e:
         ctx.apply_sgs(phi, phi, f[0], f[1], f[2], f[3:9], [f[9], f[10], f[11]], div, z0=0.0)
     assert e.value.code == _lib.IBM_E_RANGE
+
+
+def test_plane_beyond_reach_refused():
+    """A block addresses its planes with 32-bit byte offsets, so an x-y plane
+    of more than (2^32 - 1) / 5 bytes is refused: 16384 x 16384 in float32
+    (1 GiB per plane) gives IBM_E_ARG, and nothing is launched."""
+    import torch
+    import paper_2006_03343_amd as ibm
+    from paper_2006_03343_amd import _lib
+    _, dev = torch_dev()
+    n = 16384
+    _say(f"sgs+apply {n}x{n}x1 f32: plane beyond the fused pass's reach")
+    ctx = ibm.Context(n, n, 1, dtype=torch.float32, device=dev)
+    phi = torch.full((1, n, n), 3.0, dtype=torch.float32, device=dev)
+    ctx.prepare(phi, phi, 1.5, 1.5, 0.4)
+    f = [torch.zeros_like(phi) for _ in range(15)]
+    with pytest.raises(ibm.IbmError) as e:
+        ctx.apply_sgs(phi, phi, f[0], f[1], f[2], f[3:9], f[9:12], f[12:15], z0=1e-3)
+    assert e.value.code == _lib.IBM_E_ARG and "4 GiB" in str(e.value)
+    del ctx, phi, f
+    torch.cuda.empty_cache()
 
 
 @pytest.mark.parametrize("dtype,nx,ny", [("f64", 4096, 4096), ("f32", 8192, 4096)])
