@@ -9,6 +9,9 @@
   launch): one case of each grid shape against the oracle, every node;
 * replays of the captured hipGraph, with eager work and synchronisations in
   between, each equal the eager result;
+* two cases of 4096 x 4096 x 64 (2^31 nodes together, each a set of periodic
+  copies of a hill cell): each copy equal to the first, the first against the
+  oracle on the cell, counts, drag and statistics 4096 times the cell's;
 * the autotuner writes and re-reads its cache and keeps a valid shape.
 """
 import json
@@ -17,7 +20,7 @@ import os
 import numpy as np
 import pytest
 
-from _gpu import TOL, compare, torch_dev
+from _gpu import TOL, compare, first_copy, tiled, torch_dev
 from workloads import Grid, configs
 
 pytestmark = pytest.mark.gpu
@@ -306,3 +309,63 @@ def test_ensemble_full_size(ora, tmp_path):
                    counts=b.case(i).counts())
         errs = compare(out, ora.stage(wls[i]), wls[i], TOL["f32"])
         _say(f"errors {errs}")
+
+
+def test_batch_beyond_2_31_nodes_in_total(ora):
+    """Two float32 mixed cases of 4096 x 4096 x 64 (1.07e9 nodes each, 2^31 in
+    all): the batched kernels index each case from its own bases.  Each case is
+    64 x 64 periodic copies of a 64 x 64 x 64 hill cell, so every copy's outputs
+    equal the first's bit for bit and the first meets the bar against the
+    oracle's stage on the cell; counts, drag and band statistics are 4096 times
+    the cell's."""
+    import torch
+    import paper_2006_03343_amd as ibm
+    _, dev = torch_dev()
+    if torch.cuda.get_device_properties(dev).total_memory < 230 * 2 ** 30:
+        pytest.skip("needs about 190 GiB of device memory")
+    torch.cuda.empty_cache()
+    cells = [configs.hill(64, 64, 64, H=8.0, L=24.0, x0=32.0, y0=32.0).cast(np.float32),
+             configs.hill(64, 64, 64, H=12.0, L=20.0, x0=28.0, y0=36.0, seed_offset=1).cast(np.float32)]
+    g = cells[0].grid
+    rx = ry = 64
+    reps = rx * ry
+    nx, ny, nz = g.nx * rx, g.ny * ry, g.nz
+    assert 2 * nx * ny * nz >= 2 ** 31
+    _say(f"batch of 2 cases {nx}x{ny}x{nz} f32 mixed, {rx}x{ry} copies of hill cells")
+    big = lambda a: tiled(a, torch.float32, ry, rx)
+    b = ibm.Batch([(nx, ny, nz)] * 2, dtype=torch.float32, precision="mixed", device=dev)
+    b.prepare([big(c.phi_uv) for c in cells], [big(c.phi_w) for c in cells], cells[0].band_width,
+              [c.z0 for c in cells], phi_c=cells[0].phi_c)
+    io = []
+    for i, c in enumerate(cells):
+        u, v, w = big(c.u), big(c.v), big(c.w)
+        d = dict(u=u, v=v, w=w, tau=[big(t) for t in c.tau], gp=[big(t) for t in c.gradp],
+                 ustar=[u.clone(), v.clone(), w.clone()], div=[torch.empty_like(u) for _ in range(3)],
+                 drag=torch.zeros(3, dtype=torch.float64, device=dev),
+                 stats=torch.zeros(4, dtype=torch.float64, device=dev))
+        b.bind(i, u, v, w, d["tau"], d["ustar"], d["div"], gradp=d["gp"], dt=c.dt, drag=d["drag"],
+               stats=d["stats"])
+        io.append(d)
+    b.run()
+    torch.cuda.synchronize()
+    for i, (c, d) in enumerate(zip(cells, io)):
+        out = {k: np.stack([first_copy(f, g.shape, ry, rx) for f in d[k]])
+               for k in ("tau", "div", "ustar")}
+        ref = ora.stage(c)
+        mask = b.case(i).mask().reshape(nz, ry, g.ny, rx, g.nx)
+        for k in range(nz):
+            assert (mask[k] == ref["mask"][k][None, :, None, :]).all(), f"case {i} plane {k}"
+        del mask
+        assert list(b.case(i).counts()) == [reps * int(x) for x in ref["counts"]]
+        out.update(mask=ref["mask"], counts=ref["counts"], drag=None, stats=None)
+        errs = compare(out, ref, c, TOL["f32"])
+        scale = reps * g.dv * np.array([np.abs(x).sum() for x in ref["div"]])
+        errs["drag"] = float(np.max(np.abs(d["drag"].cpu().numpy() - reps * ref["drag"]) / scale))
+        st, s_ref = d["stats"].cpu().numpy(), ref["stats"]
+        errs["stats_sum"] = float(np.abs(st[:2] - reps * s_ref[:2]).max() / (reps * np.abs(s_ref[:2]).max()))
+        errs["stats_max"] = abs(st[2] - s_ref[2]) / s_ref[2]
+        assert st[3] == reps * s_ref[3]
+        _say(f"case {i} errors {errs}")
+        assert max(errs.values()) <= TOL["f32"], errs
+    del b, io
+    torch.cuda.empty_cache()
