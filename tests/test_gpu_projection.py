@@ -16,13 +16,14 @@
 * 2048 x 2048 x 511 in float32 (near the 2^31 - 1 node limit of a context, at
   the longest float transforms), made of periodic copies of a small cell:
   every node of every copy against the oracle's projection of the cell;
-* AB2 against its formula; error paths (lengths beyond the longest transform
+* AB2 against its formula, also on 4096 x 4096 x 127 (near the node limit) as
+  periodic copies of a cell; error paths (lengths beyond the longest transform
   refused).
 """
 import numpy as np
 import pytest
 
-from _gpu import TOL, normwise, tiled, torch_dev
+from _gpu import TOL, first_copy, normwise, tiled, torch_dev
 from workloads import Grid
 
 pytestmark = pytest.mark.gpu
@@ -217,4 +218,36 @@ def test_maximum_size_periodic_copies(ora):
     del out, p
     torch.cuda.empty_cache()
     _say(f"errors u v w p {errs}")
+    assert max(errs) <= TOL["f32"], errs
+
+
+def test_ab2_maximum_size(ora):
+    """AB2 on 4096 x 4096 x 127 in float32 (2.13e9 nodes) as 64 x 64 copies of
+    a 64 x 64 x 127 cell: every copy equal to the first, the first against the
+    oracle's AB2 of the cell within the float32 bar."""
+    import torch
+    import paper_2006_03343_amd as ibm
+    _, dev = torch_dev()
+    if torch.cuda.get_device_properties(dev).total_memory < 150 * 2 ** 30:
+        pytest.skip("needs about 110 GiB of device memory")
+    torch.cuda.empty_cache()
+    cell = Grid(64, 64, 127)
+    rng = np.random.default_rng(9)
+    u, rn, rp = ([rng.standard_normal(cell.shape).astype(np.float32).astype(np.float64)
+                  for _ in range(3)] for _ in range(3))
+    rx = ry = 64
+    nx, ny, nz = cell.nx * rx, cell.ny * ry, cell.nz
+    assert nx * ny * nz <= 2 ** 31 - 1
+    _say(f"ab2 {nx}x{ny}x{nz} f32: {rx}x{ry} copies of a {cell.nx}x{cell.ny}x{nz} cell")
+    big = lambda a: tiled(a, torch.float32, ry, rx)
+    ctx = ibm.Context(nx, ny, nz, dtype=torch.float32, device=dev)
+    out = [torch.empty((nz, ny, nx), dtype=torch.float32, device=dev) for _ in range(3)]
+    ctx.ab2_predict([big(a) for a in u], [big(a) for a in rn], [big(a) for a in rp], 0.03, out)
+    torch.cuda.synchronize()
+    got = [first_copy(o, cell.shape, ry, rx) for o in out]
+    del out, ctx
+    torch.cuda.empty_cache()
+    ref = ora.ab2_predict(u, rn, rp, 0.03)
+    errs = [normwise(a, b) for a, b in zip(got, ref)]
+    _say(f"errors {errs}")
     assert max(errs) <= TOL["f32"], errs
