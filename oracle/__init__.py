@@ -304,51 +304,81 @@ def _wavenumbers(n, length):
     return k
 
 
+def _walls(nz):
+    """Indices of the two wall w nodes: k = 0 on the floor (z = 0) and
+    k = nz - 1 on the lid (z = (nz - 1) dz = Lz by eq. dxdydz)."""
+    return 0, nz - 1
+
+
 def divergence_velocity(g, u, v, w):
-    """Discrete divergence D of a velocity on the staggered grid, on uv nodes:
+    """Discrete divergence D of a velocity on the staggered grid, on the uv
+    layers k = 0 .. nz-2, the cells between the w nodes k and k + 1:
     pseudo-spectral du/dx + dv/dy (eq. dudx) plus (w[k+1] - w[k]) / dz
-    (eq. dwdz), w taken as 0 above the top w node."""
+    (eq. dwdz), with w as given on the wall nodes.  The uv layer nz-1 lies
+    above the lid at z = (nz - 1/2) dz > Lz, outside the domain: its entry is
+    0."""
     u, v, w = (_f64(a, g) for a in (u, v, w))
-    above = np.zeros_like(w)
-    above[:-1] = w[1:]
-    return (spectral_derivative(u, 2, g.nx * g.dx) + spectral_derivative(v, 1, g.ny * g.dy)
-            + (above - w) / g.dz)
+    d = np.zeros(g.shape)
+    if g.nz < 2:
+        return d
+    d[:-1] = (spectral_derivative(u, 2, g.nx * g.dx)[:-1]
+              + spectral_derivative(v, 1, g.ny * g.dy)[:-1]
+              + (w[1:] - w[:-1]) / g.dz)
+    return d
 
 
-def gradient_pressure(g, p):
-    """Discrete gradient G of a pressure on uv nodes: pseudo-spectral d/dx,
-    d/dy on uv nodes; (p[k] - p[k-1]) / dz on the w node k >= 1 and 0 on the
-    bottom w node (no correction there: the lowest w node is a wall node)."""
+def gradient_pressure(g, p, wall_gradient=None):
+    """Discrete gradient G of a pressure on the uv layers: pseudo-spectral
+    d/dx, d/dy on uv nodes (the layer above the lid included, where the
+    caller's p is 0); (p[k] - p[k-1]) / dz on the interior w nodes
+    1 <= k <= nz-2; on the two wall w nodes the wall-normal gradient of
+    eq. p-bc, passed in as (bottom, top) planes (zero when None)."""
     p = _f64(p, g)
     gz = np.zeros_like(p)
-    gz[1:] = (p[1:] - p[:-1]) / g.dz
+    gz[1:-1] = (p[1:-1] - p[:-2]) / g.dz
+    if wall_gradient is not None:
+        kb, kt = _walls(g.nz)
+        gz[kb] = wall_gradient[0]
+        gz[kt] = wall_gradient[1]
     return [spectral_derivative(p, 2, g.nx * g.dx), spectral_derivative(p, 1, g.ny * g.dy), gz]
 
 
 def pressure_poisson(g, ustar, dt):
-    """eqs. p-Poisson, p-Poisson-Fourier: [d2/dz2 - (kx^2 + ky^2)] p_hat =
-    2/(3 dt) (i kx u*_hat + i ky v*_hat + d/dz w*_hat), with d2/dz2 = the
-    vertical part of D G (no flux through the bottom w node or above the top
-    plane: the rows of k = 0 and nz-1 lose their outer neighbour); each
-    horizontal mode is one tridiagonal system in z, solved here by a dense
-    solve; a mode without horizontal wavenumber (kx = ky = 0 once Nyquist
-    modes count as 0: the mean and the Nyquist modes) is singular and takes
-    p_hat = 0 at k = 0 in place of its first row."""
-    rhs = 2.0 / (3.0 * dt) * divergence_velocity(g, *ustar)
-    rh = np.fft.fft2(rhs, axes=(1, 2))                 # [nz][ny][nx] complex
+    """eqs. p-Poisson, p-Poisson-Fourier on the uv layers k = 0 .. nz-2:
+    [d2/dz2 - (kx^2 + ky^2)] p_hat = 2/(3 dt) (i kx u*_hat + i ky v*_hat +
+    d/dz w_hat), where the wall w nodes enter with the value 0 that the
+    projection leaves on them (eqs. bc-bottom-u3 and bc-top), and d2/dz2 is
+    the vertical part of D G: the first and last rows lose their outer
+    neighbour (the wall-normal gradient of eq. p-bc acts on the wall w node
+    alone and does not enter the cells' equations).  Each horizontal mode is
+    one tridiagonal system in z, solved here by a dense solve; a mode
+    without horizontal wavenumber (kx = ky = 0 once Nyquist modes count as
+    0: the mean and the Nyquist modes) is singular and takes p_hat = 0 at
+    k = 0 in place of its first row.  The pressure of the layer above the
+    lid is 0."""
+    p = np.zeros(g.shape)
+    m = g.nz - 1                                       # cells
+    if m < 1:
+        return p
+    wb = np.array(_f64(ustar[2], g), copy=True)
+    kb, kt = _walls(g.nz)
+    wb[kb] = 0.0
+    wb[kt] = 0.0
+    rhs = 2.0 / (3.0 * dt) * divergence_velocity(g, ustar[0], ustar[1], wb)[:m]
+    rh = np.fft.fft2(rhs, axes=(1, 2))                 # [m][ny][nx] complex
     kx = _wavenumbers(g.nx, g.nx * g.dx)
     ky = _wavenumbers(g.ny, g.ny * g.dy)
-    nz, c = g.nz, 1.0 / g.dz ** 2
+    c = 1.0 / g.dz ** 2
     ph = np.zeros_like(rh)
     for j in range(g.ny):
         for i in range(g.nx):
             K2 = kx[i] ** 2 + ky[j] ** 2
-            A = np.zeros((nz, nz))
-            for k in range(nz):
+            A = np.zeros((m, m))
+            for k in range(m):
                 if k > 0:
                     A[k, k - 1] = c
                     A[k, k] -= c
-                if k < nz - 1:
+                if k < m - 1:
                     A[k, k + 1] = c
                     A[k, k] -= c
                 A[k, k] -= K2
@@ -358,14 +388,23 @@ def pressure_poisson(g, ustar, dt):
                 A[0, 0] = 1.0
                 b[0] = 0.0
             ph[:, j, i] = np.linalg.solve(A, b)
-    return np.real(np.fft.ifft2(ph, axes=(1, 2)))
+    p[:m] = np.real(np.fft.ifft2(ph, axes=(1, 2)))
+    return p
 
 
 def pressure_project(g, ustar, dt):
     """eq. u-t+1: u(t + dt) = u* - (3 dt / 2) G p, with p from
-    ``pressure_poisson``.  Returns (u, v, w, p)."""
+    ``pressure_poisson``.  On the wall w nodes G is the wall-normal gradient
+    of eq. p-bc, the vertical momentum balance across the wall: with w = 0 on
+    the wall before and after the step (eqs. bc-bottom-u3, bc-top) the
+    update of eq. u-t+1 there requires dp/dz = 2 w* / (3 dt), where w* holds
+    the step's vertical forcing and stress divergence at the wall.  Returns
+    (u, v, w, p)."""
     p = pressure_poisson(g, ustar, dt)
-    gp = gradient_pressure(g, p)
+    ws = _f64(ustar[2], g)
+    kb, kt = _walls(g.nz)
+    f = 2.0 / (3.0 * dt)
+    gp = gradient_pressure(g, p, (f * ws[kb], f * ws[kt]))
     out = [_f64(a, g) - 1.5 * dt * b for a, b in zip(ustar, gp)]
     return out[0], out[1], out[2], p
 
