@@ -134,20 +134,26 @@ int ibm_apply_spectral(ibm_ctx* c, const void* const tau[6], void* const ustar[3
 
 /* The time advance around the stage (§2.4).  ibm_ab2_predict: eq. u-inter,
  * ustar = u + dt (3/2 rhs_now - 1/2 rhs_prev) per component (ustar may alias
- * u).  ibm_pressure_project: eqs. p-Poisson, p-Poisson-Fourier and u-t+1 --
- * solve D G p = 2/(3 dt) D ustar and return u_out = ustar - (3 dt/2) G p and
- * the pressure p_out (on uv nodes).  D: pseudo-spectral d/dx, d/dy (Nyquist
- * modes without derivative) plus (w[k+1] - w[k]) / dz on uv nodes, w above
- * the top w node taken as 0; G: pseudo-spectral d/dx, d/dy of p on uv nodes
- * and (p[k] - p[k-1]) / dz on w nodes k >= 1, no correction on the bottom w
- * node.  Each horizontal mode is a tridiagonal system in z (Thomas, its
- * recurrences in double for either storage type; the vertical differences of
- * p that correct w are formed there in double and transformed back, not
- * taken from the stored p, whose small-wavenumber part is large and nearly
- * constant in z); a mode
- * without horizontal wavenumber (the mean and the Nyquist modes) is singular
- * and takes p = 0 at k = 0 in place of its first row, so u_out is discretely
- * divergence-free when w is 0 on the bottom plane.  u_out may alias ustar;
+ * u).  ibm_pressure_project: eqs. p-Poisson, p-Poisson-Fourier, u-t+1 and
+ * p-bc.  By eq. dxdydz (dz = Lz / (nz - 1)) the w node 0 is the floor and the
+ * w node nz-1 the lid; the uv layers 0 .. nz-2 are the cells between them and
+ * the uv layer nz-1 lies above the lid.  Solves D G p = 2/(3 dt) D ustar on
+ * the cells and returns u_out = ustar - (3 dt/2) G p and the pressure p_out
+ * (on uv nodes).  D: pseudo-spectral d/dx, d/dy (Nyquist modes without
+ * derivative) plus (w[k+1] - w[k]) / dz with the wall w taken as 0; G:
+ * pseudo-spectral d/dx, d/dy of p on uv nodes and (p[k] - p[k-1]) / dz on the
+ * interior w nodes.  On the two wall w nodes the correction is eq. p-bc's
+ * wall-normal gradient 2 w* / (3 dt), so w_out = 0 there (eqs. bc-bottom-u3,
+ * bc-top) whatever ustar holds; it does not enter the cells' equations.
+ * Each horizontal mode is a tridiagonal system over the nz - 1 cells (Thomas,
+ * its recurrences in double for either storage type; the vertical
+ * differences of p that correct w are formed there in double and
+ * transformed back, not taken from the stored p, whose small-wavenumber part
+ * is large and nearly constant in z); a mode without horizontal wavenumber
+ * (the mean and the Nyquist modes) is singular and takes p = 0 at k = 0 in
+ * place of its first row, so u_out is discretely divergence-free in every
+ * cell.  The layer above the lid gets p_out = 0 and keeps ustar's u, v.
+ * u_out may alias ustar;
  * p_out may alias neither.  nx, ny: powers of two as for
  * ibm_apply_spectral, else IBM_E_UNSUPPORTED.  The first call allocates a
  * workspace of 3 half-spectrum complex volumes of the storage type

@@ -4,18 +4,24 @@
 //
 // ibm_ab2_predict: u* = u + dt (3/2 RHS'^t - 1/2 RHS^(t - dt)), elementwise.
 //
-// ibm_pressure_project: with D the discrete divergence of the spectral mode
-// (pseudo-spectral d/dx, d/dy on uv nodes, (w[k+1] - w[k]) / dz with w above
-// the top node taken as 0) and G the discrete gradient (pseudo-spectral on uv
-// nodes, (p[k] - p[k-1]) / dz on w nodes k >= 1, none on the bottom w node),
-// solve D G p = 2 / (3 dt) D u* and set u = u* - (3 dt / 2) G p.  In Fourier
-// space along x and y each horizontal mode is one tridiagonal system in z:
+// ibm_pressure_project: by eq. dxdydz (dz = Lz / (nz - 1)) the w node 0 lies
+// on the floor and the w node nz-1 on the lid; the uv layers 0 .. nz-2 are
+// the cells between them and the uv layer nz-1 lies above the lid.  With D
+// the discrete divergence of the spectral mode on the cells (pseudo-spectral
+// d/dx, d/dy, (w[k+1] - w[k]) / dz) and G the discrete gradient
+// (pseudo-spectral on uv nodes, (p[k] - p[k-1]) / dz on the interior w
+// nodes), solve D G p = 2 / (3 dt) D u* with the wall w taken as 0 and set
+// u = u* - (3 dt / 2) G p.  On the two wall w nodes the correction is the
+// wall-normal gradient of eq. p-bc, 2 w* / (3 dt), which leaves w = 0 there
+// (eqs. bc-bottom-u3, bc-top) and does not enter the cells' equations, so the
+// wall nodes are written as 0.  In Fourier space along x and y each
+// horizontal mode is one tridiagonal system over the nz - 1 cells:
 //   p[k-1] / dz^2 - (K^2 + (number of neighbours) / dz^2) p[k] + p[k+1] / dz^2
 //       = 2 / (3 dt) (i kx u_hat + i ky v_hat + (w_hat[k+1] - w_hat[k]) / dz),
 // K^2 = kx^2 + ky^2 with Nyquist wavenumbers taken as 0; a mode with K = 0 is
-// singular and takes p_hat = 0 at k = 0 in place of its first row.  The
-// projected field is then discretely divergence-free wherever the singular
-// modes are solvable (e.g. w = 0 on the bottom plane).
+// singular and takes p_hat = 0 at k = 0 in place of its first row (its
+// right-hand sides sum to 0 with both walls at 0, so the system is
+// consistent).  The layer above the lid gets p = 0 and keeps u*, v*.
 //
 // Real fields have Hermitian spectra along x, so only the modes 0 .. nx/2 are
 // kept (rows padded to an even length).  Launches: k_rows_fwd -- forward x
@@ -127,8 +133,8 @@ __global__ void __launch_bounds__(256) k_rows_fwd(ProjArgs<T> a) {
 // A_{n-e} above nx / 2; the imaginary parts of modes 0 and nx / 2 are
 // dropped, as a real inverse does) and inverts it.  blockIdx.y = 0: p from
 // P; 1: u = u* - (3 dt / 2) d/dx p from i kx P; 2: v = v* - (3 dt / 2)
-// d/dy p from DY; 3: w = w* - (3 dt / 2) (p[k] - p[k-1]) / dz from DZ (zero
-// on the bottom plane, which keeps w*).  One transform per team keeps the registers, and with them
+// d/dy p from DY; 3: w = w* - (3 dt / 2) (p[k] - p[k-1]) / dz from DZ, and
+// w = 0 on the two wall planes.  One transform per team keeps the registers, and with them
 // the waves per SIMD, of the forward x pass (two per team measured slower
 // despite reading P once).
 template <typename T>
@@ -177,13 +183,17 @@ __global__ void __launch_bounds__(256) k_rows_inv(ProjArgs<T> a) {
     const T* base = kind == 1 ? a.ub : kind == 2 ? a.vb : a.wb;
     T* out = kind == 0 ? a.po : kind == 1 ? a.uo : kind == 2 ? a.vo : a.wo;
     const T s = kind == 0 ? T(1) / T(n) : kind < 3 ? -a.c / T(n) : -a.c / (T(n) * a.dzs);
+    // rows are (k, j) pairs, k = r / ny: the w nodes on the floor and the lid are walls
+    const long lid = (long)(a.nz - 1) * a.ny;
+    const bool wall0 = kind == 3 && (r0 < a.ny || r0 >= lid);
+    const bool wall1 = kind == 3 && (r0 + 1 < a.ny || r0 + 1 >= lid);
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
         if (u >= ns) continue;
         const long o = r0 * n + tm.elem(u);
         const T va = v[0][u].re * s, vb = v[0][u].im * s;
-        if (in0) out[o] = kind ? base[o] + va : va;
-        if (in1) out[o + n] = kind ? base[o + n] + vb : vb;
+        if (in0) out[o] = wall0 ? T(0) : kind ? base[o] + va : va;
+        if (in1) out[o + n] = wall1 ? T(0) : kind ? base[o + n] + vb : vb;
     }
 }
 
@@ -350,14 +360,16 @@ __global__ void __launch_bounds__(256) k_cols_inv(ProjArgs<T> a) {
 }
 
 // Two threads per horizontal mode (i, j): the right-hand side and the
-// tridiagonal system in z, eliminated from both ends at once, leaving p_hat
-// in H's place.  Thread "top" runs Thomas forward elimination over rows 0 ..
-// h-1 (h = nz / 2), leaving p_k = d'_k - c'_k p_{k+1}; thread "bottom"
-// eliminates rows nz-1 .. h+1 upward, leaving p_k = d''_k - a''_k p_{k-1},
-// and forms row h's right-hand side.  Through LDS each gets the other's last
-// coefficients and both solve row h with the same expression, then
-// substitute back over their own rows.  A mode's chain is thus half as long
-// and twice as many threads hide the memory latency.
+// tridiagonal system over the m = nz - 1 cells, eliminated from both ends at
+// once, leaving p_hat in H's place.  Thread "top" runs Thomas forward
+// elimination over rows 0 .. h-1 (h = m / 2), leaving p_k = d'_k - c'_k
+// p_{k+1}; thread "bottom" eliminates rows m-1 .. h+1 upward, leaving p_k =
+// d''_k - a''_k p_{k-1}, and forms row h's right-hand side.  Through LDS each
+// gets the other's last coefficients and both solve row h with the same
+// expression, then substitute back over their own rows.  A mode's chain is
+// thus half as long and twice as many threads hide the memory latency.  The
+// wall w values (levels 0 and nz-1) enter as 0; the level above the lid gets
+// p_hat = 0.
 //
 // The recurrences run in double whatever the storage type: a K = 0 system is
 // a Neumann chain pinned at one end whose condition number grows as nz^2, and
@@ -386,32 +398,40 @@ __global__ void __launch_bounds__(256) k_solve(ProjArgs<T> a) {
     const double K2 = kx * kx + ky * ky;
     const double e = 1.0 / (a.dz * a.dz);
     const double invdz = 1.0 / a.dz;
-    const int nz = a.nz, h = nz / 2;
+    const int m = a.nz - 1, h = m / 2;                       // cells; the meeting row
     const bool pin = K2 == 0.0;
     const long hp = a.hplane;
     const Cx<T> zero{T(0), T(0)};
+    if (m < 1) {                                             // nz = 1: no cell
+        if (act && !top) {
+            H[mode] = zero;
+            W[mode] = zero;
+        }
+        return;
+    }
     // 2 / (3 dt) (H + (w[k+1] - w[k]) / dz)
     auto rhs = [&](Cx<T> hh, Cx<T> w, Cx<T> wu) {
         return Cx<double>{a.f * ((double)hh.re + ((double)wu.re - (double)w.re) * invdz),
                           a.f * ((double)hh.im + ((double)wu.im - (double)w.im) * invdz)};
     };
     if (top) {
-        // rows 0 .. h-1, the next level's loads issued before this level's work
+        // rows 0 .. h-1, the next level's loads issued before this level's work;
+        // the floor's w (level 0) is 0 and level h + 1 <= m - 1 is below the lid
         double cT = 0.0;
         Cx<double> dT{0.0, 0.0};
         if (act && h > 0) {
-            Cx<T> hn = H[mode], wn = W[mode], wun = W[hp + mode];
+            Cx<T> hn = H[mode], wn = zero, wun = W[hp + mode];
             for (int k = 0; k < h; ++k) {
                 const long q = (long)k * hp + mode;
                 const Cx<T> hh = hn, w = wn, wu = wun;
                 if (k + 1 < h) {
                     hn = H[q + hp];
                     wn = wu;
-                    wun = W[q + 2 * hp];                    // k + 2 <= h < nz
+                    wun = W[q + 2 * hp];                    // k + 2 <= h < m
                 }
                 Cx<double> r = rhs(hh, w, wu);
                 const double lo = k > 0 ? e : 0.0;
-                double up = e, b = -K2 - lo - e;            // k + 1 <= h < nz
+                double up = e, b = -K2 - lo - e;            // k + 1 <= h < m
                 if (pin && k == 0) {
                     b = 1.0;
                     up = 0.0;
@@ -428,20 +448,21 @@ __global__ void __launch_bounds__(256) k_solve(ProjArgs<T> a) {
         xs[1][lane] = dT.re;
         xs[2][lane] = dT.im;
     } else {
-        // rows nz-1 .. h+1 going up, then row h's right-hand side
+        // rows m-1 .. h+1 going up (the lid's w above row m-1 is 0), then row
+        // h's right-hand side
         double aB = 0.0;
         Cx<double> dB{0.0, 0.0}, rh{0.0, 0.0};
         if (act) {
             Cx<T> wu = zero;                                 // original w one level up
-            const long qt = (long)(nz - 1) * hp + mode;
-            Cx<T> hn = H[qt], wn = W[qt];
-            for (int k = nz - 1; k > h; --k) {
+            const long qt = (long)(m - 1) * hp + mode;
+            Cx<T> hn = H[qt], wn = m - 1 > 0 ? W[qt] : zero;
+            for (int k = m - 1; k > h; --k) {
                 const long q = (long)k * hp + mode;
                 const Cx<T> hh = hn, w = wn;
                 hn = H[q - hp];                              // k - 1 >= h
-                wn = W[q - hp];
+                wn = k - 1 > 0 ? W[q - hp] : zero;           // the floor's w is 0
                 const Cx<double> r = rhs(hh, w, wu);
-                const double up = k + 1 < nz ? e : 0.0;
+                const double up = k + 1 < m ? e : 0.0;
                 const double b = -K2 - e - up;               // k >= 1
                 const double rm = 1.0 / (b - up * aB);
                 aB = e * rm;
@@ -466,7 +487,7 @@ __global__ void __launch_bounds__(256) k_solve(ProjArgs<T> a) {
     const Cx<double> dT{xs[1][lane], xs[2][lane]}, dB{xs[4][lane], xs[5][lane]};
     Cx<double> r{xs[6][lane], xs[7][lane]};
     const double lo = h > 0 ? e : 0.0;
-    double up = h + 1 < nz ? e : 0.0, b = -K2 - lo - up;
+    double up = h + 1 < m ? e : 0.0, b = -K2 - lo - up;
     if (pin && h == 0) {
         b = 1.0;
         up = 0.0;
@@ -483,7 +504,8 @@ __global__ void __launch_bounds__(256) k_solve(ProjArgs<T> a) {
     // vertical difference p_hat[k] - p_hat[k-1] of the w correction, formed
     // here in double (into W, whose d' it has read): the small-K modes carry a
     // large part nearly constant in z that a difference of stored float
-    // pressures would cancel badly.  W at level 0 (no correction there) is 0.
+    // pressures would cancel badly.  W on the wall levels 0 and nz-1 is 0 (the
+    // inverse x pass writes w = 0 there), as are p_hat and W above the lid.
     auto diff = [&](long q, const Cx<double>& hi, const Cx<double>& lo_) {
         W[q] = Cx<T>{(T)(hi.re - lo_.re), (T)(hi.im - lo_.im)};
     };
@@ -504,17 +526,20 @@ __global__ void __launch_bounds__(256) k_solve(ProjArgs<T> a) {
         }
         W[mode] = zero;                                      // level 0
     } else {
-        if (h + 1 < nz) coef((long)(h + 1) * hp + mode, dn, cn);
-        for (int k = h + 1; k < nz; ++k) {
+        if (h + 1 < m) coef((long)(h + 1) * hp + mode, dn, cn);
+        for (int k = h + 1; k < m; ++k) {
             const long q = (long)k * hp + mode;
             const Cx<double> d = dn;
             const double c = cn;
-            if (k + 1 < nz) coef(q + hp, dn, cn);
+            if (k + 1 < m) coef(q + hp, dn, cn);
             const Cx<double> pk{d.re - c * p.re, d.im - c * p.im};
             H[q] = Cx<T>{(T)pk.re, (T)pk.im};
             diff(q, pk, p);                                  // level k > h
             p = pk;
         }
+        const long ql = (long)m * hp + mode;                 // level nz-1: lid / above it
+        H[ql] = zero;
+        W[ql] = zero;
     }
 }
 

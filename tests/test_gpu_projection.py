@@ -5,8 +5,10 @@
   x and along y of each type (2048 points in float, 1024 in double): u, v, w
   after the projection and the pressure, normwise per field <= 1e-12
   (float64) and 2e-5 (float32);
-* with w = 0 on the bottom plane the projected field is discretely
-  divergence-free (the oracle's D applied to the GPU's output);
+* the projected field is discretely divergence-free in every cell (the
+  oracle's D applied to the GPU's output) and w is exactly 0 on the floor's
+  and the lid's w nodes, also where w* is not 0 there; with w* = 0 on both
+  walls of an 8 x 8 x 9 grid the lid's w stays 0;
 * output in place of the input;
 * the 512 x 256 x 256 hill in float32: the divergence of the projected
   field, and the pressure's spectrum at sampled horizontal modes against
@@ -33,11 +35,12 @@ def _say(msg):
     print(msg, flush=True)
 
 
-def _fields(g, seed, wall=True):
+def _fields(g, seed, wall=False):
     rng = np.random.default_rng(seed)
     u, v, w = rng.standard_normal((3,) + g.shape)
     if wall:
         w[0] = 0.0
+        w[-1] = 0.0
     return [u, v, w]
 
 
@@ -91,7 +94,25 @@ def test_divergence_free_and_in_place(ora, dtype, bar):
     d1 = np.abs(ora.divergence_velocity(g, *out)).max()
     _say(f"max |D u| before {d0:.3e}, after {d1:.3e}")
     assert d1 <= bar * d0
-    np.testing.assert_array_equal(out[2][0], vel[2][0])     # no correction on the bottom w node
+    # the floor's and the lid's w nodes are walls (eqs. bc-bottom-u3, bc-top)
+    assert np.abs(out[2][0]).max() == 0.0 and np.abs(out[2][-1]).max() == 0.0
+    assert np.abs(vel[2][0]).max() > 0.0 and np.abs(vel[2][-1]).max() > 0.0
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_lid_stays_zero(ora, dtype):
+    g = Grid(8, 8, 9)
+    vel = _fields(g, 13, wall=True)
+    if dtype == "f32":
+        vel = [a.astype(np.float32).astype(np.float64) for a in vel]
+    _say(f"projection 8x8x9 {dtype}: w = 0 on both walls")
+    out, p = _project(g, vel, 0.01, dtype)
+    assert np.abs(out[2][-1]).max() == 0.0 and np.abs(out[2][0]).max() == 0.0
+    ru, rv, rw, rp = ora.pressure_project(g, vel, 0.01)
+    assert np.abs(rw[-1]).max() == 0.0
+    errs = [normwise(a, b) for a, b in zip(out + [p], [ru, rv, rw, rp])]
+    _say(f"errors u v w p {errs}")
+    assert max(errs) <= TOL[dtype], errs
 
 
 def test_hill_size_sampled_modes(ora):
@@ -104,10 +125,16 @@ def test_hill_size_sampled_modes(ora):
     d1 = np.abs(ora.divergence_velocity(g, *out)).max()
     _say(f"max |D u| before {d0:.3e}, after {d1:.3e}")
     assert d1 <= 2e-5 * d0
-    # pressure spectrum at sampled modes vs dense solves of their systems
-    rhs = 2.0 / (3.0 * dt) * ora.divergence_velocity(g, *vel)
+    # pressure spectrum at sampled modes vs dense solves of their systems over
+    # the nz - 1 cells, the wall w taken as 0 in the right-hand side
+    m = g.nz - 1
+    wb = vel[2].copy()
+    wb[0] = 0.0
+    wb[-1] = 0.0
+    rhs = 2.0 / (3.0 * dt) * ora.divergence_velocity(g, vel[0], vel[1], wb)[:m]
     rh = np.fft.fft2(rhs, axes=(1, 2))
-    ph = np.fft.fft2(p, axes=(1, 2))
+    ph = np.fft.fft2(p[:m], axes=(1, 2))
+    assert np.abs(p[m]).max() == 0.0                          # above the lid
     kx = 2 * np.pi * np.fft.fftfreq(g.nx, d=1.0 / g.nx) / g.lx
     ky = 2 * np.pi * np.fft.fftfreq(g.ny, d=1.0 / g.ny) / g.ly
     kx[g.nx // 2] = 0.0
@@ -119,7 +146,7 @@ def test_hill_size_sampled_modes(ora):
     num = den = 0.0
     for i, j in modes:
         K2 = kx[i] ** 2 + ky[j] ** 2
-        A = np.diag(np.full(g.nz - 1, c), 1) + np.diag(np.full(g.nz - 1, c), -1)
+        A = np.diag(np.full(m - 1, c), 1) + np.diag(np.full(m - 1, c), -1)
         A -= np.diag(A.sum(axis=1) + K2)
         b = rh[:, j, i].copy()
         if K2 == 0.0:
