@@ -8,6 +8,9 @@
 * Rotation covariance: tau(R plane, R U0) = R tau(plane, U0) R^T.
 * Discrete x<->y swap and x reflection permute every output.
 * Symmetry and zero trace of the rotated tensor; U_r = 0 gives zero stress.
+* Band statistics (sums of tau_w per node set, max |U_r| over all records,
+  record count) in closed form with the two node sets' bands on flat walls
+  at different heights.
 """
 import numpy as np
 import pytest
@@ -249,3 +252,35 @@ def test_per_node_log_z0_matches_scalar(ora):
                             np.full(g.shape, np.log(z0)), wl.tau)
     for c in range(6):
         np.testing.assert_allclose(a[c], b[c], rtol=1e-13, atol=1e-16)
+
+
+@pytest.mark.parametrize("za,zb,a,c", [(1.0, 3.25, -2.0, 1.5), (3.25, 1.0, -2.0, 1.5),
+                                       (1.5, 2.75, -10.0, 1.0), (2.75, 1.5, 0.5, 2.0)])
+def test_band_statistics_two_walls(ora, za, zb, a, c):
+    """All four band statistics in closed form, with the uv band and the w
+    band drawn from flat walls at different heights (the caller supplies phi
+    on each node set): every uv record samples z_a + phi_c and every w record
+    z_b + phi_c, where the velocity (a + c z)(cos t, sin t, .) is linear in z,
+    so |U_r| is |a + c (z + phi_c)| per set.  stats = [sum of tau_w over uv
+    records, the same over w records, max |U_r| over all records, record
+    count]: a maximum over one set only, or without the other set's value,
+    fails one of the four cases."""
+    g = Grid(6, 5, 12)
+    b, phi_c, z0, theta = 1.5, 1.5, 1e-3, 0.6
+    pu = terrain.flat(g, za)[0]
+    pw = terrain.flat(g, zb)[1]
+    zuv = (np.arange(g.nz) + 0.5)[:, None, None] * np.ones(g.shape)
+    prof = a + c * zuv
+    u, v = prof * np.cos(theta), prof * np.sin(theta)
+    w = np.random.default_rng(3).standard_normal(g.shape)       # removed by n = e_z
+    tau, stats = ora.wall_stress(g, b, phi_c, KAPPA, pu, pw, u, v, w, z0, None,
+                                 [np.zeros(g.shape)] * 6)
+    Ua, Ub = abs(a + c * (za + phi_c)), abs(a + c * (zb + phi_c))
+    tw = lambda U: -(KAPPA * U / _ln(phi_c, z0)) ** 2
+    nuv = int(((pu >= 0) & (pu <= b)).sum())
+    nw = int((np.abs(pw) <= b / 2).sum())
+    assert nuv > 0 and nw > 0
+    np.testing.assert_allclose(stats[0], nuv * tw(Ua), rtol=1e-12)
+    np.testing.assert_allclose(stats[1], nw * tw(Ub), rtol=1e-12)
+    np.testing.assert_allclose(stats[2], max(Ua, Ub), rtol=1e-13)
+    assert stats[3] == nuv + nw
