@@ -9,7 +9,9 @@ Every function follows §3 of Liu & Stevens (arXiv 2006.03343):
 classes (§3.3 lists), normals (§3.1), the wall model (§3.3,
 eq. bc-bottom-immersed and the tensor rotation), the stress divergence
 (§2.4, eqs. dudx/dudz/dwdz) and the direct forcing (§3.2, eq. u-*-IBM);
-and the Smagorinsky stress with Mason's damping that feeds it (§2.2).
+and the Smagorinsky stress with Mason's damping that feeds it (§2.2);
+the AB2 update and the pressure projection around the stage (§2.4); and
+Chester et al.'s original method that the paper simplifies (§1, §3.3).
 """
 import ctypes
 import os
@@ -61,6 +63,11 @@ def lib():
                                     vp, vp, vp, vp]
         L.ora_smagorinsky.argtypes = [vp, c_double, c_double, vp, vp, vp, vp, vp, c_double, vp,
                                       vp]
+        L.ora_chester_class.argtypes = [c_double, c_double]
+        L.ora_chester_counts.argtypes = [vp, vp, vp, vp, vp]
+        L.ora_chester_wall_stress.argtypes = [vp, vp, vp, vp, vp, vp, vp, c_double, vp, vp, vp]
+        L.ora_chester_extrapolate.argtypes = [vp, vp, vp, vp, vp]
+        L.ora_chester_sor.argtypes = [vp, vp, vp, vp, c_double, c_int, vp]
         L.ora_num_threads.restype = c_int
         L.ora_set_threads.argtypes = [c_int]
         _lib = L
@@ -407,6 +414,72 @@ def pressure_project(g, ustar, dt):
     gp = gradient_pressure(g, p, (f * ws[kb], f * ws[kt]))
     out = [_f64(a, g) - 1.5 * dt * b for a, b in zip(ustar, gp)]
     return out[0], out[1], out[2], p
+
+
+# ------------------------------------------ §1: Chester et al.'s original
+CH_FLUID, CH_BAND, CH_SOLID_BAND, CH_INTERIOR = 0, 1, 2, 3
+
+
+def chester_class(phi, band_width):
+    return lib().ora_chester_class(float(phi), float(band_width))
+
+
+def chester_counts(g, band_width, phi_uv, phi_w):
+    """[uv fluid, uv fluid band, uv solid band, uv interior, w ... the same]."""
+    pu, pw = _f64(phi_uv, g), _f64(phi_w, g)
+    out = np.zeros(8, dtype=np.int64)
+    gr, pr = _grid(g), _params(band_width, band_width)
+    lib().ora_chester_counts(ctypes.byref(gr), ctypes.byref(pr), _p(pu), _p(pw), _p(out))
+    return out
+
+
+def chester_wall_stress(g, band_width, phi_c, kappa, phi_uv, phi_w, u, v, w, z0, log_z0, tau):
+    """Step 1 (near-wall model in the fluid band, zero for phi < 0): returns
+    (tau list of 6 arrays, stats[4]); inputs are not modified."""
+    pu, pw, uu, vv, ww = (_f64(a, g) for a in (phi_uv, phi_w, u, v, w))
+    lz = None if log_z0 is None else _f64(log_z0, g)
+    t = [np.array(_f64(a, g), copy=True) for a in tau]
+    stats = np.zeros(4)
+    gr, pr = _grid(g), _params(band_width, phi_c, kappa)
+    lib().ora_chester_wall_stress(ctypes.byref(gr), ctypes.byref(pr), _p(pu), _p(pw), _p(uu),
+                                  _p(vv), _p(ww), float(z0), _p(lz), _parr(t), _p(stats))
+    return t, stats
+
+
+def chester_extrapolate(g, band_width, phi_c, phi_uv, phi_w, tau):
+    """Step 2 (linear extrapolation into the solid band): a new list of 6 arrays."""
+    pu, pw = _f64(phi_uv, g), _f64(phi_w, g)
+    t = [np.array(_f64(a, g), copy=True) for a in tau]
+    gr, pr = _grid(g), _params(band_width, phi_c)
+    lib().ora_chester_extrapolate(ctypes.byref(gr), ctypes.byref(pr), _p(pu), _p(pw), _parr(t))
+    return t
+
+
+def chester_sor(g, band_width, phi_uv, phi_w, omega, iterations, tau):
+    """Step 3 (red-black SOR of the Laplace equation over the interior): a new
+    list of 6 arrays."""
+    pu, pw = _f64(phi_uv, g), _f64(phi_w, g)
+    t = [np.array(_f64(a, g), copy=True) for a in tau]
+    gr, pr = _grid(g), _params(band_width, band_width)
+    lib().ora_chester_sor(ctypes.byref(gr), ctypes.byref(pr), _p(pu), _p(pw), float(omega),
+                          int(iterations), _parr(t))
+    return t
+
+
+def chester_stage(wl, omega, iterations, ustar=None):
+    """One pass of the original method on a ``workloads.configs.Workload``:
+    the three steps, then the divergence, forcing and drag of ``stage``."""
+    g = wl.grid
+    tau, stats = chester_wall_stress(g, wl.band_width, wl.phi_c, wl.kappa, wl.phi_uv, wl.phi_w,
+                                     wl.u, wl.v, wl.w, wl.z0, wl.log_z0, wl.tau)
+    tau = chester_extrapolate(g, wl.band_width, wl.phi_c, wl.phi_uv, wl.phi_w, tau)
+    tau = chester_sor(g, wl.band_width, wl.phi_uv, wl.phi_w, omega, iterations, tau)
+    div = divergence(g, tau)
+    us = forcing(g, wl.phi_uv, wl.phi_w, ustar if ustar is not None else (wl.u, wl.v, wl.w),
+                 wl.gradp, wl.dt)
+    dr = drag(g, wl.phi_uv, wl.phi_w, div)
+    return dict(counts=chester_counts(g, wl.band_width, wl.phi_uv, wl.phi_w), tau=tau,
+                stats=stats, div=div, ustar=us, drag=dr)
 
 
 def stage_vjp(wl, g_tau, g_div, g_ustar, g_drag):

@@ -540,3 +540,174 @@ void ora_smagorinsky(const ora_grid* g, double cs, double kappa, const double* p
                 tau[5][q] = -2.0 * nu_w * wk[1];
             }
 }
+
+/* ------------------------------------------- §1: Chester et al.'s original */
+/* The method the paper simplifies, in its three named steps (§1, §3.3's
+ * closing paragraphs), with both node sets classified alike. */
+int ora_chester_class(double phi, double band_width) {
+    if (phi > band_width) return ORA_CH_FLUID;
+    if (phi >= 0.0) return ORA_CH_BAND;
+    if (phi >= -band_width) return ORA_CH_SOLID_BAND;
+    return ORA_CH_INTERIOR;
+}
+
+void ora_chester_counts(const ora_grid* g, const ora_params* p, const double* phi_uv,
+                        const double* phi_w, int64_t counts[8]) {
+    long n = (long)g->nx * g->ny * g->nz;
+    for (int c = 0; c < 8; ++c) counts[c] = 0;
+    for (long q = 0; q < n; ++q) {
+        counts[ora_chester_class(phi_uv[q], p->band_width)] += 1;
+        counts[4 + ora_chester_class(phi_w[q], p->band_width)] += 1;
+    }
+}
+
+/* Step 1: the near-wall model in the fluid band, zero inside the body. */
+void ora_chester_wall_stress(const ora_grid* g, const ora_params* p, const double* phi_uv,
+                             const double* phi_w, const double* u, const double* v,
+                             const double* w, double z0, const double* log_z0,
+                             double* const tau[6], double stats[4]) {
+    long nz = g->nz;
+    double* part = (double*)calloc((size_t)nz * 4, sizeof(double));
+#pragma omp parallel for schedule(dynamic)
+    for (long k = 0; k < nz; ++k) {
+        double s_uv = 0.0, s_w = 0.0, umax = 0.0, cnt = 0.0;
+        for (long j = 0; j < g->ny; ++j)
+            for (long i = 0; i < g->nx; ++i) {
+                long q = lin(g, i, j, k);
+                double t[9], tw, U;
+                int cu = ora_chester_class(phi_uv[q], p->band_width);
+                if (cu == ORA_CH_BAND) {
+                    ora_local_stress(g, p, phi_uv, ORA_UV, i, j, k, u, v, w,
+                                     ln_ratio_at(p, z0, log_z0, q), t, &tw, &U);
+                    tau[0][q] = t[0];
+                    tau[1][q] = t[4];
+                    tau[2][q] = t[8];
+                    tau[3][q] = t[1];
+                    s_uv += tw;
+                    if (U > umax) umax = U;
+                    cnt += 1.0;
+                } else if (cu != ORA_CH_FLUID) {
+                    tau[0][q] = 0.0; tau[1][q] = 0.0; tau[2][q] = 0.0; tau[3][q] = 0.0;
+                }
+                int cw = ora_chester_class(phi_w[q], p->band_width);
+                if (cw == ORA_CH_BAND) {
+                    ora_local_stress(g, p, phi_w, ORA_W, i, j, k, u, v, w,
+                                     ln_ratio_at(p, z0, log_z0, q), t, &tw, &U);
+                    tau[4][q] = t[2];
+                    tau[5][q] = t[5];
+                    s_w += tw;
+                    if (U > umax) umax = U;
+                    cnt += 1.0;
+                } else if (cw != ORA_CH_FLUID) {
+                    tau[4][q] = 0.0; tau[5][q] = 0.0;
+                }
+            }
+        part[4 * k + 0] = s_uv;
+        part[4 * k + 1] = s_w;
+        part[4 * k + 2] = umax;
+        part[4 * k + 3] = cnt;
+    }
+    if (stats) {
+        stats[0] = stats[1] = stats[2] = stats[3] = 0.0;
+        for (long k = 0; k < nz; ++k) {
+            stats[0] += part[4 * k + 0];
+            stats[1] += part[4 * k + 1];
+            if (part[4 * k + 2] > stats[2]) stats[2] = part[4 * k + 2];
+            stats[3] += part[4 * k + 3];
+        }
+    }
+    free(part);
+}
+
+/* Step 2 on the components ``f[0..nc-1]`` of one node set: every solid-band
+ * node x takes the straight line, in the distance from the surface, through
+ * the two samples of its own components at x + (phi_c - phi) n and
+ * x + (2 phi_c - phi) n.  All values are computed from the field as it
+ * stands, then written. */
+static void chester_extrapolate_set(const ora_grid* g, const ora_params* p, const double* phi,
+                                    int kind, double* const* f, int nc) {
+    long n = (long)g->nx * g->ny * g->nz;
+    long m = 0;
+    for (long q = 0; q < n; ++q)
+        if (ora_chester_class(phi[q], p->band_width) == ORA_CH_SOLID_BAND) ++m;
+    long* idx = (long*)malloc(sizeof(long) * (size_t)(m > 0 ? m : 1));
+    double* val = (double*)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1) * nc);
+    m = 0;
+    for (long q = 0; q < n; ++q)
+        if (ora_chester_class(phi[q], p->band_width) == ORA_CH_SOLID_BAND) idx[m++] = q;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (long r = 0; r < m; ++r) {
+        long q = idx[r];
+        long i = q % g->nx, j = (q / g->nx) % g->ny, k = q / ((long)g->nx * g->ny);
+        double x[3], nrm[3], p1[3], p2[3];
+        node_position(g, kind, i, j, k, x);
+        ora_normal(g, phi, i, j, k, nrm);
+        double d1 = p->phi_c, d2 = 2.0 * p->phi_c;
+        for (int d = 0; d < 3; ++d) {
+            p1[d] = x[d] + (d1 - phi[q]) * nrm[d];
+            p2[d] = x[d] + (d2 - phi[q]) * nrm[d];
+        }
+        for (int c = 0; c < nc; ++c) {
+            double t1 = ora_interp(g, f[c], kind, p1);
+            double t2 = ora_interp(g, f[c], kind, p2);
+            val[r * nc + c] = t1 + (phi[q] - d1) * (t2 - t1) / (d2 - d1);
+        }
+    }
+    for (long r = 0; r < m; ++r)
+        for (int c = 0; c < nc; ++c) f[c][idx[r]] = val[r * nc + c];
+    free(idx);
+    free(val);
+}
+
+void ora_chester_extrapolate(const ora_grid* g, const ora_params* p, const double* phi_uv,
+                             const double* phi_w, double* const tau[6]) {
+    double* const uvf[4] = {tau[0], tau[1], tau[2], tau[3]};
+    double* const wf[2] = {tau[4], tau[5]};
+    chester_extrapolate_set(g, p, phi_uv, ORA_UV, uvf, 4);
+    chester_extrapolate_set(g, p, phi_w, ORA_W, wf, 2);
+}
+
+/* Step 3 on one node set: ``iterations`` red-black SOR sweeps of the 7-point
+ * Laplace equation over the interior nodes (parity of i + j + k; each colour
+ * from the values before its half-sweep), all other nodes held fixed. */
+static void chester_sor_set(const ora_grid* g, const ora_params* p, const double* phi,
+                            double* const* f, int nc, double omega, int iterations) {
+    long n = (long)g->nx * g->ny * g->nz;
+    const double ax = 1.0 / (g->dx * g->dx), ay = 1.0 / (g->dy * g->dy),
+                 az = 1.0 / (g->dz * g->dz);
+    const double diag = 2.0 * (ax + ay + az);
+    double* nv = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    for (int it = 0; it < iterations; ++it)
+        for (int colour = 0; colour < 2; ++colour)
+            for (int c = 0; c < nc; ++c) {
+                double* a = f[c];
+#pragma omp parallel for schedule(static)
+                for (long k = 0; k < g->nz; ++k)
+                    for (long j = 0; j < g->ny; ++j)
+                        for (long i = 0; i < g->nx; ++i) {
+                            long q = lin(g, i, j, k);
+                            if ((i + j + k) % 2 != colour) continue;
+                            if (ora_chester_class(phi[q], p->band_width) != ORA_CH_INTERIOR)
+                                continue;
+                            double s = ax * (at_padded(g, a, i + 1, j, k) + at_padded(g, a, i - 1, j, k))
+                                     + ay * (at_padded(g, a, i, j + 1, k) + at_padded(g, a, i, j - 1, k))
+                                     + az * (at_padded(g, a, i, j, k + 1) + at_padded(g, a, i, j, k - 1));
+                            nv[q] = (1.0 - omega) * a[q] + omega * s / diag;
+                        }
+#pragma omp parallel for schedule(static)
+                for (long q = 0; q < n; ++q) {
+                    long i = q % g->nx, j = (q / g->nx) % g->ny, k = q / ((long)g->nx * g->ny);
+                    if ((i + j + k) % 2 != colour) continue;
+                    if (ora_chester_class(phi[q], p->band_width) == ORA_CH_INTERIOR) a[q] = nv[q];
+                }
+            }
+    free(nv);
+}
+
+void ora_chester_sor(const ora_grid* g, const ora_params* p, const double* phi_uv,
+                     const double* phi_w, double omega, int iterations, double* const tau[6]) {
+    double* const uvf[4] = {tau[0], tau[1], tau[2], tau[3]};
+    double* const wf[2] = {tau[4], tau[5]};
+    chester_sor_set(g, p, phi_uv, uvf, 4, omega, iterations);
+    chester_sor_set(g, p, phi_w, wf, 2, omega, iterations);
+}

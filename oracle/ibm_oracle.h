@@ -127,6 +127,40 @@ void ora_smagorinsky(const ora_grid* g, double cs, double kappa, const double* p
                      const double* phi_w, const double* u, const double* v, const double* w,
                      double z0, const double* log_z0, double* const tau[6]);
 
+/* §1: Chester et al.'s original method, the comparison the paper improves on
+ * (its three steps are named in §1 and at the end of §3.3; the stencils are
+ * readings, see the design notes).  Both node sets are classified alike:
+ * fluid phi > b, fluid band 0 <= phi <= b, solid band -b <= phi < 0,
+ * interior phi < -b (b = band_width). */
+enum { ORA_CH_FLUID = 0, ORA_CH_BAND = 1, ORA_CH_SOLID_BAND = 2, ORA_CH_INTERIOR = 3 };
+int ora_chester_class(double phi, double band_width);
+/* counts[class] for uv nodes, counts[4 + class] for w nodes. */
+void ora_chester_counts(const ora_grid* g, const ora_params* p, const double* phi_uv,
+                        const double* phi_w, int64_t counts[8]);
+/* Step 1: the wall model of ora_wall_stress on the fluid band of each node
+ * set (uv: xx, yy, zz, xy; w: xz, yz); every node with phi < 0 gets 0 on its
+ * set's components; fluid nodes untouched.  stats as in ora_wall_stress,
+ * over the fluid-band nodes. */
+void ora_chester_wall_stress(const ora_grid* g, const ora_params* p, const double* phi_uv,
+                             const double* phi_w, const double* u, const double* v,
+                             const double* w, double z0, const double* log_z0,
+                             double* const tau[6], double stats[4]);
+/* Step 2: linear extrapolation into the solid band.  A solid-band node x
+ * with normal n (ora_normal on its set) samples each of its set's
+ * components (ora_interp on its set) at the points at distances phi_c and
+ * 2 phi_c from the surface along n, x + (phi_c - phi) n and
+ * x + (2 phi_c - phi) n, and takes tau1 + (phi - phi_c)(tau2 - tau1)/phi_c.
+ * Every value is computed from the field on entry, then written. */
+void ora_chester_extrapolate(const ora_grid* g, const ora_params* p, const double* phi_uv,
+                             const double* phi_w, double* const tau[6]);
+/* Step 3: ``iterations`` red-black SOR sweeps with relaxation ``omega`` of
+ * the Laplace equation (7-point, spacings dx, dy, dz; periodic in x and y,
+ * values outside 0 <= k < nz read as 0) for each component over the interior
+ * nodes of its node set, every other node held fixed.  Red = even i + j + k,
+ * first; each colour is updated from the values before its half-sweep. */
+void ora_chester_sor(const ora_grid* g, const ora_params* p, const double* phi_uv,
+                     const double* phi_w, double omega, int iterations, double* const tau[6]);
+
 int ora_num_threads(void);
 void ora_set_threads(int n);
 
