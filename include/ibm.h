@@ -207,6 +207,52 @@ int ibm_apply_sgs(ibm_ctx* c, const void* phi_uv, const void* phi_w, const void*
                   const void* const gradp[3], double dt, void* const div[3], double* drag_dev,
                   void* stream);
 
+/* Chester et al.'s original wall-modeled immersed boundary method, the
+ * comparison the paper improves on (§1: a near-wall model for the stresses in
+ * a fluid band, linear extrapolation of the stresses into a solid band around
+ * the body, SOR iterations smoothing the stress inside the body; §3.3, closing
+ * paragraphs: it classifies the w and uv grid points alike).  The paper gives
+ * no stencil or parameter for steps 2 and 3; these calls implement one stated
+ * reading.  Both node sets take the classes fluid phi > b, fluid band
+ * 0 <= phi <= b, solid band -b <= phi < 0, interior phi < -b (b = band_width
+ * of ibm_levelset_prepare).
+ *
+ * ibm_chester_prepare: the classes, band records, solid-band records and the
+ * interior node lists for this geometry.  phi_uv and phi_w must be the fields
+ * given to ibm_levelset_prepare (whose forcing flags ibm_apply keeps using);
+ * a later ibm_levelset_prepare discards this set-up.  nx and ny must each be 1
+ * or even (red-black colouring across the periodic seams), else
+ * IBM_E_UNSUPPORTED.  Synchronises ``stream``.  Errors: IBM_E_STATE (not
+ * prepared), IBM_E_ARG, IBM_E_UNSUPPORTED, IBM_E_HIP, IBM_E_NOMEM.
+ *
+ * ibm_chester_counts: out[0..3] uv nodes per class (fluid, fluid band, solid
+ * band, interior), out[4..7] w nodes.  Errors: IBM_E_STATE.
+ *
+ * ibm_chester_wall_stress: tau[6] holds the SGS stress on entry and leaves:
+ *   1. at fluid-band nodes the wall model of ibm_wall_stress (§3.3: sample at
+ *      phi_c along the normal, eq. bc-bottom-immersed, the rotated tensor;
+ *      uv nodes xx, yy, zz, xy, w nodes xz, yz); every node with phi < 0 set
+ *      to 0 on its node set's components; fluid nodes untouched;
+ *   2. at solid-band nodes, per component of the node set, the straight line
+ *      in the distance from the surface through the trilinear samples of the
+ *      field of step 1 at x + (phi_c - phi) n and x + (2 phi_c - phi) n,
+ *      evaluated at the node's phi;
+ *   3. ``iterations`` red-black SOR sweeps (relaxation ``omega`` in (0, 2);
+ *      red = even i + j + k first) of the 7-point Laplace equation with
+ *      spacings dx, dy, dz (periodic in x and y, values outside 0 <= k < nz
+ *      taken as 0) over the interior nodes of each node set, every other node
+ *      held fixed.
+ * Then ibm_apply gives the divergence, forcing and drag as for the simplified
+ * stage.  z0, log_z0 and stats_dev (4 device doubles, over the fluid-band
+ * nodes) as for ibm_wall_stress.  tau entries must be distinct and may not
+ * alias u, v, w or log_z0.  Asynchronous on ``stream`` (2 + 2 iterations
+ * launches).  Errors: IBM_E_STATE, IBM_E_ARG, IBM_E_RANGE (z0, omega). */
+int ibm_chester_prepare(ibm_ctx* c, const void* phi_uv, const void* phi_w, void* stream);
+int ibm_chester_counts(const ibm_ctx* c, int64_t out[8]);
+int ibm_chester_wall_stress(ibm_ctx* c, const void* u, const void* v, const void* w, double z0,
+                            const void* log_z0, void* const tau[6], double omega, int iterations,
+                            double* stats_dev, void* stream);
+
 /* Reverse mode of one stage pass with respect to u, v, w and log z0, for a
  * single velocity state that is both sampled by the wall model and forced
  * (ustar == u).  Cotangents: g_tau[6] (array or entries may be NULL = 0) of

@@ -676,32 +676,39 @@ static void chester_sor_set(const ora_grid* g, const ora_params* p, const double
     const double ax = 1.0 / (g->dx * g->dx), ay = 1.0 / (g->dy * g->dy),
                  az = 1.0 / (g->dz * g->dz);
     const double diag = 2.0 * (ax + ay + az);
+    /* the interior nodes of each colour, in ascending linear index */
+    long* list[2];
+    long m[2] = {0, 0};
+    for (int colour = 0; colour < 2; ++colour)
+        list[colour] = (long*)malloc(sizeof(long) * (size_t)(n > 0 ? n : 1));
+    for (long k = 0; k < g->nz; ++k)
+        for (long j = 0; j < g->ny; ++j)
+            for (long i = 0; i < g->nx; ++i) {
+                long q = lin(g, i, j, k);
+                if (ora_chester_class(phi[q], p->band_width) != ORA_CH_INTERIOR) continue;
+                int colour = (int)((i + j + k) % 2);
+                list[colour][m[colour]++] = q;
+            }
     double* nv = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     for (int it = 0; it < iterations; ++it)
         for (int colour = 0; colour < 2; ++colour)
             for (int c = 0; c < nc; ++c) {
                 double* a = f[c];
+                const long* L = list[colour];
 #pragma omp parallel for schedule(static)
-                for (long k = 0; k < g->nz; ++k)
-                    for (long j = 0; j < g->ny; ++j)
-                        for (long i = 0; i < g->nx; ++i) {
-                            long q = lin(g, i, j, k);
-                            if ((i + j + k) % 2 != colour) continue;
-                            if (ora_chester_class(phi[q], p->band_width) != ORA_CH_INTERIOR)
-                                continue;
-                            double s = ax * (at_padded(g, a, i + 1, j, k) + at_padded(g, a, i - 1, j, k))
-                                     + ay * (at_padded(g, a, i, j + 1, k) + at_padded(g, a, i, j - 1, k))
-                                     + az * (at_padded(g, a, i, j, k + 1) + at_padded(g, a, i, j, k - 1));
-                            nv[q] = (1.0 - omega) * a[q] + omega * s / diag;
-                        }
-#pragma omp parallel for schedule(static)
-                for (long q = 0; q < n; ++q) {
+                for (long r = 0; r < m[colour]; ++r) {
+                    long q = L[r];
                     long i = q % g->nx, j = (q / g->nx) % g->ny, k = q / ((long)g->nx * g->ny);
-                    if ((i + j + k) % 2 != colour) continue;
-                    if (ora_chester_class(phi[q], p->band_width) == ORA_CH_INTERIOR) a[q] = nv[q];
+                    double s = ax * (at_padded(g, a, i + 1, j, k) + at_padded(g, a, i - 1, j, k))
+                             + ay * (at_padded(g, a, i, j + 1, k) + at_padded(g, a, i, j - 1, k))
+                             + az * (at_padded(g, a, i, j, k + 1) + at_padded(g, a, i, j, k - 1));
+                    nv[r] = (1.0 - omega) * a[q] + omega * s / diag;
                 }
+                for (long r = 0; r < m[colour]; ++r) a[L[r]] = nv[r];
             }
     free(nv);
+    free(list[0]);
+    free(list[1]);
 }
 
 void ora_chester_sor(const ora_grid* g, const ora_params* p, const double* phi_uv,

@@ -167,6 +167,37 @@ class Context:
                                             self._field(log_z0, "log_z0"), ptr_array(taus), sp,
                                             self._stream()))
 
+    def chester_prepare(self, phi_uv, phi_w):
+        """Set-up of Chester et al.'s original method (after ``prepare``, same phi)."""
+        with torch.cuda.device(self.device):
+            check(self._lib.ibm_chester_prepare(self._h, self._field(phi_uv, "phi_uv"),
+                                                self._field(phi_w, "phi_w"), self._stream()))
+
+    def chester_counts(self):
+        """[uv fluid, fluid band, solid band, interior, w ... the same]."""
+        out = np.zeros(8, dtype=np.int64)
+        check(self._lib.ibm_chester_counts(self._h, out.ctypes.data_as(_lib.POINTER(_lib.c_int64))))
+        return out
+
+    def chester_wall_stress(self, u, v, w, tau, omega, iterations, z0=None, log_z0=None,
+                            stats=None):
+        """The original method's stress in place in ``tau``: wall model in the
+        fluid band, extrapolation into the solid band, ``iterations`` SOR sweeps
+        over the interior."""
+        if (z0 is None) == (log_z0 is None):
+            raise ValueError("give exactly one of z0 and log_z0")
+        taus = self._fields(tau, "tau", 6)
+        sp = None
+        if stats is not None:
+            if stats.dtype != torch.float64 or stats.numel() < 4 or stats.device != self.device:
+                raise ValueError("stats must be a float64 device tensor with 4 elements")
+            sp = stats.data_ptr()
+        with torch.cuda.device(self.device):
+            check(self._lib.ibm_chester_wall_stress(
+                self._h, self._field(u, "u"), self._field(v, "v"), self._field(w, "w"),
+                float(z0 or 0.0), self._field(log_z0, "log_z0"), ptr_array(taus), float(omega),
+                int(iterations), sp, self._stream()))
+
     def apply(self, tau, ustar, div, gradp=None, dt=0.01, drag=None):
         """div = +div(tau); ustar forced in place where phi <= 0; drag (float64[3]) optional."""
         taus = self._fields(tau, "tau", 6)

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libibm.so")
 SOURCES = ["api.hip", "prepare.hip", "stage.hip", "vjp.hip", "batch.hip", "sgs.hip",
-           "spectral.hip", "projection.hip", "sgs_apply.hip"]
+           "spectral.hip", "projection.hip", "sgs_apply.hip", "chester.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 CFLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

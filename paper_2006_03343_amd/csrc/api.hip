@@ -1,6 +1,6 @@
 // api.hip -- the extern "C" entry points declared in include/ibm.h: argument
 // checks, context lifetime, error reporting and stream plumbing.  All numeric
-// work is in prepare.hip, stage.hip and vjp.hip.
+// work is in the other sources.
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -50,6 +50,19 @@ int check_field(const ibm_ctx* c, const void* p, const char* fn, const char* nam
     if (vec_aligned && a % 16)
         return fail(IBM_E_ARG, "%s: %s must be 16-byte aligned", fn, name);
     return IBM_OK;
+}
+
+// True if any of the n pointers in ``outs`` equals one of the m pointers in
+// ``ins`` (NULL entries ignored) or two entries of ``outs`` are equal.
+bool aliases(const void* const* outs, int n, const void* const* ins, int m) {
+    for (int i = 0; i < n; ++i) {
+        if (!outs[i]) continue;
+        for (int j = 0; j < m; ++j)
+            if (ins[j] && ins[j] == outs[i]) return true;
+        for (int j = i + 1; j < n; ++j)
+            if (outs[j] == outs[i]) return true;
+    }
+    return false;
 }
 
 }  // namespace
@@ -194,6 +207,12 @@ int ibm_wall_stress(ibm_ctx* c, const void* u, const void* v, const void* w, dou
     }
     if (stats_dev && ((uintptr_t)stats_dev % 8))
         return fail(IBM_E_ARG, "%s: stats_dev misaligned", fn);
+    {   // one launch gathers u, v, w and writes tau
+        const void* ins[4] = {u, v, w, log_z0};
+        const void* outs[6] = {tau[0], tau[1], tau[2], tau[3], tau[4], tau[5]};
+        if (aliases(outs, 6, ins, 4))
+            return fail(IBM_E_ARG, "%s: tau entries must be distinct and may not alias u, v, w or log_z0", fn);
+    }
     DeviceScope dg(c->device);
     return launch_wall_stress(c, u, v, w, z0, log_z0, tau, stats_dev, (hipStream_t)stream);
 }
@@ -229,6 +248,17 @@ int ibm_apply(ibm_ctx* c, const void* const tau[6], void* const ustar[3],
             if (div[i] == tau[j]) return fail(IBM_E_ARG, "%s: div may not alias tau", fn);
     }
     if (drag_dev && ((uintptr_t)drag_dev % 8)) return fail(IBM_E_ARG, "%s: drag_dev misaligned", fn);
+    {   // one launch reads tau and gradp and writes div and ustar
+        const void* ins[9] = {tau[0], tau[1], tau[2], tau[3], tau[4], tau[5],
+                              gradp ? gradp[0] : nullptr, gradp ? gradp[1] : nullptr,
+                              gradp ? gradp[2] : nullptr};
+        const void* outs[3] = {div[0], div[1], div[2]};
+        if (aliases(outs, 3, ins, 9) || aliases(outs, 3, (const void* const*)ustar, 3))
+            return fail(IBM_E_ARG, "%s: div entries must be distinct and may not alias tau, gradp or ustar", fn);
+        const void* us[3] = {ustar[0], ustar[1], ustar[2]};
+        if (aliases(us, 3, ins, 6))
+            return fail(IBM_E_ARG, "%s: ustar entries must be distinct and may not alias tau", fn);
+    }
     DeviceScope dg(c->device);
     return launch_apply(c, cfg, tau, ustar, gradp, dt, div, drag_dev, (hipStream_t)stream);
 }
@@ -252,6 +282,17 @@ int ibm_apply_spectral(ibm_ctx* c, const void* const tau[6], void* const ustar[3
             if (div[i] == tau[j]) return fail(IBM_E_ARG, "%s: div may not alias tau", fn);
     }
     if (drag_dev && ((uintptr_t)drag_dev % 8)) return fail(IBM_E_ARG, "%s: drag_dev misaligned", fn);
+    {   // one launch reads tau and gradp and writes div and ustar
+        const void* ins[9] = {tau[0], tau[1], tau[2], tau[3], tau[4], tau[5],
+                              gradp ? gradp[0] : nullptr, gradp ? gradp[1] : nullptr,
+                              gradp ? gradp[2] : nullptr};
+        const void* outs[3] = {div[0], div[1], div[2]};
+        if (aliases(outs, 3, ins, 9) || aliases(outs, 3, (const void* const*)ustar, 3))
+            return fail(IBM_E_ARG, "%s: div entries must be distinct and may not alias tau, gradp or ustar", fn);
+        const void* us[3] = {ustar[0], ustar[1], ustar[2]};
+        if (aliases(us, 3, ins, 6))
+            return fail(IBM_E_ARG, "%s: ustar entries must be distinct and may not alias tau", fn);
+    }
     DeviceScope dg(c->device);
     return launch_apply_spectral(c, tau, ustar, gradp, dt, div, drag_dev, (hipStream_t)stream);
 }
@@ -372,6 +413,65 @@ int ibm_apply_sgs(ibm_ctx* c, const void* phi_uv, const void* phi_w, const void*
                             dt, div, drag_dev, (hipStream_t)stream);
 }
 
+int ibm_chester_prepare(ibm_ctx* c, const void* phi_uv, const void* phi_w, void* stream) {
+    g_err[0] = 0;
+    const char* fn = "ibm_chester_prepare";
+    int rc = check_ctx(c, true, fn);
+    if (rc) return rc;
+    if ((rc = check_field(c, phi_uv, fn, "phi_uv")) || (rc = check_field(c, phi_w, fn, "phi_w")))
+        return rc;
+    // red-black colouring stays a two-colouring across the periodic seams
+    if ((c->g.nx > 1 && c->g.nx % 2) || (c->g.ny > 1 && c->g.ny % 2))
+        return fail(IBM_E_UNSUPPORTED, "%s: nx and ny must be 1 or even (got %d, %d)", fn, c->g.nx,
+                    c->g.ny);
+    DeviceScope dg(c->device);
+    return chester_prepare(c, phi_uv, phi_w, (hipStream_t)stream);
+}
+
+int ibm_chester_counts(const ibm_ctx* c, int64_t out[8]) {
+    int rc = check_ctx(c, true, "ibm_chester_counts");
+    if (rc) return rc;
+    if (!c->ch.built) return fail(IBM_E_STATE, "ibm_chester_counts: call ibm_chester_prepare first");
+    if (!out) return fail(IBM_E_ARG, "ibm_chester_counts: out is NULL");
+    for (int i = 0; i < 8; ++i) out[i] = c->ch.counts[i];
+    return IBM_OK;
+}
+
+int ibm_chester_wall_stress(ibm_ctx* c, const void* u, const void* v, const void* w, double z0,
+                            const void* log_z0, void* const tau[6], double omega, int iterations,
+                            double* stats_dev, void* stream) {
+    g_err[0] = 0;
+    const char* fn = "ibm_chester_wall_stress";
+    int rc = check_ctx(c, true, fn);
+    if (rc) return rc;
+    if (!c->ch.built) return fail(IBM_E_STATE, "%s: call ibm_chester_prepare first", fn);
+    if ((rc = check_field(c, u, fn, "u")) || (rc = check_field(c, v, fn, "v")) ||
+        (rc = check_field(c, w, fn, "w")))
+        return rc;
+    if (!tau) return fail(IBM_E_ARG, "%s: tau is NULL", fn);
+    for (int i = 0; i < 6; ++i)
+        if ((rc = check_field(c, tau[i], fn, "tau[i]"))) return rc;
+    if (log_z0) {
+        if ((rc = check_field(c, log_z0, fn, "log_z0"))) return rc;
+    } else if (!(z0 > 0.0) || !(z0 < c->p.phi_c)) {
+        return fail(IBM_E_RANGE, "%s: z0 must satisfy 0 < z0 < phi_c (got %g)", fn, z0);
+    }
+    if (!(omega > 0.0 && omega < 2.0))
+        return fail(IBM_E_RANGE, "%s: omega must lie in (0, 2) (got %g)", fn, omega);
+    if (iterations < 0) return fail(IBM_E_ARG, "%s: iterations must be >= 0", fn);
+    if (stats_dev && ((uintptr_t)stats_dev % 8))
+        return fail(IBM_E_ARG, "%s: stats_dev misaligned", fn);
+    {
+        const void* ins[4] = {u, v, w, log_z0};
+        const void* outs[6] = {tau[0], tau[1], tau[2], tau[3], tau[4], tau[5]};
+        if (aliases(outs, 6, ins, 4))
+            return fail(IBM_E_ARG, "%s: tau entries must be distinct and may not alias u, v, w or log_z0", fn);
+    }
+    DeviceScope dg(c->device);
+    return launch_chester_wall_stress(c, u, v, w, z0, log_z0, tau, omega, iterations, stats_dev,
+                                      (hipStream_t)stream);
+}
+
 int ibm_set_tile(ibm_ctx* c, int vx, int ty, int kz, int wpb) {
     g_err[0] = 0;
     int rc = check_ctx(c, false, "ibm_set_tile");
@@ -432,6 +532,15 @@ int ibm_stage_vjp(ibm_ctx* c, const void* u, const void* v, const void* w, doubl
             return fail(IBM_E_RANGE, "%s: z0 must satisfy 0 < z0 < phi_c (got %g)", fn, z0);
     }
     if (glog_z0 && (rc = check_field(c, glog_z0, fn, "glog_z0"))) return rc;
+    {   // the gradients are written while the inputs are still read
+        const void* ins[16] = {u, v, w, log_z0, g_div[0], g_div[1], g_div[2],
+                               g_ustar[0], g_ustar[1], g_ustar[2]};
+        if (g_tau)
+            for (int i = 0; i < 6; ++i) ins[10 + i] = g_tau[i];
+        const void* outs[4] = {gu, gv, gw, glog_z0};
+        if (aliases(outs, 4, ins, 16))
+            return fail(IBM_E_ARG, "%s: gu, gv, gw, glog_z0 must be distinct and may not alias an input", fn);
+    }
     // the transposed stencil map keys a record in 29 bits and offsets its
     // eight corners per record in 32-bit signed integers
     const long nrec = c->rec[0].n + c->rec[1].n;

@@ -102,6 +102,26 @@ struct AdjointMap {
     void* rbar = nullptr;        // per-record sample-velocity cotangents, 3 x (nuv + nw)
 };
 
+// Set-up of Chester et al.'s original method (built by ibm_chester_prepare).
+// Both node sets are classified alike: 0 fluid (phi > b), 1 fluid band
+// (0 <= phi <= b), 2 solid band (-b <= phi < 0), 3 body interior (phi < -b);
+// the class byte holds the uv class in bits 0-1 and the w class in bits 2-3.
+struct ChesterGeom {
+    bool built = false;
+    uint8_t* mask = nullptr;
+    int64_t counts[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // [uv class 0..3, w class 0..3]
+    Records band[2];             // fluid band: sample stencil at distance phi_c
+    Records sb1[2];              // solid band: stencils at distances phi_c ...
+    Records sb2[2];              // ... and 2 phi_c from the surface along the normal
+    void* lists = nullptr;       // interior nodes of each node set and colour
+    int32_t* inner[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    long ninner[2][2] = {{0, 0}, {0, 0}};
+    void* ext = nullptr;         // extrapolated values: 4 per uv, 2 per w solid-band record
+    long nzsegs = 0;
+    Seg* zsegs = nullptr;        // segments holding a node with phi < 0 on either set
+    double* partials = nullptr;  // statistics slots, 4 per fluid-band block
+};
+
 }  // namespace ibm
 
 struct ibm_ctx {
@@ -131,6 +151,7 @@ struct ibm_ctx {
     ibm::AdjointMap adj;
     ibm::SpectralTw spec;
     ibm::ProjWs proj;
+    ibm::ChesterGeom ch;
     // bumped whenever the tile shape or any prepared device buffer may change;
     // a batch compares it against the value its work tables were built with
     unsigned long gen = 0;
@@ -194,6 +215,13 @@ int launch_sgs_apply(ibm_ctx* c, const void* phi_uv, const void* phi_w, const vo
 int launch_sgs(ibm_ctx* c, const TileCfg& cfg, const void* phi_uv, const void* phi_w,
                const void* u, const void* v, const void* w, double z0, const void* log_z0,
                double cs, double kappa, void* const tau[6], hipStream_t s);
+
+// chester.hip
+int chester_prepare(ibm_ctx* c, const void* phi_uv, const void* phi_w, hipStream_t s);
+int launch_chester_wall_stress(ibm_ctx* c, const void* u, const void* v, const void* w,
+                               double z0, const void* log_z0, void* const tau[6], double omega,
+                               int iterations, double* stats, hipStream_t s);
+void free_chester(ibm_ctx* c);
 
 // batch.hip
 int autotune(ibm_ctx* c, const char* cache_path, int flags, hipStream_t s);

@@ -73,7 +73,8 @@ __device__ inline T trilerp(const T* __restrict__ f, long c00, long c10, long c0
     return lo * gz + hi * fz;
 }
 
-// Stress of the solid nodes of one segment set to zero, by ``nthr`` threads
+// Stress of the solid nodes of one segment set to zero (class code 2, or 3:
+// the body interior of Chester et al.'s classes), by ``nthr`` threads
 // numbered ``tid``: thread tid takes nodes q + tid + i * nthr, so each store
 // of a wave is contiguous.  kPer mask bytes per thread are loaded before any
 // store (byte loads may alias the stores, so the compiler would not hoist
@@ -98,13 +99,13 @@ __device__ inline void zero_seg(const WSArgs<T>& a, const Seg sg, int tid, int n
 #pragma unroll
         for (int i = 0; i < kPer; ++i) {
             const int t = o + i * nthr;
-            if ((m[i] & 3u) == 2u) {
+            if ((m[i] & 3u) >= 2u) {
                 t0[t] = T(0);
                 t1[t] = T(0);
                 t2[t] = T(0);
                 t3[t] = T(0);
             }
-            if (((m[i] >> 2) & 3u) == 2u) {
+            if (((m[i] >> 2) & 3u) >= 2u) {
                 t4[t] = T(0);
                 t5[t] = T(0);
             }
