@@ -119,6 +119,24 @@ int ibm_apply(ibm_ctx* c, const void* const tau[6], void* const ustar[3],
               const void* const gradp[3], double dt, void* const div[3], double* drag_dev,
               void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): ibm_apply
+ * with its drag reduction slots (3 doubles per tile of the dense pass) in a
+ * static device array of the library, 1 MiB on each GPU (held until the
+ * process ends), instead of the context's.  Allocates nothing and calls no
+ * allocating routine.  Same arguments, checks and results as ibm_apply (bit
+ * for bit: the same kernels and slot order).  When drag_dev is given the
+ * context's tile shape may have at most 43690 tiles (ibm_get_tile), else
+ * IBM_E_RANGE before anything is enqueued.  Every call on one GPU shares that
+ * GPU's array, which keeps the last call's contents (each slot a call reads
+ * is written by that call first): calls that overlap on one GPU -- on
+ * different streams or from several host threads -- race and their drag is
+ * undefined; order them on one stream.  Asynchronous on ``stream``.  Errors:
+ * those of ibm_apply, IBM_E_RANGE. */
+int ibm_apply_noalloc(ibm_ctx* c, const void* const tau[6], void* const ustar[3],
+                      const void* const gradp[3], double dt, void* const div[3],
+                      double* drag_dev, void* stream);
+
 /* ibm_apply with the horizontal derivatives of the divergence taken
  * pseudo-spectrally, as the paper's solver does (§2.4, eq. dudx): d/dx A =
  * sum of i k A_hat exp(i k x) over the wavenumbers of the periodic x and y

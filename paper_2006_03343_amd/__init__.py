@@ -215,6 +215,24 @@ class Context:
             check(self._lib.ibm_apply(self._h, ptr_array(taus), ptr_array(us), gp, float(dt),
                                       ptr_array(dv), dp, self._stream()))
 
+    def apply_noalloc(self, tau, ustar, div, gradp=None, dt=0.01, drag=None):
+        """``apply`` with its drag slots in the library's static device array
+        (ibm_apply_noalloc): allocates nothing; overlapping calls on one GPU race."""
+        taus = self._fields(tau, "tau", 6)
+        us = self._fields(ustar, "ustar", 3)
+        dv = self._fields(div, "div", 3)
+        gp = None
+        if gradp is not None:
+            gp = ptr_array([self._field(t, f"gradp[{i}]") for i, t in enumerate(gradp)])
+        dp = None
+        if drag is not None:
+            if drag.dtype != torch.float64 or drag.numel() < 3 or drag.device != self.device:
+                raise ValueError("drag must be a float64 device tensor with 3 elements")
+            dp = drag.data_ptr()
+        with torch.cuda.device(self.device):
+            check(self._lib.ibm_apply_noalloc(self._h, ptr_array(taus), ptr_array(us), gp,
+                                              float(dt), ptr_array(dv), dp, self._stream()))
+
     def apply_spectral(self, tau, ustar, div, gradp=None, dt=0.01, drag=None):
         """``apply`` with pseudo-spectral horizontal derivatives (power-of-two nx, ny)."""
         taus = self._fields(tau, "tau", 6)

@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -12,8 +13,38 @@
 
 namespace ibm {
 
+// Drag slots of ibm_apply_noalloc: a static device array, one copy per GPU,
+// held until the process ends.  Host code never passes ``scratch`` itself (in
+// host code the name is a stand-in, not a device address): its address on
+// each device is taken once, at the first ibm_create on that device, and
+// kept in g_scratch.
+constexpr long kScratchDoubles = 1L << 17;   // 1 MiB: 3 slots per tile, 43690 tiles
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
 namespace {
 thread_local char g_err[512] = "";
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices] = {};
+
+// With ``dev`` current: look up and keep this device's address of scratch.
+int scratch_init(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return IBM_OK;   // ibm_apply_noalloc will refuse
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[dev]) return IBM_OK;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch[dev] = (double*)p;
+    return IBM_OK;
+}
+
+double* scratch_ptr(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch[dev];
+}
 }
 
 int fail(int code, const char* fmt, ...) {
@@ -65,6 +96,49 @@ bool aliases(const void* const* outs, int n, const void* const* ins, int m) {
     return false;
 }
 
+// Argument checks of ibm_apply and ibm_apply_noalloc; leaves the tile shape
+// to launch in *cfg (one element per lane for misaligned views).
+int check_apply(ibm_ctx* c, const void* const tau[6], void* const ustar[3],
+                const void* const gradp[3], double dt, void* const div[3], double* drag_dev,
+                const char* fn, TileCfg* cfg_out) {
+    int rc = check_ctx(c, true, fn);
+    if (rc) return rc;
+    if (!tau || !ustar || !div) return fail(IBM_E_ARG, "%s: tau, ustar and div are required", fn);
+    if (!std::isfinite(dt)) return fail(IBM_E_ARG, "%s: dt must be finite", fn);
+    TileCfg cfg = c->cfg;
+    bool vec = cfg.vx > 1;
+    for (int pass = 0; pass < 2; ++pass) {
+        bool ok = true;
+        for (int i = 0; i < 6 && ok; ++i)
+            ok = tau[i] && (uintptr_t)tau[i] % (vec ? 16 : tsize(c)) == 0;
+        for (int i = 0; i < 3 && ok; ++i) ok = div[i] && (uintptr_t)div[i] % (vec ? 16 : tsize(c)) == 0;
+        if (ok) break;
+        if (!vec) break;
+        cfg.vx = 1;   // a misaligned view: fall back to one element per lane
+        vec = false;
+    }
+    for (int i = 0; i < 6; ++i)
+        if ((rc = check_field(c, tau[i], fn, "tau[i]"))) return rc;
+    for (int i = 0; i < 3; ++i) {
+        if ((rc = check_field(c, div[i], fn, "div[i]"))) return rc;
+        if ((rc = check_field(c, ustar[i], fn, "ustar[i]"))) return rc;
+        if (gradp && gradp[i] && (rc = check_field(c, gradp[i], fn, "gradp[i]"))) return rc;
+    }
+    if (drag_dev && ((uintptr_t)drag_dev % 8)) return fail(IBM_E_ARG, "%s: drag_dev misaligned", fn);
+    {   // one launch reads tau and gradp and writes div and ustar
+        const void* ins[9] = {tau[0], tau[1], tau[2], tau[3], tau[4], tau[5],
+                              gradp ? gradp[0] : nullptr, gradp ? gradp[1] : nullptr,
+                              gradp ? gradp[2] : nullptr};
+        const void* outs[3] = {div[0], div[1], div[2]};
+        if (aliases(outs, 3, ins, 9) || aliases(outs, 3, (const void* const*)ustar, 3))
+            return fail(IBM_E_ARG, "%s: div entries must be distinct and may not alias tau, gradp or ustar", fn);
+        const void* us[3] = {ustar[0], ustar[1], ustar[2]};
+        if (aliases(us, 3, ins, 6))
+            return fail(IBM_E_ARG, "%s: ustar entries must be distinct and may not alias tau", fn);
+    }
+    *cfg_out = cfg;
+    return IBM_OK;
+}
 }  // namespace
 }  // namespace ibm
 
@@ -102,6 +176,11 @@ int ibm_create(ibm_ctx** out, const ibm_grid* g, int dtype, int precision) {
         return hip_fail(e, "hipGetDevice");
     }
     c->cfg = default_tile(c);
+    const int rc = scratch_init(c->device);
+    if (rc) {
+        delete c;
+        return rc;
+    }
     *out = c;
     return IBM_OK;
 }
@@ -221,46 +300,34 @@ int ibm_apply(ibm_ctx* c, const void* const tau[6], void* const ustar[3],
               const void* const gradp[3], double dt, void* const div[3], double* drag_dev,
               void* stream) {
     g_err[0] = 0;
-    const char* fn = "ibm_apply";
-    int rc = check_ctx(c, true, fn);
+    TileCfg cfg;
+    const int rc = check_apply(c, tau, ustar, gradp, dt, div, drag_dev, "ibm_apply", &cfg);
     if (rc) return rc;
-    if (!tau || !ustar || !div) return fail(IBM_E_ARG, "%s: tau, ustar and div are required", fn);
-    if (!std::isfinite(dt)) return fail(IBM_E_ARG, "%s: dt must be finite", fn);
-    TileCfg cfg = c->cfg;
-    bool vec = cfg.vx > 1;
-    for (int pass = 0; pass < 2; ++pass) {
-        bool ok = true;
-        for (int i = 0; i < 6 && ok; ++i)
-            ok = tau[i] && (uintptr_t)tau[i] % (vec ? 16 : tsize(c)) == 0;
-        for (int i = 0; i < 3 && ok; ++i) ok = div[i] && (uintptr_t)div[i] % (vec ? 16 : tsize(c)) == 0;
-        if (ok) break;
-        if (!vec) break;
-        cfg.vx = 1;   // a misaligned view: fall back to one element per lane
-        vec = false;
-    }
-    for (int i = 0; i < 6; ++i)
-        if ((rc = check_field(c, tau[i], fn, "tau[i]"))) return rc;
-    for (int i = 0; i < 3; ++i) {
-        if ((rc = check_field(c, div[i], fn, "div[i]"))) return rc;
-        if ((rc = check_field(c, ustar[i], fn, "ustar[i]"))) return rc;
-        if (gradp && gradp[i] && (rc = check_field(c, gradp[i], fn, "gradp[i]"))) return rc;
-        for (int j = 0; j < 6; ++j)
-            if (div[i] == tau[j]) return fail(IBM_E_ARG, "%s: div may not alias tau", fn);
-    }
-    if (drag_dev && ((uintptr_t)drag_dev % 8)) return fail(IBM_E_ARG, "%s: drag_dev misaligned", fn);
-    {   // one launch reads tau and gradp and writes div and ustar
-        const void* ins[9] = {tau[0], tau[1], tau[2], tau[3], tau[4], tau[5],
-                              gradp ? gradp[0] : nullptr, gradp ? gradp[1] : nullptr,
-                              gradp ? gradp[2] : nullptr};
-        const void* outs[3] = {div[0], div[1], div[2]};
-        if (aliases(outs, 3, ins, 9) || aliases(outs, 3, (const void* const*)ustar, 3))
-            return fail(IBM_E_ARG, "%s: div entries must be distinct and may not alias tau, gradp or ustar", fn);
-        const void* us[3] = {ustar[0], ustar[1], ustar[2]};
-        if (aliases(us, 3, ins, 6))
-            return fail(IBM_E_ARG, "%s: ustar entries must be distinct and may not alias tau", fn);
-    }
     DeviceScope dg(c->device);
     return launch_apply(c, cfg, tau, ustar, gradp, dt, div, drag_dev, (hipStream_t)stream);
+}
+
+int ibm_apply_noalloc(ibm_ctx* c, const void* const tau[6], void* const ustar[3],
+                      const void* const gradp[3], double dt, void* const div[3],
+                      double* drag_dev, void* stream) {
+    g_err[0] = 0;
+    const char* fn = "ibm_apply_noalloc";
+    TileCfg cfg;
+    int rc = check_apply(c, tau, ustar, gradp, dt, div, drag_dev, fn, &cfg);
+    if (rc) return rc;
+    double* slots = nullptr;
+    if (drag_dev) {
+        const long need = 3 * apply_tiles(c, cfg);
+        if (need > kScratchDoubles)
+            return fail(IBM_E_RANGE, "%s: %ld drag slots needed (3 per tile), the static scratch "
+                        "holds %ld; use ibm_apply or a tile shape with fewer tiles", fn, need,
+                        kScratchDoubles);
+        slots = scratch_ptr(c->device);
+        if (!slots)
+            return fail(IBM_E_STATE, "%s: no static scratch on device %d", fn, c->device);
+    }
+    DeviceScope dg(c->device);
+    return launch_apply(c, cfg, tau, ustar, gradp, dt, div, drag_dev, (hipStream_t)stream, slots);
 }
 
 int ibm_apply_spectral(ibm_ctx* c, const void* const tau[6], void* const ustar[3],

@@ -171,9 +171,11 @@ void free_prepared(ibm_ctx* c);
 // stage.hip
 int launch_wall_stress(ibm_ctx* c, const void* u, const void* v, const void* w, double z0,
                        const void* log_z0, void* const tau[6], double* stats, hipStream_t s);
+// ``partials``: the drag slots (3 per tile) to use instead of the context's
+// (NULL: the context's, sized by size_partials).
 int launch_apply(ibm_ctx* c, const TileCfg& cfg, const void* const tau[6], void* const ustar[3],
                  const void* const gradp[3], double dt, void* const div[3], double* drag,
-                 hipStream_t s);
+                 hipStream_t s, double* partials = nullptr);
 bool tile_supported(const ibm_ctx* c, const TileCfg& cfg);
 TileCfg default_tile(const ibm_ctx* c);
 long apply_tiles(const ibm_ctx* c, const TileCfg& cfg);

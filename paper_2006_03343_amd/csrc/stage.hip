@@ -106,9 +106,12 @@ bool dispatch_vx(const ApplyArgs<T>& a, int vx, int ty, unsigned grid, unsigned 
 template <typename T>
 int apply_t(ibm_ctx* c, const TileCfg& cfg, const void* const tau[6], void* const ustar[3],
             const void* const gradp[3], double dt, void* const div[3], double* drag,
-            hipStream_t s) {
+            hipStream_t s, double* partials) {
     ApplyArgs<T> a = make_apply_args<T>(c, cfg, tau, ustar, gradp, dt, div, drag);
-    if (c->ap_cap < 3 * a.ntiles) return fail(IBM_E_STATE, "apply: reduction slots not sized");
+    if (partials)
+        a.partials = partials;   // the caller's slots, of at least 3 * ntiles doubles
+    else if (c->ap_cap < 3 * a.ntiles)
+        return fail(IBM_E_STATE, "apply: reduction slots not sized");
     a.nfblocks = (int)std::min<long>((4 * c->nfsegs + 7) / 8 * 8, 2048);
     const unsigned grid = (unsigned)(a.nfblocks + 8 * a.per_xcd);
     const unsigned block = (unsigned)(64 * cfg.wpb);
@@ -217,9 +220,10 @@ int launch_wall_stress(ibm_ctx* c, const void* u, const void* v, const void* w, 
 
 int launch_apply(ibm_ctx* c, const TileCfg& cfg, const void* const tau[6], void* const ustar[3],
                  const void* const gradp[3], double dt, void* const div[3], double* drag,
-                 hipStream_t s) {
-    if (c->dtype == IBM_F64) return apply_t<double>(c, cfg, tau, ustar, gradp, dt, div, drag, s);
-    return apply_t<float>(c, cfg, tau, ustar, gradp, dt, div, drag, s);
+                 hipStream_t s, double* partials) {
+    if (c->dtype == IBM_F64)
+        return apply_t<double>(c, cfg, tau, ustar, gradp, dt, div, drag, s, partials);
+    return apply_t<float>(c, cfg, tau, ustar, gradp, dt, div, drag, s, partials);
 }
 
 }  // namespace ibm
