@@ -6,7 +6,8 @@
   oracle; also a batch of one-column, one-row, one- and two-plane and ragged
   cases;
 * the 64-case ensemble the benchmark times (105.6 M points, one graph
-  launch): one case of each grid shape against the oracle, every node;
+  launch): all 64 cases bit for bit against plain per-case calls, one case
+  of each grid shape and the last case against the oracle, every node;
 * replays of the captured hipGraph, with eager work and synchronisations in
   between, each equal the eager result;
 * two cases of 4096 x 4096 x 64 (2^31 nodes together, each a set of periodic
@@ -285,8 +286,11 @@ def test_degenerate_cases(ora, dtype, prec):
 
 def test_ensemble_full_size(ora, tmp_path):
     """The 64-case ensemble as the benchmark times it (105.6 M points, float32
-    mixed, tiles from the shipped autotuner cache, one graph launch): one case
-    of each grid shape against the oracle's stage, every node."""
+    mixed, tiles from the shipped autotuner cache, one graph launch): every
+    case equal bit for bit to plain per-case calls on the same tile (stress,
+    divergence, forced velocity, drag, statistics), which covers the late
+    items of each XCD work slice; one case of each grid shape and the last
+    case of the work list against the oracle's stage, every node."""
     import shutil
     import paper_2006_03343_amd as ibm
     torch, dev = torch_dev()
@@ -300,8 +304,12 @@ def test_ensemble_full_size(ora, tmp_path):
     b.capture()
     b.launch()
     torch.cuda.synchronize()
+    for i, (w, f) in enumerate(zip(wls, fs)):
+        tile = b.case(i).get_tile()
+        _same(f.snapshot(), _plain(w, tile, torch.float32, "mixed", dev), f"case {i} tile {tile}")
+    _say("all 64 cases equal the plain calls bit for bit")
     picked = sorted({s: i for i, s in reversed(list(enumerate(shapes)))}.values())
-    for i in picked:
+    for i in picked + [len(wls) - 1]:
         _say(f"case {i} {shapes[i]} tile {b.case(i).get_tile()} vs the oracle")
         out = dict(tau=fs[i].tau.cpu().numpy(), div=fs[i].div.cpu().numpy(),
                    ustar=fs[i].ustar.cpu().numpy(), drag=fs[i].drag.cpu().numpy(),

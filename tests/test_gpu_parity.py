@@ -271,6 +271,56 @@ def test_hill_full_size_mixed(ora):
     _say(f"errors {errs}")
 
 
+def test_hill_full_size_f64_plain(ora):
+    """The float64 plain hill the benchmark divides by, on the autotuner's
+    cached tile for it (2, 4, 64, 4), every node compared."""
+    wl = configs.hill()
+    _say("hill 512x256x256 f64 plain (benchmark ratio's denominator)")
+    out, ctx = run_gpu(wl, "f64", "plain", tile=(2, 4, 64, 4))
+    errs = compare(out, _ref(ora, wl), wl, TOL["f64"])
+    _say(f"errors {errs}")
+
+
+def _node_errors(out, ref, mask):
+    """Per band node: max over its node set's stress components of |gpu -
+    oracle|, and the same of |oracle| (the node's own scale)."""
+    res = []
+    for comps, shift in (((0, 1, 2, 3), 0), ((4, 5), 2)):
+        sel = ((mask >> shift) & 3) == 1
+        d = np.max([np.abs(out["tau"][c][sel] - ref["tau"][c][sel]) for c in comps], axis=0)
+        m = np.max([np.abs(ref["tau"][c][sel]) for c in comps], axis=0)
+        res.append((d, m))
+    return res
+
+
+def test_hill_mixed_node_by_node(ora):
+    """Mixed precision on the full hill, band node by band node against each
+    node's own stress (not the field's maximum): the near-wall records
+    (|phi| <= dz, log law in double) and the rest, per node set.  Nodes at
+    least 1e-3 of the field's maximum stay within 2e-5 of their own value;
+    smaller ones within 2e-8 of the field's maximum."""
+    wl = configs.hill().cast(np.float32)
+    _say("hill 512x256x256 f32 mixed: node-by-node stress")
+    out, ctx = run_gpu(wl, "f32", "mixed")
+    ref = _ref(ora, wl)
+    compare(out, ref, wl, TOL["f32"])
+    near = [np.abs(np.asarray(p, np.float64)) <= wl.grid.dz for p in (wl.phi_uv, wl.phi_w)]
+    for (d, m), name, shift, nr in zip(_node_errors(out, ref, ref["mask"]), ("uv", "w"), (0, 2),
+                                       near):
+        sel = ((ref["mask"] >> shift) & 3) == 1
+        nsel = nr[sel]
+        top = float(m.max())
+        big = m >= 1e-3 * top
+        rel = d[big] / m[big]
+        _say(f"{name}: {sel.sum()} band nodes ({nsel.sum()} within dz); relative error per node "
+             f"(>= 1e-3 of max) median {np.median(rel):.2e}, 99.9% {np.quantile(rel, 0.999):.2e}, "
+             f"max {rel.max():.2e} (within dz: {(d[big & nsel] / m[big & nsel]).max():.2e}); "
+             f"small nodes max {d[~big].max() / top if (~big).any() else 0.0:.2e} of the max")
+        assert rel.max() <= 2e-5
+        if (~big).any():
+            assert d[~big].max() <= 2e-8 * top
+
+
 def test_maximum_size_periodic_copies(ora):
     """The largest grid a context takes, near its 2^31 - 1 node limit: 4096 x 4096
     x 127 in float32 mixed (2.13e9 nodes), built as 64 x 64 copies of a 64 x 64 x
