@@ -1,23 +1,32 @@
 """Benchmark of the wall-modeled IBM stage on one MI355X.
 
-One step = one stage pass over the whole grid: ibm_wall_stress (band wall
-model + solid zeroing + band statistics) followed by ibm_apply (stress
-divergence + in-body forcing + drag), on the axisymmetric cos^2 hill
+One step = one stage pass over the whole grid through ibm_stage: the wall
+stress (band wall model + solid zeroing + band statistics) and the dense
+pass (stress divergence + in-body forcing + drag), on the axisymmetric cos^2 hill
 512 x 256 x 256 (H = 32, L = 80 cells, z0 = 2e-4 H), float32 storage in the
 mixed-precision mode.  Inputs are generated (seeded, synthetic), copied to
 HBM and the geometry prepared before the timed region.
 
 Printed: one JSON line.  ``value`` is grid points per second of the stage
 (nx*ny*nz*steps / time of ``steps`` back-to-back passes between two HIP
-events).  ``roofline`` is the dense kernel (ibm_apply): algorithmic bytes per
+events).  ``stage`` gives the whole pass's fraction of the HBM roofline on
+its algorithmic bytes (dense pass, solid zeroing, band records, one read of
+every velocity node the samples touch) and the time of the same pass as two
+calls (ibm_wall_stress, ibm_apply).  ``roofline`` is the dense kernel (ibm_apply): algorithmic bytes per
 launch divided by its mean launch duration, from HIP events on the kernel's
 stream around ``steps`` back-to-back launches of it in the same run.  ``fp64_plain`` repeats the measurement with float64 storage.
 ``cpu_baseline`` times the FP64 CPU oracle (a test checker, never tuned) on
 full passes of the same hill.  ``batched`` compares the 64-case ensemble of
 Gaussian-bump terrains advanced by one hipGraph launch of the batched kernels
 (float32, mixed) with the same cases advanced by plain per-case float64 calls.
-``adjoint`` times the forward pass and the hand-written reverse mode on the
-256 x 128 x 128 fractal terrain with a per-node log z0 field (float32 mixed).
+``adjoint`` times the stage, the forward pass and the hand-written reverse
+mode on the 256 x 128 x 128 fractal terrain with a per-node log z0 field
+(float32 mixed), and on a 512 x 256 x 256 fractal whose working set is well
+above the 256 MB Infinity Cache; the reverse mode's roofline is against its
+algorithmic bytes (``adjoint_bytes``).
+``chester`` times Chester et al.'s original method (wall model in its fluid
+band, extrapolation into a solid band, 10 red-black SOR sweeps over the body)
+beside the simplified stage on the same hill.
 ``sgs`` times the Smagorinsky stress with Mason's wall damping that feeds
 the stage (ibm_sgs_stress, float32 on the same hill: its roofline against
 44 algorithmic bytes per node) and the three calls in a row (SGS stress, wall
@@ -86,6 +95,54 @@ def apply_bytes(wl, mask, s):
     return dense + flags + forcing
 
 
+def gathered_nodes(ctx, wl):
+    """Distinct velocity nodes the band records' trilinear samples touch:
+    (uv-grid nodes, read for u and v; w-grid nodes, read for w).  The sample
+    point of a record at node x is x + (phi_c - phi) n (the exported unit
+    normal); index coordinates periodic in x and y, vertical clamped."""
+    import numpy as np
+    g = wl.grid
+    touched = [set(), set()]
+    uvn, wn = [], []
+    for grid, phi, zoff in ((0, wl.phi_uv, 0.5), (1, wl.phi_w, 0.0)):
+        idx, nrm = ctx.band(grid)
+        if idx.size == 0:
+            continue
+        k, j, i = np.unravel_index(idx.astype(np.int64), g.shape)
+        ph = np.asarray(phi, np.float64).ravel()[idx]
+        shift = wl.phi_c - ph
+        px = i * g.dx + shift * nrm[:, 0]
+        py = j * g.dy + shift * nrm[:, 1]
+        pz = (k + zoff) * g.dz + shift * nrm[:, 2]
+        for kind, out in ((0, uvn), (1, wn)):
+            zi = np.clip(pz / g.dz - (0.5 if kind == 0 else 0.0), 0, g.nz - 1)
+            i0 = np.floor(px / g.dx).astype(np.int64)
+            j0 = np.floor(py / g.dy).astype(np.int64)
+            k0 = np.floor(zi).astype(np.int64)
+            for di in (0, 1):
+                for dj in (0, 1):
+                    for dk in (0, 1):
+                        kk = np.minimum(k0 + dk, g.nz - 1)
+                        out.append((kk * g.ny + (j0 + dj) % g.ny) * g.nx + (i0 + di) % g.nx)
+    n_uv = int(np.unique(np.concatenate(uvn)).size) if uvn else 0
+    n_w = int(np.unique(np.concatenate(wn)).size) if wn else 0
+    return n_uv, n_w
+
+
+def stage_bytes(wl, mask, s, gathered):
+    """Algorithmic HBM bytes of one whole stage pass: the dense pass
+    (``apply_bytes``), the solid zeroing, the band records' minimum (index,
+    normal, phi) and stress writes, and one read of every velocity node the
+    samples touch (u and v on the uv grid, w on the w grid)."""
+    band_uv = int(((mask & 3) == 1).sum())
+    band_w = int((((mask >> 2) & 3) == 1).sum())
+    solid_uv = int(((mask & 3) == 2).sum())
+    solid_w = int((((mask >> 2) & 3) == 2).sum())
+    return (apply_bytes(wl, mask, s) + solid_uv * 4 * s + solid_w * 2 * s
+            + band_uv * (4 + 4 * s + 4 * s) + band_w * (4 + 4 * s + 2 * s)
+            + s * (2 * gathered[0] + gathered[1]))
+
+
 def run_gpu(wl, dtype, precision, steps, warmup, tile=None):
     import numpy as np
     import torch
@@ -115,11 +172,16 @@ def run_gpu(wl, dtype, precision, steps, warmup, tile=None):
     taus, uss, divs = list(tau), list(ustar), list(div)
 
     def step():
+        ctx.stage(u, v, w, taus, uss, divs, z0=wl.z0, gradp=gp, dt=wl.dt, stats=stats,
+                  drag=drag)
+
+    def two_calls():
         ctx.wall_stress(u, v, w, taus, z0=wl.z0, stats=stats)
         ctx.apply(taus, uss, divs, gradp=gp, dt=wl.dt, drag=drag)
 
     for _ in range(warmup):
         step()
+        two_calls()
     # the timed region: ``steps`` back-to-back steps between two events
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
@@ -149,10 +211,13 @@ def run_gpu(wl, dtype, precision, steps, warmup, tile=None):
 
     ws_ms = each(lambda: ctx.wall_stress(u, v, w, taus, z0=wl.z0, stats=stats))
     ap_ms = each(lambda: ctx.apply(taus, uss, divs, gradp=gp, dt=wl.dt, drag=drag))
+    two_ms = each(two_calls)
     mask = ctx.mask()
     res = dict(ms_per_step=total_ms / steps, wall_s=t_wall, wall_stress_ms=ws_ms, apply_ms=ap_ms,
-               prepare_s=t_prep, tile=ctx.get_tile(), counts=[int(x) for x in ctx.counts()],
-               mask=mask, drag=drag.cpu().tolist(), stats=stats.cpu().tolist())
+               two_calls_ms=two_ms, prepare_s=t_prep, tile=ctx.get_tile(),
+               counts=[int(x) for x in ctx.counts()], mask=mask,
+               gathered=gathered_nodes(ctx, wl), drag=drag.cpu().tolist(),
+               stats=stats.cpu().tolist())
     del ctx, u, v, w, tau, gp, ustar, div
     torch.cuda.empty_cache()
     return res
@@ -249,15 +314,26 @@ def run_ensemble(steps, warmup, ncases=64):
     return res
 
 
-def run_adjoint(steps, warmup):
-    """Forward pass and reverse mode on the fractal terrain (float32, mixed)."""
+def adjoint_bytes(n, s, flags, nrec, gathered):
+    """Algorithmic HBM bytes of one ibm_stage_vjp call (no stress cotangent,
+    a log z0 field): per node g_ustar read and gu, gv, gw, glog_z0 written
+    (7 s) and the forcing flags; per band record its index, normal and phi
+    (4 + 4 s), its log z0 read and glog_z0 written (2 s) and the three
+    divergence cotangents at its node (3 s); one read of every velocity node
+    the samples touch (u, v on the uv grid, w on the w grid)."""
+    return n * 7 * s + flags + nrec * (4 + 4 * s + 2 * s + 3 * s) + s * (2 * gathered[0] + gathered[1])
+
+
+def run_adjoint(steps, warmup, shape=(256, 128, 128)):
+    """The stage (ibm_stage), the autograd forward and the reverse mode on the
+    fractal terrain with a per-node log z0 field (float32, mixed)."""
     import numpy as np
     import torch
 
     import paper_2006_03343_amd as ibm
     from workloads import configs
     dev = torch.device("cuda", 0)
-    wl = configs.fractal().cast(np.float32)
+    wl = configs.fractal(*shape).cast(np.float32)
     g = wl.grid
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     ctx = ibm.Context(g.nx, g.ny, g.nz, dtype=torch.float32, precision="mixed", device=dev)
@@ -269,10 +345,16 @@ def run_adjoint(steps, warmup):
     fwd = lambda: ibm.stage_forward(ctx, u, v, w, tau0, gp, wl.dt, log_z0=lz)
     tau, div, us, drag = fwd()
     bwd = lambda: ctx.vjp(u, v, w, list(div), list(us), [1.0, 0.0, 0.0], log_z0=lz)
+    ts = [t.clone() for t in tau0]
+    ust = [x.clone() for x in (u, v, w)]
+    dv = [torch.empty_like(u) for _ in range(3)]
+    dr = torch.zeros(3, dtype=torch.float64, device=dev)
+    stage = lambda: ctx.stage(u, v, w, ts, ust, dv, log_z0=lz, gradp=gp, dt=wl.dt, drag=dr)
     for _ in range(warmup):
         fwd()
         bwd()
-    e0, e1, e2 = _events(3)
+        stage()
+    e0, e1, e2, e3 = _events(4)
     torch.cuda.synchronize()
     e0.record()
     for _ in range(steps):
@@ -281,11 +363,96 @@ def run_adjoint(steps, warmup):
     for _ in range(steps):
         bwd()
     e2.record()
+    for _ in range(steps):
+        stage()
+    e3.record()
     torch.cuda.synchronize()
     f_ms, b_ms = e0.elapsed_time(e1) / steps, e1.elapsed_time(e2) / steps
+    s_ms = e2.elapsed_time(e3) / steps
+    counts = ctx.counts()
+    nrec = int(counts[1] + counts[4])
+    gathered = gathered_nodes(ctx, wl)
+    flags = g.ny * g.nz * ((g.nx + 15) // 16) * 4
+    nb = adjoint_bytes(g.n, 4, flags, nrec, gathered)
+    gbs = nb / (b_ms * 1e-3) / 1e9
+    del ctx
+    torch.cuda.empty_cache()
     return {"workload": f"fractal {g.nx}x{g.ny}x{g.nz}, per-node log z0, f32 mixed",
-            "forward_ms": f_ms, "backward_ms": b_ms, "backward_points_per_s": g.n / (b_ms * 1e-3),
-            "note": "forward = out-of-place stage pass incl. tensor copies; backward = ibm_stage_vjp"}
+            "band_records": nrec, "stage_ms": s_ms, "forward_ms": f_ms, "backward_ms": b_ms,
+            "backward_over_stage": b_ms / s_ms,
+            "backward_points_per_s": g.n / (b_ms * 1e-3),
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS, "bytes_per_call": nb},
+            "note": "stage = ibm_stage; forward = the autograd op's out-of-place pass incl. "
+                    "tensor copies; backward = ibm_stage_vjp"}
+
+
+def run_chester(wl, steps, warmup, omega=1.5, sweeps=10):
+    """Chester et al.'s original method against the simplified stage on the
+    same hill (float32 mixed): ibm_chester_wall_stress (wall model on its
+    fluid band, extrapolation into the solid band, ``sweeps`` red-black SOR
+    sweeps over the body interior) followed by ibm_apply, against ibm_stage;
+    also with no sweep (steps 1 and 2 alone) and the cost per sweep."""
+    import numpy as np
+    import torch
+
+    import paper_2006_03343_amd as ibm
+    dev = torch.device("cuda", 0)
+    g = wl.grid
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev, torch.float32)
+    ctx = ibm.Context(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, dtype=torch.float32,
+                      precision="mixed", device=dev)
+    pu, pw = T(wl.phi_uv), T(wl.phi_w)
+    ctx.prepare(pu, pw, wl.band_width, wl.phi_c, wl.kappa)
+    ctx.autotune(TUNE_CACHE)
+    t0 = time.time()
+    ctx.chester_prepare(pu, pw)
+    torch.cuda.synchronize()
+    t_prep = time.time() - t0
+    u, v, w = T(wl.u), T(wl.v), T(wl.w)
+    tau = [T(t) for t in wl.tau]
+    gp = [T(t) for t in wl.gradp]
+    ustar = [u.clone(), v.clone(), w.clone()]
+    div = [torch.empty_like(u) for _ in range(3)]
+    stats = torch.zeros(4, dtype=torch.float64, device=dev)
+    drag = torch.zeros(3, dtype=torch.float64, device=dev)
+
+    def chester(n):
+        ctx.chester_wall_stress(u, v, w, tau, omega, n, z0=wl.z0, stats=stats)
+        ctx.apply(tau, ustar, div, gradp=gp, dt=wl.dt, drag=drag)
+
+    def simplified():
+        ctx.stage(u, v, w, tau, ustar, div, z0=wl.z0, gradp=gp, dt=wl.dt, stats=stats,
+                  drag=drag)
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        e0, e1 = _events(2)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    ms_simple = timed(simplified)
+    ms_ch = timed(lambda: chester(sweeps))
+    ms_ch0 = timed(lambda: chester(0))
+    counts = [int(x) for x in ctx.chester_counts()]
+    del ctx, tau, ustar, div
+    torch.cuda.empty_cache()
+    return {"workload": f"hill {g.nx}x{g.ny}x{g.nz}, float32 mixed, omega {omega}",
+            "sweeps": sweeps, "chester_ms": ms_ch, "chester_points_per_s": g.n / (ms_ch * 1e-3),
+            "chester_no_sweep_ms": ms_ch0, "ms_per_sweep": (ms_ch - ms_ch0) / sweeps,
+            "simplified_ms": ms_simple, "chester_over_simplified": ms_ch / ms_simple,
+            "chester_prepare_s": t_prep,
+            "classes_uv": dict(zip(("fluid", "fluid_band", "solid_band", "interior"), counts[:4])),
+            "classes_w": dict(zip(("fluid", "fluid_band", "solid_band", "interior"), counts[4:])),
+            "launches_per_step": {"chester": 4 + 2 * sweeps + 1, "simplified": 3},
+            "note": "chester = ibm_chester_wall_stress + ibm_apply; simplified = ibm_stage; "
+                    "both one GPU, same inputs"}
 
 
 def run_sgs(wl, steps, warmup):
@@ -601,6 +768,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--no-terrains", action="store_true", help="skip the cube and ridge runs")
     ap.add_argument("--no-sgs", action="store_true", help="skip the Smagorinsky stress runs")
+    ap.add_argument("--no-chester", action="store_true",
+                    help="skip Chester et al.'s original method")
     ap.add_argument("--no-spectral", action="store_true", help="skip the pseudo-spectral mode")
     ap.add_argument("--no-projection", action="store_true",
                     help="skip the AB2 update and the pressure projection")
@@ -629,12 +798,15 @@ def main():
     tile = tuple(int(x) for x in args.tile.split(",")) if args.tile else None
 
     r32 = run_gpu(wl, "f32", "mixed", args.steps, args.warmup, tile)
-    log(f"f32 mixed: {r32['ms_per_step']:.4f} ms/step (wall_stress {r32['wall_stress_ms']:.4f}, "
+    log(f"f32 mixed: {r32['ms_per_step']:.4f} ms/step through ibm_stage, "
+        f"{r32['two_calls_ms']:.4f} as two calls (wall_stress {r32['wall_stress_ms']:.4f}, "
         f"apply {r32['apply_ms']:.4f}) tile {r32['tile']}")
     g = wl.grid
     value = g.n / (r32["ms_per_step"] * 1e-3)
     b_apply = apply_bytes(wl, r32["mask"], 4)
     achieved = b_apply / (r32["apply_ms"] * 1e-3) / 1e9
+    b_stage = stage_bytes(wl, r32["mask"], 4, r32["gathered"])
+    stage_gbs = b_stage / (r32["ms_per_step"] * 1e-3) / 1e9
     out = {
         "metric": "IBM stage grid-points/s + % HBM roofline; batched FP32 vs plain FP64, same GPU",
         "value": value,
@@ -657,6 +829,12 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(r32["tile"]),
                      "bytes_per_launch": b_apply, "launch_ms": r32["apply_ms"]},
         "kernels_ms": {"wall_stress": r32["wall_stress_ms"], "apply": r32["apply_ms"]},
+        "stage": {"entry": "ibm_stage (wall stress, dense pass, one launch summing both "
+                           "sets of slots)",
+                  "bytes_per_pass": b_stage, "achieved_GBs": stage_gbs,
+                  "frac": stage_gbs / HBM_PEAK_GBS,
+                  "two_calls_ms_per_step": r32["two_calls_ms"],
+                  "gathered_nodes": list(r32["gathered"])},
         "prepare_s": r32["prepare_s"],
     }
     if not args.no_f64:
@@ -673,7 +851,15 @@ def main():
         log(f"ensemble: {out['batched']['ratio']:.1f}x (f32 batched graph over f64 plain)")
     if not args.no_adjoint:
         out["adjoint"] = run_adjoint(max(5, args.steps // 4), args.warmup)
+        out["adjoint"]["above_mall"] = run_adjoint(max(5, args.steps // 4), args.warmup,
+                                                   (512, 256, 256))
         log(f"adjoint: {out['adjoint']}")
+    if not args.no_chester:
+        out["chester"] = run_chester(wl, args.steps, args.warmup)
+        log(f"chester: {out['chester']['chester_ms']:.4f} ms per step with "
+            f"{out['chester']['sweeps']} sweeps ({out['chester']['ms_per_sweep'] * 1e3:.1f} us "
+            f"per sweep) vs simplified {out['chester']['simplified_ms']:.4f} ms: "
+            f"{out['chester']['chester_over_simplified']:.2f}x")
     if not args.no_sgs:
         out["sgs"] = run_sgs(wl, args.steps, args.warmup)
         log(f"sgs: {out['sgs']['sgs_ms']:.4f} ms ({out['sgs']['sgs_roofline']['frac'] * 100:.1f} % "

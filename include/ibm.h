@@ -119,6 +119,20 @@ int ibm_apply(ibm_ctx* c, const void* const tau[6], void* const ustar[3],
               const void* const gradp[3], double dt, void* const div[3], double* drag_dev,
               void* stream);
 
+/* One stage pass in one call: ibm_wall_stress (§3.3) followed by ibm_apply
+ * (§2.4 divergence, §3.2 eq. u-*-IBM forcing), with the band statistics and
+ * the drag summed by one launch instead of one each.  Arguments, layouts and
+ * results as for those two calls (bit for bit: the same kernels and slot
+ * order); stats_dev (4 doubles) and drag_dev (3 doubles) are each nullable.
+ * tau entries must be distinct and may not alias u, v, w or log_z0; div and
+ * ustar as for ibm_apply.  ustar may be u, v, w themselves (the forcing runs
+ * after the wall stress has read them).  Asynchronous on ``stream`` (three
+ * launches).  Errors: those of ibm_wall_stress and ibm_apply. */
+int ibm_stage(ibm_ctx* c, const void* u, const void* v, const void* w, double z0,
+              const void* log_z0, void* const tau[6], void* const ustar[3],
+              const void* const gradp[3], double dt, void* const div[3], double* stats_dev,
+              double* drag_dev, void* stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): ibm_apply
  * with its drag reduction slots (3 doubles per tile of the dense pass) in a

@@ -215,6 +215,34 @@ class Context:
             check(self._lib.ibm_apply(self._h, ptr_array(taus), ptr_array(us), gp, float(dt),
                                       ptr_array(dv), dp, self._stream()))
 
+    def stage(self, u, v, w, tau, ustar, div, z0=None, log_z0=None, gradp=None, dt=0.01,
+              stats=None, drag=None):
+        """``wall_stress`` then ``apply`` in one call (ibm_stage): one launch
+        fewer, the same results."""
+        if (z0 is None) == (log_z0 is None):
+            raise ValueError("give exactly one of z0 and log_z0")
+        taus = self._fields(tau, "tau", 6)
+        us = self._fields(ustar, "ustar", 3)
+        dv = self._fields(div, "div", 3)
+        gp = None
+        if gradp is not None:
+            gp = ptr_array([self._field(t, f"gradp[{i}]") for i, t in enumerate(gradp)])
+        sp = dp = None
+        if stats is not None:
+            if stats.dtype != torch.float64 or stats.numel() < 4 or stats.device != self.device:
+                raise ValueError("stats must be a float64 device tensor with 4 elements")
+            sp = stats.data_ptr()
+        if drag is not None:
+            if drag.dtype != torch.float64 or drag.numel() < 3 or drag.device != self.device:
+                raise ValueError("drag must be a float64 device tensor with 3 elements")
+            dp = drag.data_ptr()
+        with torch.cuda.device(self.device):
+            check(self._lib.ibm_stage(self._h, self._field(u, "u"), self._field(v, "v"),
+                                      self._field(w, "w"), float(z0 or 0.0),
+                                      self._field(log_z0, "log_z0"), ptr_array(taus),
+                                      ptr_array(us), gp, float(dt), ptr_array(dv), sp, dp,
+                                      self._stream()))
+
     def apply_noalloc(self, tau, ustar, div, gradp=None, dt=0.01, drag=None):
         """``apply`` with its drag slots in the library's static device array
         (ibm_apply_noalloc): allocates nothing; overlapping calls on one GPU race."""

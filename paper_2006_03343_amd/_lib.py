@@ -20,6 +20,7 @@ EXPORTS = ["ibm_create", "ibm_destroy", "ibm_levelset_prepare", "ibm_counts", "i
            "ibm_band_export", "ibm_mask_export", "ibm_wall_stress", "ibm_apply", "ibm_apply_spectral", "ibm_ab2_predict", "ibm_pressure_project",
            "ibm_sgs_stress", "ibm_apply_sgs", "ibm_stage_vjp", "ibm_chester_prepare",
            "ibm_chester_counts", "ibm_chester_wall_stress", "ibm_apply_noalloc",
+           "ibm_stage",
            "ibm_set_tile", "ibm_get_tile", "ibm_last_error", "ibm_autotune", "ibm_batch_create",
            "ibm_batch_destroy", "ibm_batch_prepare", "ibm_batch_bind", "ibm_batch_tune",
            "ibm_batch_run", "ibm_batch_capture", "ibm_batch_launch", "ibm_batch_case"]
@@ -71,6 +72,7 @@ def load():
     L.ibm_apply.argtypes = [vp, vp, vp, vp, c_double, vp, vp, vp]
     L.ibm_apply_spectral.argtypes = [vp, vp, vp, vp, c_double, vp, vp, vp]
     L.ibm_apply_noalloc.argtypes = [vp, vp, vp, vp, c_double, vp, vp, vp]
+    L.ibm_stage.argtypes = [vp, vp, vp, vp, c_double, vp, vp, vp, vp, c_double, vp, vp, vp, vp]
     L.ibm_ab2_predict.argtypes = [vp, vp, vp, vp, c_double, vp, vp]
     L.ibm_pressure_project.argtypes = [vp, vp, c_double, vp, vp, vp]
     L.ibm_sgs_stress.argtypes = [vp, vp, vp, vp, vp, vp, c_double, vp, c_double, c_double, vp, vp]

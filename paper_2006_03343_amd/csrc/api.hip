@@ -330,6 +330,37 @@ int ibm_apply_noalloc(ibm_ctx* c, const void* const tau[6], void* const ustar[3]
     return launch_apply(c, cfg, tau, ustar, gradp, dt, div, drag_dev, (hipStream_t)stream, slots);
 }
 
+int ibm_stage(ibm_ctx* c, const void* u, const void* v, const void* w, double z0,
+              const void* log_z0, void* const tau[6], void* const ustar[3],
+              const void* const gradp[3], double dt, void* const div[3], double* stats_dev,
+              double* drag_dev, void* stream) {
+    g_err[0] = 0;
+    const char* fn = "ibm_stage";
+    int rc = check_ctx(c, true, fn);
+    if (rc) return rc;
+    if ((rc = check_field(c, u, fn, "u")) || (rc = check_field(c, v, fn, "v")) ||
+        (rc = check_field(c, w, fn, "w")))
+        return rc;
+    if (log_z0) {
+        if ((rc = check_field(c, log_z0, fn, "log_z0"))) return rc;
+    } else if (!(z0 > 0.0) || !(z0 < c->p.phi_c)) {
+        return fail(IBM_E_RANGE, "%s: z0 must satisfy 0 < z0 < phi_c (got %g)", fn, z0);
+    }
+    if (stats_dev && ((uintptr_t)stats_dev % 8))
+        return fail(IBM_E_ARG, "%s: stats_dev misaligned", fn);
+    TileCfg cfg;
+    if ((rc = check_apply(c, tau, ustar, gradp, dt, div, drag_dev, fn, &cfg))) return rc;
+    {   // the wall-stress kernel gathers u, v, w and writes tau
+        const void* ins[4] = {u, v, w, log_z0};
+        const void* outs[6] = {tau[0], tau[1], tau[2], tau[3], tau[4], tau[5]};
+        if (aliases(outs, 6, ins, 4))
+            return fail(IBM_E_ARG, "%s: tau entries must be distinct and may not alias u, v, w or log_z0", fn);
+    }
+    DeviceScope dg(c->device);
+    return launch_stage(c, cfg, u, v, w, z0, log_z0, tau, ustar, gradp, dt, div, stats_dev,
+                        drag_dev, (hipStream_t)stream);
+}
+
 int ibm_apply_spectral(ibm_ctx* c, const void* const tau[6], void* const ustar[3],
                        const void* const gradp[3], double dt, void* const div[3],
                        double* drag_dev, void* stream) {

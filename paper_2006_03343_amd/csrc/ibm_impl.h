@@ -176,6 +176,11 @@ int launch_wall_stress(ibm_ctx* c, const void* u, const void* v, const void* w, 
 int launch_apply(ibm_ctx* c, const TileCfg& cfg, const void* const tau[6], void* const ustar[3],
                  const void* const gradp[3], double dt, void* const div[3], double* drag,
                  hipStream_t s, double* partials = nullptr);
+// ibm_wall_stress then ibm_apply, with one launch for both slot sums.
+int launch_stage(ibm_ctx* c, const TileCfg& cfg, const void* u, const void* v, const void* w,
+                 double z0, const void* log_z0, void* const tau[6], void* const ustar[3],
+                 const void* const gradp[3], double dt, void* const div[3], double* stats,
+                 double* drag, hipStream_t s);
 bool tile_supported(const ibm_ctx* c, const TileCfg& cfg);
 TileCfg default_tile(const ibm_ctx* c);
 long apply_tiles(const ibm_ctx* c, const TileCfg& cfg);

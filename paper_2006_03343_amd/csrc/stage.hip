@@ -1,6 +1,8 @@
 // stage.hip -- per-case launches of the stage kernels (device code in
 // kernels.h): the wall-stress pass with its statistics, the dense pass with
-// forcing and drag, and the fixed-order finalize of the reductions.
+// forcing and drag, and the fixed-order finalize of the reductions; and the
+// one-call stage, which runs both passes and sums both sets of slots in one
+// launch.
 #include <algorithm>
 #include <cmath>
 
@@ -54,7 +56,7 @@ __global__ void __launch_bounds__(256) k_apply(ApplyArgs<T> a) {
 
 template <typename T>
 int wall_stress_t(ibm_ctx* c, const T* u, const T* v, const T* w, double z0, const T* log_z0,
-                  void* const tau[6], double* stats, hipStream_t s) {
+                  void* const tau[6], double* stats, hipStream_t s, bool finalize = true) {
     WSArgs<T> a = make_ws_args<T>(c, u, v, w, z0, log_z0, tau, stats);
     if (c->ws_cap < 4L * a.nb_band) return fail(IBM_E_STATE, "wall_stress: reduction slots not sized");
     const unsigned grid = (unsigned)(a.nb_band + c->nzsegs);
@@ -67,11 +69,21 @@ int wall_stress_t(ibm_ctx* c, const T* u, const T* v, const T* w, double z0, con
         hipLaunchKernelGGL((k_wall_stress<T, false, true>), dim3(grid), dim3(kBandBlock), 0, s, a);
     else
         hipLaunchKernelGGL((k_wall_stress<T, false, false>), dim3(grid), dim3(kBandBlock), 0, s, a);
-    if (stats)
+    if (stats && finalize)
         hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, (const double*)a.partials,
                            (long)a.nb_band, 4, 1u << 2, 1.0, stats);
     IBM_HIP(hipGetLastError());
     return IBM_OK;
+}
+
+// The slot sums of one stage pass in one launch: the wall stress's band
+// statistics (4 per band block) and the dense pass's drag (3 per tile).
+__global__ void __launch_bounds__(256) k_finalize_stage(const double* __restrict__ ws, long nws,
+                                                         double* __restrict__ stats,
+                                                         const double* __restrict__ ap, long nap,
+                                                         double dv, double* __restrict__ drag) {
+    if (stats) finalize_slots(ws, nws, 4, 1u << 2, 1.0, stats);
+    if (drag) finalize_slots(ap, nap, 3, 0u, dv, drag);
 }
 
 template <typename T, typename Acc, int VX, int TY>
@@ -106,7 +118,7 @@ bool dispatch_vx(const ApplyArgs<T>& a, int vx, int ty, unsigned grid, unsigned 
 template <typename T>
 int apply_t(ibm_ctx* c, const TileCfg& cfg, const void* const tau[6], void* const ustar[3],
             const void* const gradp[3], double dt, void* const div[3], double* drag,
-            hipStream_t s, double* partials) {
+            hipStream_t s, double* partials, bool finalize = true) {
     ApplyArgs<T> a = make_apply_args<T>(c, cfg, tau, ustar, gradp, dt, div, drag);
     if (partials)
         a.partials = partials;   // the caller's slots, of at least 3 * ntiles doubles
@@ -121,10 +133,33 @@ int apply_t(ibm_ctx* c, const TileCfg& cfg, const void* const tau[6], void* cons
     else
         ok = dispatch_vx<T, float>(a, cfg.vx, cfg.ty, grid, block, s);
     if (!ok) return fail(IBM_E_ARG, "apply: unsupported tile shape vx=%d ty=%d", cfg.vx, cfg.ty);
-    if (drag)
+    if (drag && finalize)
         hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, (const double*)a.partials,
                            a.ntiles, 3, 0u, a.dv, drag);
     IBM_HIP(hipGetLastError());
+    return IBM_OK;
+}
+
+// One stage pass: the wall-stress kernel, the dense pass, and one launch
+// for both slot sums (the same slots and order as the two calls, so the
+// results are theirs bit for bit).
+template <typename T>
+int stage_t(ibm_ctx* c, const TileCfg& cfg, const T* u, const T* v, const T* w, double z0,
+            const T* log_z0, void* const tau[6], void* const ustar[3], const void* const gradp[3],
+            double dt, void* const div[3], double* stats, double* drag, hipStream_t s) {
+    int rc = wall_stress_t<T>(c, u, v, w, z0, log_z0, tau, stats, s, false);
+    if (rc) return rc;
+    rc = apply_t<T>(c, cfg, tau, ustar, gradp, dt, div, drag, s, nullptr, false);
+    if (rc) return rc;
+    if (stats || drag) {
+        const long nws = band_blocks(c);
+        const long nap = apply_tiles(c, cfg);
+        hipLaunchKernelGGL(k_finalize_stage, dim3(1), dim3(256), 0, s,
+                           (const double*)c->ws_partials, nws, stats,
+                           (const double*)c->ap_partials, nap,
+                           c->g.dx * c->g.dy * c->g.dz, drag);
+        IBM_HIP(hipGetLastError());
+    }
     return IBM_OK;
 }
 
@@ -216,6 +251,17 @@ int launch_wall_stress(ibm_ctx* c, const void* u, const void* v, const void* w, 
                                      (const double*)log_z0, tau, stats, s);
     return wall_stress_t<float>(c, (const float*)u, (const float*)v, (const float*)w, z0,
                                 (const float*)log_z0, tau, stats, s);
+}
+
+int launch_stage(ibm_ctx* c, const TileCfg& cfg, const void* u, const void* v, const void* w,
+                 double z0, const void* log_z0, void* const tau[6], void* const ustar[3],
+                 const void* const gradp[3], double dt, void* const div[3], double* stats,
+                 double* drag, hipStream_t s) {
+    if (c->dtype == IBM_F64)
+        return stage_t<double>(c, cfg, (const double*)u, (const double*)v, (const double*)w, z0,
+                               (const double*)log_z0, tau, ustar, gradp, dt, div, stats, drag, s);
+    return stage_t<float>(c, cfg, (const float*)u, (const float*)v, (const float*)w, z0,
+                          (const float*)log_z0, tau, ustar, gradp, dt, div, stats, drag, s);
 }
 
 int launch_apply(ibm_ctx* c, const TileCfg& cfg, const void* const tau[6], void* const ustar[3],
