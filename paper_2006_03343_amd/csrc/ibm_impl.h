@@ -100,6 +100,8 @@ struct AdjointMap {
     int32_t* rec[2] = {nullptr, nullptr};   // record index in [uv records | w records]
     void* wgt[2] = {nullptr, nullptr};      // trilinear weight of the entry's corner (storage type)
     void* rbar = nullptr;        // per-record sample-velocity cotangents, 3 x (nuv + nw)
+    long nb = 0;                 // band nodes (a uv record, a w record or both)
+    int32_t* brec = nullptr;     // per band node, ascending: [uv record or -1, w record or -1]
 };
 
 // Set-up of Chester et al.'s original method (built by ibm_chester_prepare).

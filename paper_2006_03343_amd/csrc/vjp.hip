@@ -7,7 +7,9 @@
 //   ustar   = u where phi > 0, (3 dt / 2) grad p elsewhere.
 // Reverse:
 //   1. dense pass:  gu = g_ustar [phi_uv > 0] (and v, w alike); glog_z0 = 0;
-//   2. band pass:   per band record, the stress cotangent at its node,
+//   2. band pass:   one thread per band node (its uv record, then its w
+//                   record, so their log z0 cotangents add in a fixed order);
+//                   per record the stress cotangent at its node,
 //                   g_tau + (D^T gbar)(q) with gbar = g_div + dV g_drag [phi > 0],
 //                   evaluated from the transposed stencil at that node only;
 //                   then back through tau = -c |U_r| (U_r n^T + n U_r^T):
@@ -17,10 +19,13 @@
 //                   weighted record cotangents, reading a transposed map sorted
 //                   by node (built once per geometry, with each entry's
 //                   trilinear weight) -- no atomics, so the result is
-//                   deterministic.
+//                   deterministic; one launch for both node sets (uv-grid
+//                   nodes first, then w-grid nodes), blocks of consecutive
+//                   nodes staging their entries through LDS.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <climits>
 #include <numeric>
 #include <vector>
 
@@ -52,9 +57,10 @@ __global__ void k_vjp_dense(const T* __restrict__ g0, const T* __restrict__ g1,
 
 template <typename T>
 struct BandArgs {
-    RecView<T> rec;
-    int kind;
-    long roff;                 // index of this kind's first record in the concatenated list
+    RecView<T> recs[2];        // uv records, w records
+    const int32_t* brec;       // per band node: [uv record or -1, w record or -1]
+    long nb;                   // band nodes
+    long nuv;                  // uv records (the w records follow them in rbar)
     const T *u, *v, *w, *log_z0;
     const T* g_tau[6];
     const T* g_div[3];
@@ -97,11 +103,11 @@ __device__ inline T trilerp(const T* __restrict__ f, int c00, int c10, int c01, 
     return (a0 * gy + b0 * fy) * gz + (a1 * gy + b1 * fy) * fz;
 }
 
+// The reverse of one band record of node set ``kind``: writes its sample
+// cotangent into rbar and returns its log z0 cotangent (0 without a field).
 template <typename T, bool HAS_LZ>
-__global__ void k_vjp_band(BandArgs<T> a) {
-    const long r = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    const RecView<T>& R = a.rec;
-    if (r >= R.n) return;
+__device__ inline T band_record(const BandArgs<T>& a, int kind, long r) {
+    const RecView<T>& R = a.recs[kind];
     const int q = R.q[r];
     const int k = q / (int)a.plane;
     const int rem = q - k * (int)a.plane;
@@ -137,7 +143,7 @@ __global__ void k_vjp_band(BandArgs<T> a) {
     }
     // stress cotangent at this node for the components the record stores
     T S, P0, P1, P2;
-    if (a.kind == IBM_GRID_UV) {
+    if (kind == IBM_GRID_UV) {
         const T txx = (a.g_tau[0] ? a.g_tau[0][q] : T(0)) -
                       (gbar(a, 0, ip, j, k) - gbar(a, 0, im, j, k)) * a.cx;
         const T tyy = (a.g_tau[1] ? a.g_tau[1][q] : T(0)) -
@@ -165,74 +171,124 @@ __global__ void k_vjp_band(BandArgs<T> a) {
         P2 = txz * n0 + tyz * n1;
     }
     // tau = -c U M, M = U_r n^T + n U_r^T:  dtau/dU_r,j = -c (U_r,j / U M + U dM/dU_r,j)
-    T b0 = T(0), b1 = T(0), b2 = T(0);
+    T b0 = T(0), b1 = T(0), b2 = T(0), gl = T(0);
     if (U > T(0)) {
         const T sU = S / U;
         b0 = -c * (ur0 * sU + U * P0);
         b1 = -c * (ur1 * sU + U * P1);
         b2 = -c * (ur2 * sU + U * P2);
-        if (HAS_LZ && a.glz) {
+        if (HAS_LZ) {
             const double cbar = -(double)U * (double)S;
-            a.glz[q] += (T)(cbar * 2.0 * a.kappa * a.kappa / (lnr * lnr * lnr));
+            gl = (T)(cbar * 2.0 * a.kappa * a.kappa / (lnr * lnr * lnr));
         }
     }
     // through U_r = (I - n n^T) u_s
     const T bn = b0 * n0 + b1 * n1 + b2 * n2;
-    const long rr = a.roff + r;
+    const long rr = (kind ? a.nuv : 0) + r;
     a.rbar[rr] = b0 - bn * n0;
     a.rbar[a.ntot + rr] = b1 - bn * n1;
     a.rbar[2 * a.ntot + rr] = b2 - bn * n2;
+    return gl;
+}
+
+// One thread per band node: its uv record, then its w record; the log z0
+// cotangent of the node is 0 (the dense pass) + the uv record's + the w
+// record's, in that order.
+template <typename T, bool HAS_LZ>
+__global__ void __launch_bounds__(256) k_vjp_band(BandArgs<T> a) {
+    const long b = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= a.nb) return;
+    const int ruv = a.brec[2 * b], rw = a.brec[2 * b + 1];
+    T gl = T(0);
+    int q = 0;
+    if (ruv >= 0) {
+        gl = gl + band_record<T, HAS_LZ>(a, IBM_GRID_UV, ruv);
+        q = a.recs[0].q[ruv];
+    }
+    if (rw >= 0) {
+        gl = gl + band_record<T, HAS_LZ>(a, IBM_GRID_W, rw);
+        q = a.recs[1].q[rw];
+    }
+    if (HAS_LZ && a.glz) a.glz[q] = gl;
 }
 
 template <typename T>
 struct GatherArgs {
     long ntot;
-    const int32_t *node, *off, *erec;
-    const T* wgt;
-    long m;
-    int zgrid;                 // 0: u, v cotangents (uv grid), 1: w (w grid)
+    const int32_t *node[2], *off[2], *erec[2];
+    const T* wgt[2];
+    long m[2];
+    int nb0;                   // blocks of the uv-grid nodes (u, v cotangents)
     const T* rbar;
-    T* out0;                   // gu (zgrid 0) or gw (zgrid 1)
-    T* out1;                   // gv (zgrid 0) or nullptr
+    T* out0[2];                // gu (uv grid), gw (w grid)
+    T* out1;                   // gv
 };
 
-// One thread per touched node; its entries are taken kB at a time with all
-// their loads issued before the (entry-ordered) sums.
+// 256 consecutive touched nodes per block, the uv-grid nodes' blocks first.
+// Their entries are contiguous in the map: the block stages them kChunk at a
+// time -- each thread loads kPer entries (record, weight) and the record
+// cotangents they point to, all issued before use, and leaves the weighted
+// products in LDS -- then each thread adds its own node's products in entry
+// order.  The entry reads are coalesced across the block instead of strided
+// per node, and every node's sum keeps one fixed order (deterministic).
+constexpr int kGatherBlock = 256;
+constexpr int kGatherPer = 4;
+constexpr int kGatherChunk = kGatherBlock * kGatherPer;
+
 template <typename T>
-__global__ void k_vjp_gather(GatherArgs<T> a) {
-    constexpr int kB = 8;
-    const long m = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= a.m) return;
-    const int e0 = a.off[m], e1 = a.off[m + 1];
-    const T* rb0 = a.rbar + (a.zgrid ? 2 * a.ntot : 0);
-    const T* rb1 = a.rbar + a.ntot;
+__global__ void __launch_bounds__(kGatherBlock) k_vjp_gather(GatherArgs<T> ga) {
+    __shared__ T p0s[kGatherChunk], p1s[kGatherChunk];
+    __shared__ int offs[kGatherBlock + 1];
+    const int zg = (int)blockIdx.x < ga.nb0 ? 0 : 1;
+    const long m0 = (long)((int)blockIdx.x - (zg ? ga.nb0 : 0)) * kGatherBlock;
+    const long mcount = min((long)kGatherBlock, ga.m[zg] - m0);
+    const int t = threadIdx.x;
+    const int32_t* __restrict__ off = ga.off[zg];
+    const int32_t* __restrict__ erec = ga.erec[zg];
+    const T* __restrict__ wgt = ga.wgt[zg];
+    const T* __restrict__ rb0 = ga.rbar + (zg ? 2 * ga.ntot : 0);
+    const T* __restrict__ rb1 = ga.rbar + ga.ntot;
+    if (t < mcount) offs[t] = off[m0 + t];
+    if (t == 0) offs[mcount] = off[m0 + mcount];      // the map holds m + 1 offsets
+    __syncthreads();
+    const int e0 = offs[0], e1 = offs[mcount];
+    const int my0 = t < mcount ? offs[t] : e1, my1 = t < mcount ? offs[t + 1] : e1;
     T s0 = T(0), s1 = T(0);
-    for (int e = e0; e < e1; e += kB) {
-        int rr[kB];
-        T wg[kB], b0[kB], b1[kB];
+    for (int cb = e0; cb < e1; cb += kGatherChunk) {
+        const int ce = min(cb + kGatherChunk, e1);
+        int rr[kGatherPer];
+        T wg[kGatherPer], b0[kGatherPer], b1[kGatherPer];
 #pragma unroll
-        for (int u = 0; u < kB; ++u) {
-            const bool in = e + u < e1;
-            rr[u] = in ? a.erec[e + u] : 0;
-            wg[u] = in ? a.wgt[e + u] : T(0);
+        for (int u = 0; u < kGatherPer; ++u) {
+            const int e = cb + t + u * kGatherBlock;
+            rr[u] = e < ce ? erec[e] : 0;
+            wg[u] = e < ce ? wgt[e] : T(0);
         }
 #pragma unroll
-        for (int u = 0; u < kB; ++u) {
-            const bool in = e + u < e1;
-            b0[u] = in ? rb0[rr[u]] : T(0);
-            b1[u] = (in && a.zgrid == 0) ? rb1[rr[u]] : T(0);
+        for (int u = 0; u < kGatherPer; ++u) {
+            const int e = cb + t + u * kGatherBlock;
+            b0[u] = e < ce ? rb0[rr[u]] : T(0);
+            b1[u] = (e < ce && zg == 0) ? rb1[rr[u]] : T(0);
         }
 #pragma unroll
-        for (int u = 0; u < kB; ++u) {
-            if (e + u < e1) {
-                s0 += wg[u] * b0[u];
-                s1 += wg[u] * b1[u];
-            }
+        for (int u = 0; u < kGatherPer; ++u) {
+            const int i = t + u * kGatherBlock;
+            p0s[i] = wg[u] * b0[u];
+            p1s[i] = wg[u] * b1[u];
         }
+        __syncthreads();
+        const int lo = max(my0, cb), hi = min(my1, ce);
+        for (int e = lo; e < hi; ++e) {
+            s0 += p0s[e - cb];
+            s1 += p1s[e - cb];
+        }
+        __syncthreads();   // the next chunk overwrites the products
     }
-    const long node = a.node[m];
-    a.out0[node] += s0;
-    if (a.out1) a.out1[node] += s1;
+    if (t < mcount) {
+        const long node = ga.node[zg][m0 + t];
+        ga.out0[zg][node] += s0;
+        if (zg == 0) ga.out1[node] += s1;
+    }
 }
 
 // Transposed stencil map: for each node set, the (record, corner) pairs that
@@ -303,6 +359,28 @@ int build_map(ibm_ctx* c) {
         }
     }
     IBM_HIP(hipMalloc(&A.rbar, sizeof(T) * 3 * (size_t)std::max<long>(ntot, 1)));
+    // band nodes in ascending order with their uv and w records
+    std::vector<int32_t> qs[2];
+    for (int kind = 0; kind < 2; ++kind) {
+        qs[kind].resize(c->rec[kind].n);
+        if (c->rec[kind].n)
+            IBM_HIP(hipMemcpy(qs[kind].data(), c->rec[kind].q, 4 * c->rec[kind].n,
+                              hipMemcpyDeviceToHost));
+    }
+    std::vector<int32_t> brec;
+    brec.reserve(2 * (size_t)ntot);
+    size_t iu = 0, iw = 0;
+    while (iu < qs[0].size() || iw < qs[1].size()) {
+        const int64_t qu = iu < qs[0].size() ? qs[0][iu] : INT64_MAX;
+        const int64_t qw = iw < qs[1].size() ? qs[1][iw] : INT64_MAX;
+        const int64_t q = std::min(qu, qw);
+        brec.push_back(qu == q ? (int32_t)iu++ : -1);
+        brec.push_back(qw == q ? (int32_t)iw++ : -1);
+    }
+    A.nb = (long)brec.size() / 2;
+    IBM_HIP(hipMalloc(&A.brec, 4 * std::max<size_t>(brec.size(), 2)));
+    if (!brec.empty())
+        IBM_HIP(hipMemcpy(A.brec, brec.data(), 4 * brec.size(), hipMemcpyHostToDevice));
     A.built = true;
     return IBM_OK;
 }
@@ -352,31 +430,32 @@ int vjp_t(ibm_ctx* c, const T* u, const T* v, const T* w, double z0, const T* lo
     a.rbar = (T*)c->adj.rbar;
     a.ntot = ntot;
     a.glz = glz;
-    for (int kind = 0; kind < 2; ++kind) {   // uv first, then w: log z0 adds in a fixed order
-        a.rec = view<T>(c->rec[kind]);
-        a.kind = kind;
-        a.roff = kind ? nuv : 0;
-        if (a.rec.n == 0) continue;
+    a.recs[0] = view<T>(c->rec[0]);
+    a.recs[1] = view<T>(c->rec[1]);
+    a.brec = c->adj.brec;
+    a.nb = c->adj.nb;
+    a.nuv = nuv;
+    if (a.nb) {
         if (log_z0)
-            hipLaunchKernelGGL((k_vjp_band<T, true>), dim3(nblk(a.rec.n, 256)), dim3(256), 0, s, a);
+            hipLaunchKernelGGL((k_vjp_band<T, true>), dim3(nblk(a.nb, 256)), dim3(256), 0, s, a);
         else
-            hipLaunchKernelGGL((k_vjp_band<T, false>), dim3(nblk(a.rec.n, 256)), dim3(256), 0, s, a);
+            hipLaunchKernelGGL((k_vjp_band<T, false>), dim3(nblk(a.nb, 256)), dim3(256), 0, s, a);
     }
     GatherArgs<T> ga;
     ga.ntot = ntot;
     ga.rbar = (const T*)c->adj.rbar;
     for (int zg = 0; zg < 2; ++zg) {
-        ga.node = c->adj.node[zg];
-        ga.off = c->adj.off[zg];
-        ga.erec = c->adj.rec[zg];
-        ga.wgt = (const T*)c->adj.wgt[zg];
-        ga.m = c->adj.m[zg];
-        ga.zgrid = zg;
-        ga.out0 = zg ? gw : gu;
-        ga.out1 = zg ? nullptr : gv;
-        if (ga.m == 0) continue;
-        hipLaunchKernelGGL(k_vjp_gather<T>, dim3(nblk(ga.m, 256)), dim3(256), 0, s, ga);
+        ga.node[zg] = c->adj.node[zg];
+        ga.off[zg] = c->adj.off[zg];
+        ga.erec[zg] = c->adj.rec[zg];
+        ga.wgt[zg] = (const T*)c->adj.wgt[zg];
+        ga.m[zg] = c->adj.m[zg];
+        ga.out0[zg] = zg ? gw : gu;
     }
+    ga.out1 = gv;
+    ga.nb0 = (int)nblk(ga.m[0], kGatherBlock);
+    const unsigned gg = (unsigned)(ga.nb0 + nblk(ga.m[1], kGatherBlock));
+    if (gg) hipLaunchKernelGGL(k_vjp_gather<T>, dim3(gg), dim3(kGatherBlock), 0, s, ga);
     IBM_HIP(hipGetLastError());
     return IBM_OK;
 }
@@ -392,6 +471,7 @@ void free_adjoint(ibm_ctx* c) {
         (void)hipFree(A.wgt[zg]);
     }
     (void)hipFree(A.rbar);
+    (void)hipFree(A.brec);
     A = AdjointMap();
 }
 
