@@ -2,22 +2,26 @@
 // the tile autotuner.
 //
 // Each case of a batch is an ordinary context (prepare.hip builds its masks,
-// band records and segment lists).  One step of the whole ensemble is three persistent
+// band records and segment lists).  One step of the whole ensemble is three
 // kernels -- wall stress, dense pass, finalize -- captured once in a hipGraph
 // and replayed with a single hipGraphLaunch:
-//   * the grid of each kernel is sized to what the GPU holds at once, and its
-//     waves (dense pass) or blocks (wall stress) walk a work list that spans
-//     every case: (case, band block | solid segment) for the wall stress and
-//     (case, quarter of a forcing segment | wave-tile) for the dense pass;
-//   * the work list is cut into 8 contiguous slices of equal estimated cost,
-//     one per XCD (block b runs on XCD b % 8), so each XCD's L2 sees
-//     neighbouring tiles of the same case;
+//   * the wall stress and the dense pass take one work item per block or per
+//     wave from lists that span every case: (case, band block | solid segment)
+//     for the wall stress, and for the dense pass the wave-tiles of every case
+//     followed by the quarters of the forcing segments;
+//   * each list of equal-role items is cut into 8 contiguous slices of equal
+//     estimated cost, one per XCD (block b runs on XCD b % 8, and the blocks of
+//     one XCD are dispatched in order), so each XCD's L2 sees neighbouring
+//     tiles of one case at the same time and the hardware dispatcher balances
+//     the waves; the forcing blocks come after every tile block, as in the
+//     per-case dense pass;
 //   * items call the same device functions as the per-case kernels (kernels.h)
 //     with the case's own arguments and tile shape, so every value of a case is
 //     bit-identical to a plain call with the same tile shape.
 // No memset and no host synchronisation is inside the graph.
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <fstream>
@@ -54,12 +58,15 @@ struct ibm_batch {
     void* ap_tab = nullptr;        // ApplyArgs<T>[ncases]
     int* ws_flags = nullptr;       // per case: bit 0 mixed, bit 1 per-node log z0
     int2* ws_items = nullptr;
-    int4* ap_items = nullptr;
+    int4* ap_items = nullptr;      // wave-tiles of every case, then forcing quarters
     ibm::FinJob* fin = nullptr;
-    long nws = 0, nap = 0;
+    long nws = 0, nap = 0;         // items of the wall stress; of the dense pass
+    long ntiles = 0;               // the dense pass's tile items (the first ntiles of ap_items)
     int nfin = 0;
-    ibm::Split ws_split{}, ap_split{};
+    ibm::Split ws_split{}, ap_split{};   // XCD slices of the wall-stress items, of the tiles
     unsigned ws_grid = 0, ap_grid = 0;
+    int ws_per_xcd = 0, ap_per_xcd = 0;  // blocks per XCD for the longest slice
+    int ap_fblocks = 0;                  // forcing blocks after the tile blocks
     double* drag = nullptr;        // [ncases][3], for cases bound without drag_dev
     double* stats = nullptr;       // [ncases][4], for cases bound without stats_dev
     hipGraph_t graph = nullptr;
@@ -69,60 +76,69 @@ struct ibm_batch {
 namespace ibm {
 namespace {
 
+// One block per item: block b runs on XCD b % 8 and takes item i = b / 8 of
+// that XCD's slice.
 template <typename T>
 __global__ void __launch_bounds__(kBandBlock) k_batch_ws(const WSArgs<T>* __restrict__ tab,
                                                          const int* __restrict__ flags,
                                                          const int2* __restrict__ items, Split sp) {
-    const int x = blockIdx.x & 7, lb = blockIdx.x >> 3, nb = gridDim.x >> 3;
-    for (long it = sp.off[x] + lb; it < sp.off[x + 1]; it += nb) {
-        const int2 w = items[it];
-        const int cs = __builtin_amdgcn_readfirstlane(w.x);
-        const int blk = __builtin_amdgcn_readfirstlane(w.y);
-        const WSArgs<T>& a = tab[cs];
-        switch (flags[cs]) {
-            case 0: ws_block<T, false, false>(a, blk); break;
-            case 1: ws_block<T, true, false>(a, blk); break;
-            case 2: ws_block<T, false, true>(a, blk); break;
-            default: ws_block<T, true, true>(a, blk); break;
-        }
+    const int x = blockIdx.x & 7;
+    const long it = sp.off[x] + (blockIdx.x >> 3);
+    if (it >= sp.off[x + 1]) return;
+    const int2 w = items[it];
+    const int cs = __builtin_amdgcn_readfirstlane(w.x);
+    const int blk = __builtin_amdgcn_readfirstlane(w.y);
+    const WSArgs<T>& a = tab[cs];
+    switch (flags[cs]) {
+        case 0: ws_block<T, false, false>(a, blk); break;
+        case 1: ws_block<T, true, false>(a, blk); break;
+        case 2: ws_block<T, false, true>(a, blk); break;
+        default: ws_block<T, true, true>(a, blk); break;
     }
 }
 
+// The first 8 * per_xcd blocks own wave-tiles, one per wave: block b runs on
+// XCD b % 8 and takes tiles 4 (b / 8) .. 4 (b / 8) + 3 of that XCD's slice.
+// The blocks after them force quarters of the forcing segments, one per wave.
 template <typename T, typename Acc>
 __global__ void __launch_bounds__(256) k_batch_apply(const ApplyArgs<T>* __restrict__ tab,
-                                                     const int4* __restrict__ items, Split sp) {
+                                                     const int4* __restrict__ items, Split sp,
+                                                     int per_xcd, long nitems, int nfblocks) {
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int wpb = blockDim.x >> 6;
-    const int x = blockIdx.x & 7, lb = blockIdx.x >> 3, nb = gridDim.x >> 3;
-    const long nslot = (long)nb * wpb;
-    for (long it = sp.off[x] + (long)lb * wpb + wv; it < sp.off[x + 1]; it += nslot) {
-        const int4 w = items[it];
-        const int cs = __builtin_amdgcn_readfirstlane(w.x);
-        const int kind = __builtin_amdgcn_readfirstlane(w.y);
-        const int idx = __builtin_amdgcn_readfirstlane(w.z);
-        const int shape = __builtin_amdgcn_readfirstlane(w.w);
-        const ApplyArgs<T>& a = tab[cs];
-        if (kind == 0) {
-            // one quarter of a forcing segment per wave
+    const int ntb = 8 * per_xcd;
+    if ((int)blockIdx.x >= ntb) {
+        for (long it = sp.off[8] + 4L * (blockIdx.x - ntb) + wv; it < nitems; it += 4L * nfblocks) {
+            const int4 w = items[it];
+            const int cs = __builtin_amdgcn_readfirstlane(w.x);
+            const int idx = __builtin_amdgcn_readfirstlane(w.z);
+            const ApplyArgs<T>& a = tab[cs];
             const Seg sg = a.fsegs[idx >> 2];
             const int off = (idx & 3) * (kSeg / 4);
             force_seg<T>(a, Seg{sg.q + off, min(kSeg / 4, sg.len - off), 0, 0}, lane, 64);
-            continue;
         }
-        switch (shape) {
-            case 11: apply_tile<T, Acc, 1, 1>(a, idx, lane); break;
-            case 12: apply_tile<T, Acc, 1, 2>(a, idx, lane); break;
-            case 21: apply_tile<T, Acc, 2, 1>(a, idx, lane); break;
-            case 22: apply_tile<T, Acc, 2, 2>(a, idx, lane); break;
-            case 41:
-                if constexpr (sizeof(T) == 4) apply_tile<T, Acc, 4, 1>(a, idx, lane);
-                break;
-            case 42:
-                if constexpr (sizeof(T) == 4) apply_tile<T, Acc, 4, 2>(a, idx, lane);
-                break;
-            default: break;
-        }
+        return;
+    }
+    const int x = blockIdx.x & 7;
+    const long it = sp.off[x] + 4L * (blockIdx.x >> 3) + wv;
+    if (it >= sp.off[x + 1]) return;
+    const int4 w = items[it];
+    const int cs = __builtin_amdgcn_readfirstlane(w.x);
+    const int idx = __builtin_amdgcn_readfirstlane(w.z);
+    const int shape = __builtin_amdgcn_readfirstlane(w.w);
+    const ApplyArgs<T>& a = tab[cs];
+    switch (shape) {
+        case 11: apply_tile<T, Acc, 1, 1>(a, idx, lane); break;
+        case 12: apply_tile<T, Acc, 1, 2>(a, idx, lane); break;
+        case 21: apply_tile<T, Acc, 2, 1>(a, idx, lane); break;
+        case 22: apply_tile<T, Acc, 2, 2>(a, idx, lane); break;
+        case 41:
+            if constexpr (sizeof(T) == 4) apply_tile<T, Acc, 4, 1>(a, idx, lane);
+            break;
+        case 42:
+            if constexpr (sizeof(T) == 4) apply_tile<T, Acc, 4, 2>(a, idx, lane);
+            break;
+        default: break;
     }
 }
 
@@ -169,16 +185,12 @@ void free_tables(ibm_batch* b) {
     b->tables = false;
 }
 
-int occupancy_grid(const void* kernel, int block, long items, int item_per_block, unsigned* grid) {
-    int dev = 0, ncu = 0, occ = 0;
-    IBM_HIP(hipGetDevice(&dev));
-    IBM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    IBM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, block, 0));
-    long want = std::max<long>(1, (items + item_per_block - 1) / item_per_block);
-    long cap = (long)std::max(1, ncu) * std::max(1, occ);
-    long g = std::min(want, cap);
-    *grid = (unsigned)((g + 7) / 8 * 8);
-    return IBM_OK;
+// Blocks per XCD for the longest slice when each block takes ``per_block``
+// items of its XCD's slice.
+int slice_blocks(const Split& sp, int per_block) {
+    long m = 0;
+    for (int x = 0; x < 8; ++x) m = std::max(m, sp.off[x + 1] - sp.off[x]);
+    return (int)((m + per_block - 1) / per_block);
 }
 
 template <typename T>
@@ -189,7 +201,7 @@ int build_tables(ibm_batch* b) {
     std::vector<ApplyArgs<T>> ap(n);
     std::vector<int> flags(n);
     std::vector<int2> wsi;
-    std::vector<int4> api;
+    std::vector<int4> api, fpi;   // tile items; forcing items (appended after the tiles)
     std::vector<double> wsc, apc;
     std::vector<FinJob> fin;
     for (int cs = 0; cs < n; ++cs) {
@@ -222,12 +234,10 @@ int build_tables(ibm_batch* b) {
         if (c->nfsegs)
             IBM_HIP(hipMemcpy(fs.data(), c->fsegs, sizeof(Seg) * c->nfsegs, hipMemcpyDeviceToHost));
         for (long k = 0; k < c->nfsegs; ++k)
-            for (int part = 0; part < 4 && part * (kSeg / 4) < fs[k].len; ++part) {
-                api.push_back(make_int4(cs, 0, (int)(4 * k + part), 0));
-                apc.push_back(0.5 * (kSeg / 4));
-            }
+            for (int part = 0; part < 4 && part * (kSeg / 4) < fs[k].len; ++part)
+                fpi.push_back(make_int4(cs, 0, (int)(4 * k + part), 0));
         const int shape = 10 * c->cfg.vx + c->cfg.ty;
-        const double tile_pts = 64.0 * c->cfg.vx * c->cfg.ty * c->cfg.kz;
+        const double tile_pts = 64.0 * c->cfg.vx * c->cfg.ty * std::min(c->cfg.kz, c->g.nz);
         for (long t = 0; t < ap[cs].ntiles; ++t) {
             api.push_back(make_int4(cs, 1, (int)t, shape));
             apc.push_back(tile_pts);
@@ -236,6 +246,8 @@ int build_tables(ibm_batch* b) {
         fin.push_back(FinJob{c->ap_partials, ap[cs].ntiles, 3, 0u, ap[cs].dv, dr});
     }
     b->nws = (long)wsi.size();
+    b->ntiles = (long)api.size();
+    api.insert(api.end(), fpi.begin(), fpi.end());
     b->nap = (long)api.size();
     b->nfin = (int)fin.size();
     b->gens.resize(n);
@@ -256,12 +268,14 @@ int build_tables(ibm_batch* b) {
     if (b->nap)
         IBM_HIP(hipMemcpy(b->ap_items, api.data(), sizeof(int4) * b->nap, hipMemcpyHostToDevice));
     IBM_HIP(hipMemcpy(b->fin, fin.data(), sizeof(FinJob) * b->nfin, hipMemcpyHostToDevice));
-    int rc = occupancy_grid((const void*)k_batch_ws<T>, kBandBlock, b->nws, 1, &b->ws_grid);
-    if (rc) return rc;
-    const bool dacc = b->precision == IBM_PREC_MIXED || sizeof(T) == 8;
-    const void* ak = dacc ? (const void*)k_batch_apply<T, double> : (const void*)k_batch_apply<T, float>;
-    rc = occupancy_grid(ak, 256, b->nap, 4, &b->ap_grid);
-    if (rc) return rc;
+    b->ws_per_xcd = slice_blocks(b->ws_split, 1);
+    b->ws_grid = (unsigned)(8L * b->ws_per_xcd);
+    b->ap_per_xcd = slice_blocks(b->ap_split, 4);
+    const long nf = b->nap - b->ntiles;
+    b->ap_fblocks = (int)std::min<long>((nf + 3) / 4, 2048);
+    b->ap_grid = (unsigned)(8L * b->ap_per_xcd + b->ap_fblocks);
+    if (8L * b->ap_per_xcd + b->ap_fblocks > INT32_MAX || 8L * b->ws_per_xcd > INT32_MAX)
+        return fail(IBM_E_RANGE, "batch: too many work items for one launch");
     b->tables = true;
     return IBM_OK;
 }
@@ -276,11 +290,11 @@ int enqueue(ibm_batch* b, hipStream_t s) {
         if (b->precision == IBM_PREC_MIXED || sizeof(T) == 8)
             hipLaunchKernelGGL((k_batch_apply<T, double>), dim3(b->ap_grid), dim3(256), 0, s,
                                (const ApplyArgs<T>*)b->ap_tab, (const int4*)b->ap_items,
-                               b->ap_split);
+                               b->ap_split, b->ap_per_xcd, b->nap, b->ap_fblocks);
         else
             hipLaunchKernelGGL((k_batch_apply<T, float>), dim3(b->ap_grid), dim3(256), 0, s,
                                (const ApplyArgs<T>*)b->ap_tab, (const int4*)b->ap_items,
-                               b->ap_split);
+                               b->ap_split, b->ap_per_xcd, b->nap, b->ap_fblocks);
     }
     hipLaunchKernelGGL(k_batch_finalize, dim3(b->nfin), dim3(256), 0, s, (const FinJob*)b->fin);
     IBM_HIP(hipGetLastError());

@@ -153,12 +153,11 @@ struct ExtArgs {
 // Sample of one component at a record's stencil on the node set ``kind``.
 template <typename T>
 __device__ inline T ch_sample(const RecView<T>& R, long r, int kind, const T* f, long plane, int nz) {
-    const long base = R.base[r];
-    const long c00 = base, c10 = base + R.sx[r], c01 = base + R.sy[r], c11 = c10 + R.sy[r];
+    const long c00 = R.base[r], sx = R.sx[r], c01 = c00 + R.sy[r];
     const int k0 = kind == IBM_GRID_UV ? R.ku[r] : R.kw[r];
     const T fz = kind == IBM_GRID_UV ? R.fzu[r] : R.fzw[r];
     const long z0 = k0 * plane, z1 = min(k0 + 1, nz - 1) * plane;
-    return trilerp<T>(f, c00, c10, c01, c11, z0, z1, R.fx[r], R.fy[r], fz);
+    return trilerp_xpair<T>(f, c00, c01, sx, z0, z1, R.fx[r], R.fy[r], fz);
 }
 
 // Step 2, first half: one thread per solid-band record (uv blocks first).

@@ -73,6 +73,43 @@ __device__ inline T trilerp(const T* __restrict__ f, long c00, long c10, long c0
     return lo * gz + hi * fz;
 }
 
+// The x-neighbour pair f[off], f[off + sx] of a sample stencil: one 8-byte
+// (16-byte for double) load where the pair is contiguous (sx = 1), two loads
+// across the periodic seam.  Global loads of several dwords need only 4-byte
+// alignment.
+template <typename T>
+__device__ inline void load_xpair(const T* __restrict__ f, long off, long sx, T& lo, T& hi) {
+    if (sx == 1) {
+        typedef T T2 __attribute__((ext_vector_type(2))) __attribute__((aligned(sizeof(T))));
+        const T2 p = *reinterpret_cast<const T2*>(f + off);
+        lo = p.x;
+        hi = p.y;
+    } else {
+        lo = f[off];
+        hi = f[off + sx];
+    }
+}
+
+// trilerp with the four x pairs loaded by load_xpair (c10 = c00 + sx,
+// c11 = c01 + sx); the same arithmetic in the same order.
+template <typename T>
+__device__ inline T trilerp_xpair(const T* __restrict__ f, long c00, long c01, long sx, long z0,
+                                  long z1, T fx, T fy, T fz) {
+    const T gx = T(1) - fx, gy = T(1) - fy, gz = T(1) - fz;
+    T p00, p10, p01, p11, q00, q10, q01, q11;
+    load_xpair<T>(f, z0 + c00, sx, p00, p10);
+    load_xpair<T>(f, z0 + c01, sx, p01, p11);
+    load_xpair<T>(f, z1 + c00, sx, q00, q10);
+    load_xpair<T>(f, z1 + c01, sx, q01, q11);
+    T a0 = p00 * gx + p10 * fx;
+    T b0 = p01 * gx + p11 * fx;
+    T a1 = q00 * gx + q10 * fx;
+    T b1 = q01 * gx + q11 * fx;
+    T lo = a0 * gy + b0 * fy;
+    T hi = a1 * gy + b1 * fy;
+    return lo * gz + hi * fz;
+}
+
 // Stress of the solid nodes of one segment set to zero (class code 2, or 3:
 // the body interior of Chester et al.'s classes), by ``nthr`` threads
 // numbered ``tid``: thread tid takes nodes q + tid + i * nthr, so each store
@@ -129,17 +166,15 @@ __device__ inline void ws_block(const WSArgs<T>& a, int b) {
     if (r < R.n) {
         const long q = R.q[r];
         const T n0 = R.nx[r], n1 = R.ny[r], n2 = R.nz[r];
-        const long base = R.base[r];
-        const long c00 = base, c10 = base + R.sx[r], c01 = base + R.sy[r];
-        const long c11 = c10 + R.sy[r];
+        const long c00 = R.base[r], sx = R.sx[r], c01 = c00 + R.sy[r];
         const T fx = R.fx[r], fy = R.fy[r];
         const int ku = R.ku[r], kw = R.kw[r];
         const long zu0 = ku * a.plane, zu1 = min(ku + 1, a.nz - 1) * a.plane;
         const long zw0 = kw * a.plane, zw1 = min(kw + 1, a.nz - 1) * a.plane;
         const T fzu = R.fzu[r], fzw = R.fzw[r];
-        const T us = trilerp<T>(a.u, c00, c10, c01, c11, zu0, zu1, fx, fy, fzu);
-        const T vs = trilerp<T>(a.v, c00, c10, c01, c11, zu0, zu1, fx, fy, fzu);
-        const T ws = trilerp<T>(a.w, c00, c10, c01, c11, zw0, zw1, fx, fy, fzw);
+        const T us = trilerp_xpair<T>(a.u, c00, c01, sx, zu0, zu1, fx, fy, fzu);
+        const T vs = trilerp_xpair<T>(a.v, c00, c01, sx, zu0, zu1, fx, fy, fzu);
+        const T ws = trilerp_xpair<T>(a.w, c00, c01, sx, zw0, zw1, fx, fy, fzw);
         const T un = us * n0 + vs * n1 + ws * n2;
         const T ur0 = us - un * n0, ur1 = vs - un * n1, ur2 = ws - un * n2;
         const T U = sqrt(ur0 * ur0 + ur1 * ur1 + ur2 * ur2);

@@ -76,14 +76,18 @@ int wall_stress_t(ibm_ctx* c, const T* u, const T* v, const T* w, double z0, con
     return IBM_OK;
 }
 
-// The slot sums of one stage pass in one launch: the wall stress's band
-// statistics (4 per band block) and the dense pass's drag (3 per tile).
+// The slot sums of one stage pass in one launch of two blocks, which run side
+// by side: block 0 the wall stress's band statistics (4 per band block),
+// block 1 the dense pass's drag (3 per tile).  Each is k_finalize's sum.
 __global__ void __launch_bounds__(256) k_finalize_stage(const double* __restrict__ ws, long nws,
                                                          double* __restrict__ stats,
                                                          const double* __restrict__ ap, long nap,
                                                          double dv, double* __restrict__ drag) {
-    if (stats) finalize_slots(ws, nws, 4, 1u << 2, 1.0, stats);
-    if (drag) finalize_slots(ap, nap, 3, 0u, dv, drag);
+    if (blockIdx.x == 0) {
+        if (stats) finalize_slots(ws, nws, 4, 1u << 2, 1.0, stats);
+    } else if (drag) {
+        finalize_slots(ap, nap, 3, 0u, dv, drag);
+    }
 }
 
 template <typename T, typename Acc, int VX, int TY>
@@ -154,7 +158,7 @@ int stage_t(ibm_ctx* c, const TileCfg& cfg, const T* u, const T* v, const T* w, 
     if (stats || drag) {
         const long nws = band_blocks(c);
         const long nap = apply_tiles(c, cfg);
-        hipLaunchKernelGGL(k_finalize_stage, dim3(1), dim3(256), 0, s,
+        hipLaunchKernelGGL(k_finalize_stage, dim3(2), dim3(256), 0, s,
                            (const double*)c->ws_partials, nws, stats,
                            (const double*)c->ap_partials, nap,
                            c->g.dx * c->g.dy * c->g.dz, drag);

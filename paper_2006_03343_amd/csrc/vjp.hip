@@ -92,14 +92,37 @@ __device__ inline T gbar(const BandArgs<T>& a, int c, int ii, int jj, int k) {
     return g;
 }
 
+// f[off], f[off + sx]: one load of both where they are contiguous (sx = 1),
+// two across the periodic seam (global loads of several dwords need only
+// 4-byte alignment).
 template <typename T>
-__device__ inline T trilerp(const T* __restrict__ f, int c00, int c10, int c01, int c11, int z0,
-                            int z1, T fx, T fy, T fz) {
+__device__ inline void load_xpair(const T* __restrict__ f, int off, int sx, T& lo, T& hi) {
+    if (sx == 1) {
+        typedef T T2 __attribute__((ext_vector_type(2))) __attribute__((aligned(sizeof(T))));
+        const T2 p = *reinterpret_cast<const T2*>(f + off);
+        lo = p.x;
+        hi = p.y;
+    } else {
+        lo = f[off];
+        hi = f[off + sx];
+    }
+}
+
+// Trilinear sample from the stencil's lower corners c00, c01 (the upper
+// ones are c00 + sx, c01 + sx) at plane offsets z0, z1.
+template <typename T>
+__device__ inline T trilerp_xpair(const T* __restrict__ f, int c00, int c01, int sx, int z0,
+                                  int z1, T fx, T fy, T fz) {
     const T gx = T(1) - fx, gy = T(1) - fy, gz = T(1) - fz;
-    T a0 = f[z0 + c00] * gx + f[z0 + c10] * fx;
-    T b0 = f[z0 + c01] * gx + f[z0 + c11] * fx;
-    T a1 = f[z1 + c00] * gx + f[z1 + c10] * fx;
-    T b1 = f[z1 + c01] * gx + f[z1 + c11] * fx;
+    T p00, p10, p01, p11, q00, q10, q01, q11;
+    load_xpair<T>(f, z0 + c00, sx, p00, p10);
+    load_xpair<T>(f, z0 + c01, sx, p01, p11);
+    load_xpair<T>(f, z1 + c00, sx, q00, q10);
+    load_xpair<T>(f, z1 + c01, sx, q01, q11);
+    T a0 = p00 * gx + p10 * fx;
+    T b0 = p01 * gx + p11 * fx;
+    T a1 = q00 * gx + q10 * fx;
+    T b1 = q01 * gx + q11 * fx;
     return (a0 * gy + b0 * fy) * gz + (a1 * gy + b1 * fy) * fz;
 }
 
@@ -116,15 +139,15 @@ __device__ inline T band_record(const BandArgs<T>& a, int kind, long r) {
     const int jm = j == 0 ? a.ny - 1 : j - 1, jp = j + 1 == a.ny ? 0 : j + 1;
     const T n0 = R.nx[r], n1 = R.ny[r], n2 = R.nz[r];
     const int base = R.base[r];
-    const int c00 = base, c10 = base + R.sx[r], c01 = base + R.sy[r], c11 = c10 + R.sy[r];
+    const int sx = R.sx[r], c00 = base, c01 = base + R.sy[r];
     const T fx = R.fx[r], fy = R.fy[r];
     const int ku = R.ku[r], kw = R.kw[r];
     const int pl = (int)a.plane;
     const int zu0 = ku * pl, zu1 = min(ku + 1, a.nz - 1) * pl;
     const int zw0 = kw * pl, zw1 = min(kw + 1, a.nz - 1) * pl;
-    const T us = trilerp<T>(a.u, c00, c10, c01, c11, zu0, zu1, fx, fy, R.fzu[r]);
-    const T vs = trilerp<T>(a.v, c00, c10, c01, c11, zu0, zu1, fx, fy, R.fzu[r]);
-    const T ws = trilerp<T>(a.w, c00, c10, c01, c11, zw0, zw1, fx, fy, R.fzw[r]);
+    const T us = trilerp_xpair<T>(a.u, c00, c01, sx, zu0, zu1, fx, fy, R.fzu[r]);
+    const T vs = trilerp_xpair<T>(a.v, c00, c01, sx, zu0, zu1, fx, fy, R.fzu[r]);
+    const T ws = trilerp_xpair<T>(a.w, c00, c01, sx, zw0, zw1, fx, fy, R.fzw[r]);
     const T un = us * n0 + vs * n1 + ws * n2;
     const T ur0 = us - un * n0, ur1 = vs - un * n1, ur2 = ws - un * n2;
     const T U = sqrt(ur0 * ur0 + ur1 * ur1 + ur2 * ur2);
