@@ -15,13 +15,22 @@
 //          other field), inverse transform; writes div_x = d/dx tau_xx,
 //          div_y = d/dx tau_xy, div_z = d/dx tau_xz; the blocks after the row
 //          blocks force the forcing segments;
-//   k_dy   the same along y, a team per pair of columns of one plane, on
-//          tau_xy + i tau_yy and tau_yz, adding d/dy tau_xy, d/dy tau_yy,
-//          d/dy tau_yz and the staggered vertical differences (d/dz tau_xz,
-//          tau_yz on uv nodes, d/dz tau_zz on w nodes, zero padded), loaded
-//          with the divergence it updates; with the final divergence in hand
-//          it leaves per-block drag partials over the fluid nodes, summed in
-//          slot order by k_spec_finalize.
+//   k_dy   the same along y with one divergence component per block: a team
+//          per pair of columns (c, c+1) of one plane transforms tau_xy,
+//          tau_yy or tau_yz of the two columns as one sequence, adds d/dy of
+//          it and the staggered vertical difference of the component's third
+//          term (d/dz tau_xz, tau_yz on uv nodes, d/dz tau_zz on w nodes, zero
+//          padded), loaded with the divergence it updates; with the final
+//          divergence component in hand it leaves its drag partial over the
+//          fluid nodes, summed in slot order by k_spec_finalize.  The three
+//          components of a plane's column group are consecutive blocks of one
+//          XCD, so the lines they share (tau_yz, the flags) meet in its L2.
+// The y pass with all three sequences in one team needed about 200 registers
+// (two waves per SIMD) and ran at 3.7 TB/s; with one it holds 68 (seven waves)
+// and runs at 4.5.  The x pass, whose three sequences are one stress row
+// each, is faster with all three in one team (225 against 275 us on the
+// 512 x 256 x 256 hill): split, its blocks each stage the twiddles and run
+// two transforms for a third of the data.
 // Transforms: fft.h (register-resident Stockham passes of radix 8, thread
 // teams of n / 8).
 #include <algorithm>
@@ -88,6 +97,9 @@ __device__ inline Two<T> zdiff2(const SpecArgs<T>& a, int c, long q, int k, bool
     const Two<T> nb = k > 0 ? *reinterpret_cast<const Two<T>*>(t + q - a.plane) : z;
     return Two<T>{(here.x - nb.x) * a.cz, (here.y - nb.y) * a.cz};
 }
+
+// Stress component differenced along y for divergence component c.
+__device__ inline int yfield(int c) { return c == 0 ? 3 : c == 1 ? 1 : 5; }   // xy, yy, yz
 
 // Sequences a team transforms at once: all three in float; one after another
 // in double, whose registers would spill otherwise.
@@ -166,153 +178,93 @@ __global__ void __launch_bounds__(256) k_dx(SpecArgs<T> a, ApplyArgs<T> z, unsig
     }
 }
 
-// Drag over the fluid nodes: flag bit 0 marks a forced uv node (div_x,
-// div_y left out), bit 1 a forced w node (div_z left out).
-template <typename Acc, typename T>
-__device__ inline void drag_add(Acc (&acc)[3], uint32_t fb, T d0, T d1, T d2) {
-    if (!(fb & 1u)) {
-        acc[0] += (Acc)d0;
-        acc[1] += (Acc)d1;
-    }
-    if (!(fb & 2u)) acc[2] += (Acc)d2;
-}
-
-// A team per pair of columns (c, c+1) of plane k; the teams of a block are
-// interleaved across lanes (lane = j * teams + team), so a row's columns are
-// read together.  A block's row segment (16 float columns, 64 B) is half a
-// cache line whose other half the next block reads, and the vertical
-// differences read the neighbouring planes' blocks' stresses: with the
-// XCD-aware block order blocks that share lines run on one XCD's L2.  Sequences: tau_xy + i tau_yy of column c, of column c+1,
-// and tau_yz of column c + i tau_yz of column c+1.  PAIR (float, nx even,
-// fields 8-byte aligned): each field's two columns move as one 8-byte access.
-template <typename T, bool ALL, bool PAIR, typename Acc>
+// Logical block lb (XCD-aware): component c = lb % 3 of column group lb / 3
+// = (plane k, group gi); a team per pair of columns (c0, c0+1) of plane k,
+// the teams of a block interleaved across lanes (lane = j * teams + team) so
+// a row's columns are read together; sequence tau(c0) + i tau(c0+1) along y.
+// PAIR (nx even, fields aligned to two elements): the two columns of a field
+// move as one access.
+template <typename T, bool PAIR, typename Acc>
 __global__ void __launch_bounds__(256) k_dy(SpecArgs<T> a, ApplyArgs<T> z) {
-    constexpr int G = kSeqAtOnce<T>;
-    static_assert(!PAIR || G == 3, "column pairs move together only with all sequences at once");
     extern __shared__ unsigned char lds_raw[];
     Cx<T>* xl = reinterpret_cast<Cx<T>*>(lds_raw);
     const int n = a.ny, logn = a.logy;
     const int P = n >= 8 ? n >> 3 : 1, ns = n >= 8 ? 8 : n;
     const int teams = (int)blockDim.x / P;
     const int groups = (a.nx + 2 * teams - 1) / (2 * teams);
-    const int lb = xcd_block(groups * a.nz);
+    const int lb = xcd_block(3 * groups * a.nz);
     if (lb < 0) return;                                   // the whole block
-    Cx<T>* tw = xl + team_lds_elems(blockDim.x) * (ALL ? G : 1);
+    Cx<T>* tw = xl + team_lds_elems(blockDim.x);
     stage_twiddles(tw, a.twy, n);
-    const int k = lb / groups;
-    const int gi = lb - k * groups;
+    const int comp = lb % 3;
+    const int rest = lb / 3;
+    const int k = rest / groups;
+    const int gi = rest - k * groups;
     const int team = (int)threadIdx.x % teams;
     const Team tm = make_team(logn, (int)threadIdx.x / teams, team, teams, true);
     const int c0 = 2 * (gi * teams + team);
-    const bool in[2] = {c0 < a.nx, c0 + 1 < a.nx};
+    const bool in0 = c0 < a.nx, in1 = c0 + 1 < a.nx;
     const long pk = (long)k * a.ny * a.nx;
-    Acc acc[3] = {Acc(0), Acc(0), Acc(0)};     // drag partials over the fluid nodes
-    for (int s0 = 0; s0 < 3; s0 += G) {
-        Cx<T> v[G][8];
+    const T* __restrict__ f = a.tau[yfield(comp)];
+    const int zc = comp == 0 ? 4 : comp == 1 ? 5 : 2;    // tau_xz, tau_yz up; tau_zz down
+    const bool up = comp < 2;
+    const uint32_t fbit = comp < 2 ? 1u : 2u;            // forced uv node / forced w node
+    T* __restrict__ d = a.div[comp];
+    Cx<T> v[1][8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const long q = pk + (long)tm.elem(u) * a.nx + c0;
-#pragma unroll
-            for (int g = 0; g < G; ++g) v[g][u] = Cx<T>{T(0), T(0)};
-            if (u >= ns) continue;
-            if constexpr (PAIR) {
-                if (!in[0]) continue;
-                const Two<T> xy = *reinterpret_cast<const Two<T>*>(a.tau[3] + q);
-                const Two<T> yy = *reinterpret_cast<const Two<T>*>(a.tau[1] + q);
-                const Two<T> yz = *reinterpret_cast<const Two<T>*>(a.tau[5] + q);
-                v[0][u] = Cx<T>{xy.x, yy.x};
-                v[1][u] = Cx<T>{xy.y, yy.y};
-                v[2][u] = Cx<T>{yz.x, yz.y};
-            } else {
-#pragma unroll
-                for (int g = 0; g < G; ++g) {
-                    const int sq = s0 + g;
-                    if (sq < 2) {
-                        if (in[sq]) v[g][u] = Cx<T>{a.tau[3][q + sq], a.tau[1][q + sq]};
-                    } else {
-                        if (in[0]) v[g][u].re = a.tau[5][q];
-                        if (in[1]) v[g][u].im = a.tau[5][q + 1];
-                    }
-                }
-            }
+    for (int u = 0; u < 8; ++u) {
+        v[0][u] = Cx<T>{T(0), T(0)};
+        if (u >= ns || !in0) continue;
+        const long q = pk + (long)tm.elem(u) * a.nx + c0;
+        if constexpr (PAIR) {
+            const Two<T> t = *reinterpret_cast<const Two<T>*>(f + q);
+            v[0][u] = Cx<T>{t.x, t.y};
+        } else {
+            v[0][u] = Cx<T>{f[q], in1 ? f[q + 1] : T(0)};
         }
-        __syncthreads();
-        team_fft<T, G, ALL>(v, tm, xl, tw);
-        derivative<T, G>(v, tm, n, a.ky);
-        team_ifft<T, G, ALL>(v, tm, xl, tw);
+    }
+    __syncthreads();
+    team_fft<T, 1>(v, tm, xl, tw);
+    derivative<T, 1>(v, tm, n, a.ky);
+    team_ifft<T, 1>(v, tm, xl, tw);
+    Acc acc = Acc(0);                                     // drag partial over the fluid nodes
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            if (u >= ns) continue;
-            const int row = tm.elem(u);
-            const long q = pk + (long)row * a.nx + c0;
-            // forcing flags of columns c0, c0 + 1 (one word: c0 is even)
-            const uint32_t fw = (in[0] && s0 + G >= 3) ?
-                z.fmask[((long)k * a.ny + row) * z.wrow + (c0 >> 4)] >> (2 * (c0 & 15)) : 0u;
-            if constexpr (PAIR) {
-                if (!in[0]) continue;
-                Two<T>* d0 = reinterpret_cast<Two<T>*>(a.div[0] + q);
-                Two<T>* d1 = reinterpret_cast<Two<T>*>(a.div[1] + q);
-                Two<T>* d2 = reinterpret_cast<Two<T>*>(a.div[2] + q);
-                const Two<T> o0 = *d0, o1 = *d1, o2 = *d2;
-                // staggered vertical differences, loaded with the divergence
-                const Two<T> zx = zdiff2(a, 4, q, k, true), zy = zdiff2(a, 5, q, k, true),
-                             zz = zdiff2(a, 2, q, k, false);
-                const Two<T> n0{o0.x + v[0][u].re + zx.x, o0.y + v[1][u].re + zx.y};
-                const Two<T> n1{o1.x + v[0][u].im + zy.x, o1.y + v[1][u].im + zy.y};
-                const Two<T> n2{o2.x + v[2][u].re + zz.x, o2.y + v[2][u].im + zz.y};
-                *d0 = n0;
-                *d1 = n1;
-                *d2 = n2;
-                drag_add(acc, fw, n0.x, n1.x, n2.x);
-                if (in[1]) drag_add(acc, fw >> 2, n0.y, n1.y, n2.y);
-            } else {
-#pragma unroll
-                for (int g = 0; g < G; ++g) {
-                    const int sq = s0 + g;
-                    if (sq < 2) {
-                        if (in[sq]) {
-                            a.div[0][q + sq] += v[g][u].re;
-                            a.div[1][q + sq] += v[g][u].im;
-                        }
-                    } else {
-                        if (in[0]) a.div[2][q] += v[g][u].re;
-                        if (in[1]) a.div[2][q + 1] += v[g][u].im;
-                    }
-                }
-                if (s0 + G >= 3) {
-                    // the last group: add the vertical differences, then
-                    // every component of both columns is final
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        if (!in[h]) continue;
-                        const long qh = q + h;
-                        const T d0 = a.div[0][qh] + zdiff(a, 4, qh, k, true);
-                        const T d1 = a.div[1][qh] + zdiff(a, 5, qh, k, true);
-                        const T d2 = a.div[2][qh] + zdiff(a, 2, qh, k, false);
-                        a.div[0][qh] = d0;
-                        a.div[1][qh] = d1;
-                        a.div[2][qh] = d2;
-                        drag_add(acc, fw >> (2 * h), d0, d1, d2);
-                    }
-                }
+    for (int u = 0; u < 8; ++u) {
+        if (u >= ns || !in0) continue;
+        const int row = tm.elem(u);
+        const long q = pk + (long)row * a.nx + c0;
+        // forcing flags of columns c0, c0 + 1 (one word: c0 is even)
+        const uint32_t fw = z.fmask[((long)k * a.ny + row) * z.wrow + (c0 >> 4)] >> (2 * (c0 & 15));
+        if constexpr (PAIR) {
+            Two<T>* dp = reinterpret_cast<Two<T>*>(d + q);
+            const Two<T> o = *dp;
+            // the staggered vertical difference, loaded with the divergence
+            const Two<T> zd = zdiff2(a, zc, q, k, up);
+            const Two<T> r{o.x + v[0][u].re + zd.x, o.y + v[0][u].im + zd.y};
+            *dp = r;
+            if (!(fw & fbit)) acc += (Acc)r.x;
+            if (in1 && !((fw >> 2) & fbit)) acc += (Acc)r.y;
+        } else {
+            const T r0v = d[q] + v[0][u].re + zdiff(a, zc, q, k, up);
+            d[q] = r0v;
+            if (!(fw & fbit)) acc += (Acc)r0v;
+            if (in1) {
+                const T r1v = d[q + 1] + v[0][u].im + zdiff(a, zc, q + 1, k, up);
+                d[q + 1] = r1v;
+                if (!((fw >> 2) & fbit)) acc += (Acc)r1v;
             }
         }
     }
     if (!z.drag) return;
-    __shared__ double red[3][4];
-    const double w0 = wave_sum((double)acc[0]), w1 = wave_sum((double)acc[1]),
-                 w2 = wave_sum((double)acc[2]);
+    __shared__ double red[4];
+    const double ws = wave_sum((double)acc);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (lane == 0) {
-        red[0][wv] = w0;
-        red[1][wv] = w1;
-        red[2][wv] = w2;
-    }
+    if (lane == 0) red[wv] = ws;
     __syncthreads();
-    if (threadIdx.x < 3) {
+    if (threadIdx.x == 0) {
         double r = 0.0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += red[threadIdx.x][w];
-        z.partials[3L * lb + threadIdx.x] = r;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += red[w];
+        z.partials[3L * rest + comp] = r;     // slot of (plane, group), component comp
     }
 }
 
@@ -372,8 +324,9 @@ int spectral_t(ibm_ctx* c, const void* const tau[6], void* const ustar[3],
     ApplyArgs<T> z = make_apply_args<T>(c, c->cfg, tau, ustar, gradp, dt, div, drag);
     const int ty = 256 / (ny >= 8 ? ny / 8 : 1);
     const int groups = (nx + 2 * ty - 1) / (2 * ty);
-    const long nyb = (long)groups * nz;                     // y-pass blocks = drag slots
-    if (c->ap_cap < 3L * nyb) return fail(IBM_E_STATE, "apply_spectral: reduction slots not sized");
+    const long nsl = (long)groups * nz;                     // drag slots: one per column group
+    const long nyb = 3 * nsl;                               // y-pass blocks: three per group
+    if (c->ap_cap < 3L * nsl) return fail(IBM_E_STATE, "apply_spectral: reduction slots not sized");
     z.partials = c->ap_partials;
     z.nfblocks = (int)std::min<long>((4 * c->nfsegs + 7) / 8 * 8, 2048);
     const int tx = 256 / (nx >= 8 ? nx / 8 : 1);            // teams per block
@@ -383,23 +336,23 @@ int spectral_t(ibm_ctx* c, const void* const tau[6], void* const ustar[3],
     // slower here (more registers, fewer waves)
     hipLaunchKernelGGL((k_dx<T, false>), dim3(nrb + (unsigned)z.nfblocks), dim3(256),
                        spectral_lds_bytes(c, nx, 1), s, a, z, nrb);
-    bool aligned = sizeof(T) == 4 && nx % 2 == 0;
+    bool aligned = nx % 2 == 0;
     for (int i = 0; i < 6; ++i) aligned = aligned && (uintptr_t)tau[i] % (2 * sizeof(T)) == 0;
     for (int i = 0; i < 3; ++i) aligned = aligned && (uintptr_t)div[i] % (2 * sizeof(T)) == 0;
     const bool wide = c->precision == IBM_PREC_MIXED || sizeof(T) == 8;   // drag in double
     const dim3 gdy((unsigned)(8 * ((nyb + 7) / 8)));     // logical blocks dealt per XCD
     const size_t lds_y = spectral_lds_bytes(c, ny, 1);
     if (aligned && wide)
-        hipLaunchKernelGGL((k_dy<T, false, sizeof(T) == 4, double>), gdy, dim3(256), lds_y, s, a, z);
+        hipLaunchKernelGGL((k_dy<T, true, double>), gdy, dim3(256), lds_y, s, a, z);
     else if (aligned)
-        hipLaunchKernelGGL((k_dy<T, false, sizeof(T) == 4, T>), gdy, dim3(256), lds_y, s, a, z);
+        hipLaunchKernelGGL((k_dy<T, true, T>), gdy, dim3(256), lds_y, s, a, z);
     else if (wide)
-        hipLaunchKernelGGL((k_dy<T, false, false, double>), gdy, dim3(256), lds_y, s, a, z);
+        hipLaunchKernelGGL((k_dy<T, false, double>), gdy, dim3(256), lds_y, s, a, z);
     else
-        hipLaunchKernelGGL((k_dy<T, false, false, T>), gdy, dim3(256), lds_y, s, a, z);
+        hipLaunchKernelGGL((k_dy<T, false, T>), gdy, dim3(256), lds_y, s, a, z);
     if (drag)
         hipLaunchKernelGGL(k_spec_finalize, dim3(1), dim3(256), 0, s, (const double*)z.partials,
-                           nyb, z.dv, drag);
+                           nsl, z.dv, drag);
     IBM_HIP(hipGetLastError());
     return IBM_OK;
 }
@@ -456,8 +409,8 @@ size_t spectral_lds_bytes(const ibm_ctx* c, int n, int seqs) {
 }
 
 long spectral_slots(const ibm_ctx* c) {
-    // one per y-pass block and drag component; none for a grid the
-    // transforms refuse (its y pass would have no teams per block)
+    // one per column group of a plane and drag component; none for a grid
+    // the transforms refuse (its y pass would have no teams per block)
     if (!spectral_fits(c)) return 0;
     const int ny = c->g.ny, nx = c->g.nx;
     const int ty = 256 / (ny >= 8 ? ny / 8 : 1);
