@@ -202,7 +202,7 @@ int ensure_twiddles(ibm_ctx* c);          // twiddle tables of nx and ny (first 
 int spectral_check(const ibm_ctx* c);
 // Dynamic LDS bytes of a 256-thread transform block for sequences of n that
 // exchanges ``seqs`` sequences at once.
-size_t spectral_lds_bytes(const ibm_ctx* c, int n, int seqs);
+size_t spectral_lds_bytes(const ibm_ctx* c, int n, int seqs, int threads = 256);
 void free_spectral(ibm_ctx* c);
 
 // projection.hip

@@ -184,8 +184,15 @@ __global__ void __launch_bounds__(256) k_dx(SpecArgs<T> a, ApplyArgs<T> z, unsig
 // a row's columns are read together; sequence tau(c0) + i tau(c0+1) along y.
 // PAIR (nx even, fields aligned to two elements): the two columns of a field
 // move as one access.
+// Threads per y-pass block: in float 16 teams of a 256-point transform, so a
+// block's row segment is a whole 128-byte line of column pairs; in double 8
+// teams already move two lines, and their exchanges fill 64 KiB of LDS at the
+// longest transform.
+template <typename T>
+constexpr int kDyThreads = sizeof(T) == 4 ? 512 : 256;
+
 template <typename T, bool PAIR, typename Acc>
-__global__ void __launch_bounds__(256) k_dy(SpecArgs<T> a, ApplyArgs<T> z) {
+__global__ void __launch_bounds__(kDyThreads<T>) k_dy(SpecArgs<T> a, ApplyArgs<T> z) {
     extern __shared__ unsigned char lds_raw[];
     Cx<T>* xl = reinterpret_cast<Cx<T>*>(lds_raw);
     const int n = a.ny, logn = a.logy;
@@ -256,7 +263,7 @@ __global__ void __launch_bounds__(256) k_dy(SpecArgs<T> a, ApplyArgs<T> z) {
         }
     }
     if (!z.drag) return;
-    __shared__ double red[4];
+    __shared__ double red[kDyThreads<T> / 64];
     const double ws = wave_sum((double)acc);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (lane == 0) red[wv] = ws;
@@ -322,7 +329,7 @@ int spectral_t(ibm_ctx* c, const void* const tau[6], void* const ustar[3],
     a.ky = (T)(2.0 * M_PI / (ny * c->g.dy));
     a.cz = (T)(1.0 / c->g.dz);
     ApplyArgs<T> z = make_apply_args<T>(c, c->cfg, tau, ustar, gradp, dt, div, drag);
-    const int ty = 256 / (ny >= 8 ? ny / 8 : 1);
+    const int ty = kDyThreads<T> / (ny >= 8 ? ny / 8 : 1);
     const int groups = (nx + 2 * ty - 1) / (2 * ty);
     const long nsl = (long)groups * nz;                     // drag slots: one per column group
     const long nyb = 3 * nsl;                               // y-pass blocks: three per group
@@ -341,15 +348,15 @@ int spectral_t(ibm_ctx* c, const void* const tau[6], void* const ustar[3],
     for (int i = 0; i < 3; ++i) aligned = aligned && (uintptr_t)div[i] % (2 * sizeof(T)) == 0;
     const bool wide = c->precision == IBM_PREC_MIXED || sizeof(T) == 8;   // drag in double
     const dim3 gdy((unsigned)(8 * ((nyb + 7) / 8)));     // logical blocks dealt per XCD
-    const size_t lds_y = spectral_lds_bytes(c, ny, 1);
+    const size_t lds_y = spectral_lds_bytes(c, ny, 1, kDyThreads<T>);
     if (aligned && wide)
-        hipLaunchKernelGGL((k_dy<T, true, double>), gdy, dim3(256), lds_y, s, a, z);
+        hipLaunchKernelGGL((k_dy<T, true, double>), gdy, dim3(kDyThreads<T>), lds_y, s, a, z);
     else if (aligned)
-        hipLaunchKernelGGL((k_dy<T, true, T>), gdy, dim3(256), lds_y, s, a, z);
+        hipLaunchKernelGGL((k_dy<T, true, T>), gdy, dim3(kDyThreads<T>), lds_y, s, a, z);
     else if (wide)
-        hipLaunchKernelGGL((k_dy<T, false, double>), gdy, dim3(256), lds_y, s, a, z);
+        hipLaunchKernelGGL((k_dy<T, false, double>), gdy, dim3(kDyThreads<T>), lds_y, s, a, z);
     else
-        hipLaunchKernelGGL((k_dy<T, false, T>), gdy, dim3(256), lds_y, s, a, z);
+        hipLaunchKernelGGL((k_dy<T, false, T>), gdy, dim3(kDyThreads<T>), lds_y, s, a, z);
     if (drag)
         hipLaunchKernelGGL(k_spec_finalize, dim3(1), dim3(256), 0, s, (const double*)z.partials,
                            nsl, z.dv, drag);
@@ -403,9 +410,9 @@ int spectral_check(const ibm_ctx* c) {
     return IBM_OK;
 }
 
-size_t spectral_lds_bytes(const ibm_ctx* c, int n, int seqs) {
+size_t spectral_lds_bytes(const ibm_ctx* c, int n, int seqs, int threads) {
     const size_t cs = c->dtype == IBM_F64 ? 16 : 8;
-    return ((size_t)team_lds_elems(256) * seqs + (size_t)n) * cs;
+    return ((size_t)team_lds_elems(threads) * seqs + (size_t)n) * cs;
 }
 
 long spectral_slots(const ibm_ctx* c) {
@@ -413,7 +420,7 @@ long spectral_slots(const ibm_ctx* c) {
     // the transforms refuse (its y pass would have no teams per block)
     if (!spectral_fits(c)) return 0;
     const int ny = c->g.ny, nx = c->g.nx;
-    const int ty = 256 / (ny >= 8 ? ny / 8 : 1);
+    const int ty = (c->dtype == IBM_F64 ? kDyThreads<double> : kDyThreads<float>) / (ny >= 8 ? ny / 8 : 1);
     return 3L * ((nx + 2 * ty - 1) / (2 * ty)) * c->g.nz;
 }
 
