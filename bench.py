@@ -242,6 +242,30 @@ def _warm(fn, warmup, min_ms=WARM_MS):
         torch.cuda.synchronize()
 
 
+def stream_triad(n=33554432, reps=50):
+    """The GPU's measured streaming rate: torch's c = a + 0.5 b on float32
+    fields of n elements (3 x 134 MB at the default, above the 256 MB
+    Infinity Cache), 12 bytes per element per call, timed over ``reps`` calls
+    after a warm-up."""
+    import torch
+    dev = torch.device("cuda", 0)
+    a = torch.rand(n, device=dev)
+    b = torch.rand(n, device=dev)
+    c = torch.empty_like(a)
+    _warm(lambda: torch.add(a, b, alpha=0.5, out=c), 5)
+    e0, e1 = _events(2)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        torch.add(a, b, alpha=0.5, out=c)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b, c
+    torch.cuda.empty_cache()
+    return 12.0 * n / (ms * 1e-3) / 1e9
+
+
 def _events(n):
     import torch
     return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
@@ -820,6 +844,9 @@ def main():
     value = g.n / (r32["ms_per_step"] * 1e-3)
     b_apply = apply_bytes(wl, r32["mask"], 4)
     achieved = b_apply / (r32["apply_ms"] * 1e-3) / 1e9
+    triad = stream_triad()
+    log(f"stream triad (torch, 3 x 134 MB float32): {triad:.0f} GB/s; k_apply at "
+        f"{achieved / triad * 100:.1f} % of it")
     b_stage = stage_bytes(wl, r32["mask"], 4, r32["gathered"])
     stage_gbs = b_stage / (r32["ms_per_step"] * 1e-3) / 1e9
     out = {
@@ -842,7 +869,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "ibm_apply (k_apply)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(r32["tile"]),
-                     "bytes_per_launch": b_apply, "launch_ms": r32["apply_ms"]},
+                     "bytes_per_launch": b_apply, "launch_ms": r32["apply_ms"],
+                     "stream_triad_GBs": triad, "frac_of_triad": achieved / triad},
         "kernels_ms": {"wall_stress": r32["wall_stress_ms"], "apply": r32["apply_ms"]},
         "stage": {"entry": "ibm_stage (wall stress, dense pass, one launch summing both "
                            "sets of slots)",

@@ -27,10 +27,11 @@
 //          XCD, so the lines they share (tau_yz, the flags) meet in its L2.
 // The y pass with all three sequences in one team needed about 200 registers
 // (two waves per SIMD) and ran at 3.7 TB/s; with one it holds 68 (seven waves)
-// and runs at 4.5.  The x pass, whose three sequences are one stress row
-// each, is faster with all three in one team (225 against 275 us on the
-// 512 x 256 x 256 hill): split, its blocks each stage the twiddles and run
-// two transforms for a third of the data.
+// and, in 512-thread blocks whose row segments are whole cache lines, runs at
+// 5.4 TB/s on the bytes it moves.  The x pass, whose three sequences are one
+// stress row each, is faster with all three in one team (225 against 275 us
+// on the 512 x 256 x 256 hill): split, its blocks each stage the twiddles and
+// run two transforms for a third of the data.
 // Transforms: fft.h (register-resident Stockham passes of radix 8, thread
 // teams of n / 8).
 #include <algorithm>
