@@ -332,9 +332,9 @@ int ibm_autotune(ibm_ctx* c, const char* cache_path, int flags, void* stream);
 
 /* ------------------------------------------------------------- ensembles
  * A batch advances many grids of different sizes together: one step is three
- * persistent kernels (wall stress, dense pass, reductions) over a work list
- * that spans every case, captured once in a hipGraph and replayed by
- * ibm_batch_launch.  Each case computes exactly what ibm_wall_stress followed
+ * kernels (wall stress, dense pass, reductions) whose blocks take items of
+ * work lists that span every case, captured once in a hipGraph and replayed
+ * by ibm_batch_launch.  Each case computes exactly what ibm_wall_stress followed
  * by ibm_apply computes on a context with the same tile shape (bitwise). */
 typedef struct ibm_batch ibm_batch;
 

@@ -359,8 +359,8 @@ class Context:
 
 
 class Batch:
-    """An ensemble of grids advanced together by persistent kernels, one
-    hipGraph launch per step (ibm_batch_*).  Bound tensors are kept alive by
+    """An ensemble of grids advanced together by three kernels whose blocks
+    take work items of every case, one hipGraph launch per step (ibm_batch_*).  Bound tensors are kept alive by
     the batch until they are rebound or the batch is closed."""
 
     def __init__(self, grids, dtype=torch.float32, precision="plain", device=None):

@@ -1,17 +1,17 @@
 // kernels.h -- device code of the stage, shared by the per-case kernels
-// (stage.hip) and the batched persistent kernels (batch.hip), so that a case
-// computed in a batch runs exactly the arithmetic of a plain call.
+// (stage.hip) and the batched kernels (batch.hip), so that a case computed in
+// a batch runs exactly the arithmetic of a plain call.
 //
 // Wall stress (§3.3): one thread per band record.  It gathers u, v on the uv
-// grid and w on the w grid at the record's sample point (trilinear, 24 loads
-// that mostly hit L2), takes the tangential part U_r = u - (u.n) n, and writes
-// tau = -c |U_r| (U_r n^T + n U_r^T) with c = (kappa / ln(phi_c / z0))^2.  That
-// is the rotation tau_ij = a_im a_jn tau'_mn of the local tensor whose only
-// non-zero entries are tau'_13 = tau'_31 = tau_w = -c |U_r|^2 (eq.
-// bc-bottom-immersed), written without forming the frame.  uv records store
-// xx, yy, zz, xy and w records xz, yz (§3.3).  Other blocks zero the stress of
-// the solid nodes of one kSeg-node segment each (§3.3: stress inside the body
-// set to zero): a whole block per segment, its mask bytes read first.
+// grid and w on the w grid at the record's sample point (trilinear, 24 values
+// in 12 x pairs that mostly hit L2), takes the tangential part U_r = u - (u.n)
+// n, and writes tau = -c |U_r| (U_r n^T + n U_r^T) with c = (kappa / ln(phi_c /
+// z0))^2.  That is the rotation tau_ij = a_im a_jn tau'_mn of the local tensor
+// whose only non-zero entries are tau'_13 = tau'_31 = tau_w = -c |U_r|^2 (eq.
+// bc-bottom-immersed), written without forming the frame.  uv records store xx,
+// yy, zz, xy and w records xz, yz (§3.3).  Other blocks zero the stress of the
+// solid nodes of one kSeg-node segment each (§3.3: stress inside the body set
+// to zero): a whole block per segment, its mask bytes read first.
 //
 // Dense pass: one read of the six stress fields and one write of the three
 // divergence components per node (HBM bound, no matrix cores).  A wave owns a
@@ -227,7 +227,6 @@ __device__ inline void ws_block(const WSArgs<T>& a, int b) {
         p[2] = mm;
         p[3] = cc;
     }
-    __syncthreads();   // ``red`` is reused when a persistent block runs the next item
 }
 
 // Fixed-order reduction of per-slot partials (one block): out[c] = scale_c *
