@@ -5,6 +5,9 @@
   forced velocity, drag and band statistics; one case is also held to the
   oracle; also a batch of one-column, one-row, one- and two-plane and ragged
   cases;
+* seeded random ensembles (random grids, degenerate ones among them, and
+  random tile shapes): every case bit for bit against plain calls, eager and
+  through a captured graph, the largest against the oracle;
 * the 64-case ensemble the benchmark times (105.6 M points, one graph
   launch): all 64 cases bit for bit against plain per-case calls, one case
   of each grid shape and the last case against the oracle, every node;
@@ -282,6 +285,66 @@ def test_degenerate_cases(ora, dtype, prec):
                ustar=fs[5].ustar.cpu().numpy(), drag=fs[5].drag.cpu().numpy(),
                stats=fs[5].stats.cpu().numpy(), mask=b.case(5).mask(), counts=b.case(5).counts())
     compare(out, ref, wls[5], TOL[dtype])
+
+
+def _random_ensemble(seed, dtype):
+    """Seeded random ensemble: 6-10 cases of random shapes (a few degenerate:
+    one row, one column, one or two planes), bump terrains or flat walls, and
+    random tile shapes (vx > 1 only where the row splits into whole vectors
+    and the stacked fields stay 16-byte aligned)."""
+    rng = np.random.Generator(np.random.PCG64(200603343 + 77 + seed))
+    ncase = int(rng.integers(6, 11))
+    wls, tiles = [], []
+    for i in range(ncase):
+        if rng.random() < 0.3:
+            shape = (int(rng.integers(1, 90)), int(rng.integers(1, 6)), int(rng.integers(1, 12)))
+            wl = configs.flat(Grid(*shape), float(rng.choice([1.0, 1.25, 1.5, 1.75])), theta=0.4,
+                              z0=1e-3, noise=0.3, tau_std=0.01, gp_std=0.1, seed=seed * 100 + i)
+        else:
+            shape = (int(rng.integers(8, 140)), int(rng.integers(4, 48)), int(rng.integers(6, 40)))
+            wl = configs.bumps_case(1000 + 100 * seed + i, shape)
+        wls.append(wl.cast(np.float32) if dtype == "f32" else wl)
+        n = shape[0] * shape[1] * shape[2]
+        vmax, item = (4, 4) if dtype == "f32" else (2, 8)
+        # vx > 1 needs each stacked stress and divergence component 16-byte aligned
+        vx = int(rng.choice([v for v in (1, 2, 4)
+                             if v <= vmax and shape[0] % v == 0 and (v == 1 or n * item % 16 == 0)]))
+        tiles.append((vx, int(rng.choice([1, 2])), int(rng.integers(1, 33)), 1))
+    return wls, tiles
+
+
+@pytest.mark.parametrize("seed,dtype,prec", [(0, "f32", "mixed"), (1, "f32", "mixed"),
+                                             (2, "f64", "plain")])
+def test_random_ensembles_equal_plain_calls(ora, seed, dtype, prec):
+    """Batches of random grids and tile shapes (uneven work items, slices of
+    very different lengths, cases with and without forcing): every case equals
+    its plain per-case calls bit for bit, after the eager run and after a
+    captured graph's launch; the largest case also against the oracle."""
+    torch, dev = torch_dev()
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    wls, tiles = _random_ensemble(seed, dtype)
+    shapes = [(w.grid.nx, w.grid.ny, w.grid.nz) for w in wls]
+    _say(f"random ensemble seed {seed} {dtype} {prec}: {list(zip(shapes, tiles))}")
+    b, fs = _batch(wls, tiles, tdt, prec, dev)
+    plain = [_plain(w, tiles[i], tdt, prec, dev) for i, w in enumerate(wls)]
+    b.run()
+    torch.cuda.synchronize()
+    for i, f in enumerate(fs):
+        _same(f.snapshot(), plain[i], f"eager case {i} {shapes[i]} tile {tiles[i]}")
+    for f in fs:
+        f.reset()
+    b.capture()
+    b.launch()
+    torch.cuda.synchronize()
+    for i, f in enumerate(fs):
+        _same(f.snapshot(), plain[i], f"graph case {i} {shapes[i]} tile {tiles[i]}")
+    big = int(np.argmax([np.prod(s) for s in shapes]))
+    ref = ora.stage(wls[big])
+    out = dict(tau=fs[big].tau.cpu().numpy(), div=fs[big].div.cpu().numpy(),
+               ustar=fs[big].ustar.cpu().numpy(), drag=fs[big].drag.cpu().numpy(),
+               stats=fs[big].stats.cpu().numpy(), mask=b.case(big).mask(),
+               counts=b.case(big).counts())
+    compare(out, ref, wls[big], TOL[dtype])
 
 
 def test_ensemble_full_size(ora, tmp_path):
