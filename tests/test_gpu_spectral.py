@@ -6,7 +6,8 @@ float64, 2e-5 for float32; masks and forcing exact).  The SGS stress inputs
 are white noise, so every case carries Nyquist-mode content: a leak of one
 packed field's Nyquist term into the other would show.  Cases: the cube,
 small hills in three precisions, per-node log z0, grids with one row, one
-column, one plane and two nodes, the 512 x 256 x 256 hill, fields one
+column, one plane and two nodes (float64, and in float32 with the y pass's
+512-thread blocks on uneven team layouts), the 512 x 256 x 256 hill, fields one
 element into their buffers (float32: the y pass then takes one column per
 access instead of 8-byte column pairs), the longest transforms along x and
 along y in both precisions, 2048 x 2048 x 511 (near the 2^31 - 1 node limit
@@ -66,6 +67,21 @@ def test_degenerate_grids(ora):
         _say(f"spectral flat {shape} f64")
         out, _ = run_gpu(wl, "f64", spectral=True)
         compare(out, _ref(ora, wl), wl, TOL["f64"])
+
+
+@pytest.mark.parametrize("shape", [(2, 256, 5), (4, 64, 7), (128, 2, 6), (8, 1024, 3),
+                                   (1024, 8, 3), (2, 1, 5), (1, 4, 6), (16, 8, 1)])
+def test_float_team_layouts(ora, shape):
+    """Float32 mixed on grids whose 512-thread y blocks hold a few columns of
+    many teams, many columns of few teams, or columns beyond the grid (nx of
+    1 or 2 against 16 teams), and x transforms of 1 to 1024 points."""
+    g = Grid(*shape)
+    wl = configs.flat(g, 1.25, theta=0.4, z0=1e-3, noise=0.2, tau_std=0.01, gp_std=0.1,
+                      seed=shape[0] + 10 * shape[1]).cast(np.float32)
+    _say(f"spectral flat {shape} f32 mixed")
+    out, _ = run_gpu(wl, "f32", "mixed", spectral=True)
+    errs = compare(out, _ref(ora, wl), wl, TOL["f32"])
+    _say(f"errors {errs}")
 
 
 def test_misaligned_views(ora):
