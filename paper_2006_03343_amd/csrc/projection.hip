@@ -152,6 +152,36 @@ __global__ void __launch_bounds__(256) k_rows_inv(ProjArgs<T> a) {
     const long r0 = 2 * ((long)blockIdx.x * teams + team);
     const bool in0 = r0 < a.rows, in1 = r0 + 1 < a.rows;
     const Cx<T>* __restrict__ A = a.spec[kind < 2 ? 0 : kind - 1];
+    // Slots above nx / 2 hold the conjugates of slots below it.  When a team's
+    // threads lie in one wave (8 <= nx <= 512) they come from the mirror thread
+    // P - j, slot 7 - u, through a lane permutation (thread 0 holds its own
+    // mirror, in slot 8 - u) instead of a second load of the same lines.
+    const bool wave_team = n >= 8 && P <= 64;
+    Cx<T> ra[8], rb[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        ra[u] = rb[u] = Cx<T>{T(0), T(0)};
+        if (u >= ns) continue;
+        const int e = tm.elem(u);
+        const bool upper = 2 * e > n;
+        if (upper && wave_team) continue;
+        const int m = upper ? n - e : e;
+        if (in0) ra[u] = A[r0 * a.nhp + m];
+        if (in1) rb[u] = A[(r0 + 1) * a.nhp + m];
+    }
+    if (wave_team) {
+        const int lane = (int)threadIdx.x & 63;
+        const int src = lane - tm.j + ((P - tm.j) & (P - 1));
+#pragma unroll
+        for (int u = 4; u < 8; ++u) {
+            const Cx<T> ma{__shfl(ra[7 - u].re, src), __shfl(ra[7 - u].im, src)};
+            const Cx<T> mb{__shfl(rb[7 - u].re, src), __shfl(rb[7 - u].im, src)};
+            if (2 * tm.elem(u) > n) {
+                ra[u] = tm.j == 0 ? ra[8 - u] : ma;
+                rb[u] = tm.j == 0 ? rb[8 - u] : mb;
+            }
+        }
+    }
     Cx<T> v[1][8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -160,8 +190,8 @@ __global__ void __launch_bounds__(256) k_rows_inv(ProjArgs<T> a) {
         const int e = tm.elem(u);
         const bool upper = 2 * e > n;
         const int m = upper ? n - e : e;
-        Cx<T> za = in0 ? A[r0 * a.nhp + m] : Cx<T>{T(0), T(0)};
-        Cx<T> zb = in1 ? A[(r0 + 1) * a.nhp + m] : Cx<T>{T(0), T(0)};
+        Cx<T> za = ra[u];
+        Cx<T> zb = rb[u];
         if (m == 0 || 2 * m == n) {
             za.im = T(0);
             zb.im = T(0);

@@ -63,6 +63,12 @@ def _project(g, vel, dt, dtype, in_place=False):
                                             ((32, 16, 12), (1.0, 1.0, 1.0), "f32"),
                                             ((4, 2, 1), (1.0, 1.0, 1.0), "f64"),
                                             ((1, 8, 5), (1.0, 1.0, 1.0), "f64"),
+                                            # x teams within one wave, the mirror
+                                            # slots by lane permutation: the
+                                            # shortest and the longest such rows
+                                            ((8, 16, 4), (1.0, 1.0, 1.0), "f32"),
+                                            ((256, 8, 5), (0.9, 1.1, 1.0), "f32"),
+                                            ((512, 4, 3), (1.0, 1.0, 1.0), "f64"),
                                             # the longest transforms each type takes
                                             ((2048, 4, 3), (1.0, 1.0, 1.0), "f32"),
                                             ((4, 2048, 3), (1.0, 1.0, 1.0), "f32"),
