@@ -137,49 +137,48 @@ __global__ void __launch_bounds__(256) k_rows_fwd(ProjArgs<T> a) {
 // w = 0 on the two wall planes.  One transform per team keeps the registers, and with them
 // the waves per SIMD, of the forward x pass (two per team measured slower
 // despite reading P once).
-template <typename T>
+template <typename T, bool WT>
 __global__ void __launch_bounds__(256) k_rows_inv(ProjArgs<T> a) {
     extern __shared__ unsigned char lds_raw[];
     Cx<T>* xl = reinterpret_cast<Cx<T>*>(lds_raw);
     const int n = a.nx, logn = a.logx;
-    const int P = n >= 8 ? n >> 3 : 1, ns = n >= 8 ? 8 : n;
+    const int P = n >= 8 ? n >> 3 : 1, ns = WT ? 8 : n >= 8 ? 8 : n;
     const int teams = (int)blockDim.x / P;
     Cx<T>* tw = xl + team_lds_elems(blockDim.x);
-    stage_twiddles(tw, a.twx, n);
     const int team = (int)threadIdx.x / P;
     const Team tm = make_team(logn, (int)threadIdx.x - team * P, team, teams, false);
     const int kind = (int)blockIdx.y;
     const long r0 = 2 * ((long)blockIdx.x * teams + team);
     const bool in0 = r0 < a.rows, in1 = r0 + 1 < a.rows;
+    // rows past the end read the last row (in bounds, never stored): every load
+    // is unconditional, so all of a thread's loads are in flight at once
+    const long ca = in0 ? r0 : a.rows - 1, cb = in1 ? r0 + 1 : a.rows - 1;
     const Cx<T>* __restrict__ A = a.spec[kind < 2 ? 0 : kind - 1];
-    // Slots above nx / 2 hold the conjugates of slots below it.  When a team's
-    // threads lie in one wave (8 <= nx <= 512) they come from the mirror thread
-    // P - j, slot 7 - u, through a lane permutation (thread 0 holds its own
-    // mirror, in slot 8 - u) instead of a second load of the same lines.
-    const bool wave_team = n >= 8 && P <= 64;
+    // Slots above nx / 2 hold the conjugates of slots below it.  WT (a team's
+    // threads lie in one wave, 8 <= nx <= 512): slots 5 .. 7 come from the
+    // mirror thread P - j, slot 7 - u, through a lane permutation (thread 0
+    // holds its own mirror, in slot 8 - u) instead of a second load of the
+    // same lines.
     Cx<T> ra[8], rb[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
         ra[u] = rb[u] = Cx<T>{T(0), T(0)};
-        if (u >= ns) continue;
+        if (u >= ns || (WT && u > 4)) continue;
         const int e = tm.elem(u);
-        const bool upper = 2 * e > n;
-        if (upper && wave_team) continue;
-        const int m = upper ? n - e : e;
-        if (in0) ra[u] = A[r0 * a.nhp + m];
-        if (in1) rb[u] = A[(r0 + 1) * a.nhp + m];
+        const int m = 2 * e > n ? n - e : e;
+        ra[u] = A[ca * a.nhp + m];
+        rb[u] = A[cb * a.nhp + m];
     }
-    if (wave_team) {
+    stage_twiddles(tw, a.twx, n);
+    if constexpr (WT) {
         const int lane = (int)threadIdx.x & 63;
         const int src = lane - tm.j + ((P - tm.j) & (P - 1));
 #pragma unroll
-        for (int u = 4; u < 8; ++u) {
+        for (int u = 5; u < 8; ++u) {
             const Cx<T> ma{__shfl(ra[7 - u].re, src), __shfl(ra[7 - u].im, src)};
             const Cx<T> mb{__shfl(rb[7 - u].re, src), __shfl(rb[7 - u].im, src)};
-            if (2 * tm.elem(u) > n) {
-                ra[u] = tm.j == 0 ? ra[8 - u] : ma;
-                rb[u] = tm.j == 0 ? rb[8 - u] : mb;
-            }
+            ra[u] = tm.j == 0 ? ra[8 - u] : ma;
+            rb[u] = tm.j == 0 ? rb[8 - u] : mb;
         }
     }
     Cx<T> v[1][8];
@@ -190,8 +189,8 @@ __global__ void __launch_bounds__(256) k_rows_inv(ProjArgs<T> a) {
         const int e = tm.elem(u);
         const bool upper = 2 * e > n;
         const int m = upper ? n - e : e;
-        Cx<T> za = ra[u];
-        Cx<T> zb = rb[u];
+        Cx<T> za = in0 ? ra[u] : Cx<T>{T(0), T(0)};
+        Cx<T> zb = in1 ? rb[u] : Cx<T>{T(0), T(0)};
         if (m == 0 || 2 * m == n) {
             za.im = T(0);
             zb.im = T(0);
@@ -210,9 +209,20 @@ __global__ void __launch_bounds__(256) k_rows_inv(ProjArgs<T> a) {
     }
     __syncthreads();   // twiddles staged
     team_ifft<T, 1>(v, tm, xl, tw);
-    const T* base = kind == 1 ? a.ub : kind == 2 ? a.vb : a.wb;
     T* out = kind == 0 ? a.po : kind == 1 ? a.uo : kind == 2 ? a.vo : a.wo;
     const T s = kind == 0 ? T(1) / T(n) : kind < 3 ? -a.c / T(n) : -a.c / (T(n) * a.dzs);
+    // the bases of the corrections, all loads issued before the first store
+    T b0[8], b1[8];
+    if (kind) {
+        const T* __restrict__ base = kind == 1 ? a.ub : kind == 2 ? a.vb : a.wb;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            b0[u] = b1[u] = T(0);
+            if (u >= ns) continue;
+            b0[u] = base[ca * n + tm.elem(u)];
+            b1[u] = base[cb * n + tm.elem(u)];
+        }
+    }
     // rows are (k, j) pairs, k = r / ny: the w nodes on the floor and the lid are walls
     const long lid = (long)(a.nz - 1) * a.ny;
     const bool wall0 = kind == 3 && (r0 < a.ny || r0 >= lid);
@@ -222,8 +232,8 @@ __global__ void __launch_bounds__(256) k_rows_inv(ProjArgs<T> a) {
         if (u >= ns) continue;
         const long o = r0 * n + tm.elem(u);
         const T va = v[0][u].re * s, vb = v[0][u].im * s;
-        if (in0) out[o] = wall0 ? T(0) : kind ? base[o] + va : va;
-        if (in1) out[o + n] = wall1 ? T(0) : kind ? base[o + n] + vb : vb;
+        if (in0) out[o] = wall0 ? T(0) : kind ? b0[u] + va : va;
+        if (in1) out[o + n] = wall1 ? T(0) : kind ? b1[u] + vb : vb;
     }
 }
 
@@ -637,7 +647,12 @@ int project_t(ibm_ctx* c, const void* const ustar[3], double dt, void* const uo[
                        dim3(2 * kSolveModes), 0, s, a);
     hipLaunchKernelGGL(k_cols_inv<T>, dim3(gy), dim3(256), spectral_lds_bytes(c, a.ny, 1), s, a);
     // p, u = u* - c d/dx p, v = v* - c d/dy p, w = w* - c (p[k] - p[k-1]) / dz
-    hipLaunchKernelGGL(k_rows_inv<T>, dim3(gx, 4), dim3(256), spectral_lds_bytes(c, a.nx, 1), s, a);
+    if (a.nx >= 8 && a.nx <= 512)
+        hipLaunchKernelGGL((k_rows_inv<T, true>), dim3(gx, 4), dim3(256),
+                           spectral_lds_bytes(c, a.nx, 1), s, a);
+    else
+        hipLaunchKernelGGL((k_rows_inv<T, false>), dim3(gx, 4), dim3(256),
+                           spectral_lds_bytes(c, a.nx, 1), s, a);
     IBM_HIP(hipGetLastError());
     return IBM_OK;
 }
