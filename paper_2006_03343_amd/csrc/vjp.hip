@@ -62,7 +62,8 @@ struct BandArgs {
     long nb;                   // band nodes
     long nuv;                  // uv records (the w records follow them in rbar)
     const T *u, *v, *w, *log_z0;
-    const T* g_tau[6];
+    const T* g_tau[6];         // with HAS_GT: g_div[0] in place of a null entry (never used)
+    unsigned gt_mask;          // bit i: g_tau[i] was given
     const T* g_div[3];
     const uint32_t* fmask;
     int nx, ny, nz, wrow;
@@ -82,14 +83,17 @@ struct BandArgs {
 // offsets: a context holds fewer than 2^31 nodes.
 template <typename T>
 __device__ inline T gbar(const BandArgs<T>& a, int c, int ii, int jj, int k) {
-    if (k < 0 || k >= a.nz) return T(0);
-    const int row = k * a.ny + jj;
+    // outside the planes the loads read plane 0 (in bounds) and the value is
+    // dropped: no branch around the loads, so the compiler issues all of a
+    // record's loads before waiting on any
+    const bool in = k >= 0 && k < a.nz;
+    const int row = (in ? k : 0) * a.ny + jj;
     const int q = row * a.nx + ii;
     const uint32_t fb = a.fmask[row * a.wrow + (ii >> 4)] >> (2 * (ii & 15));
     const bool forced = (c < 2) ? (fb & 1u) : (fb & 2u);
     T g = a.g_div[c][q];
     if (!forced) g += (T)(a.dv * a.gdrag[c]);
-    return g;
+    return in ? g : T(0);
 }
 
 // f[off], f[off + sx]: one load of both where they are contiguous (sx = 1),
@@ -128,7 +132,19 @@ __device__ inline T trilerp_xpair(const T* __restrict__ f, int c00, int c01, int
 
 // The reverse of one band record of node set ``kind``: writes its sample
 // cotangent into rbar and returns its log z0 cotangent (0 without a field).
-template <typename T, bool HAS_LZ>
+// The g_tau cotangent of component i at node q (0 without one): loaded
+// unconditionally when any is given, so no branch separates the loads.
+template <typename T, bool HAS_GT>
+__device__ inline T gtau(const BandArgs<T>& a, int i, int q) {
+    if constexpr (!HAS_GT) {
+        return T(0);
+    } else {
+        const T g = a.g_tau[i][q];
+        return (a.gt_mask >> i) & 1u ? g : T(0);
+    }
+}
+
+template <typename T, bool HAS_LZ, bool HAS_GT>
 __device__ inline T band_record(const BandArgs<T>& a, int kind, long r) {
     const RecView<T>& R = a.recs[kind];
     const int q = R.q[r];
@@ -167,13 +183,13 @@ __device__ inline T band_record(const BandArgs<T>& a, int kind, long r) {
     // stress cotangent at this node for the components the record stores
     T S, P0, P1, P2;
     if (kind == IBM_GRID_UV) {
-        const T txx = (a.g_tau[0] ? a.g_tau[0][q] : T(0)) -
+        const T txx = gtau<T, HAS_GT>(a, 0, q) -
                       (gbar(a, 0, ip, j, k) - gbar(a, 0, im, j, k)) * a.cx;
-        const T tyy = (a.g_tau[1] ? a.g_tau[1][q] : T(0)) -
+        const T tyy = gtau<T, HAS_GT>(a, 1, q) -
                       (gbar(a, 1, i, jp, k) - gbar(a, 1, i, jm, k)) * a.cy;
-        const T tzz = (a.g_tau[2] ? a.g_tau[2][q] : T(0)) +
+        const T tzz = gtau<T, HAS_GT>(a, 2, q) +
                       (gbar(a, 2, i, j, k) - gbar(a, 2, i, j, k + 1)) * a.cz;
-        const T txy = (a.g_tau[3] ? a.g_tau[3][q] : T(0)) -
+        const T txy = gtau<T, HAS_GT>(a, 3, q) -
                       (gbar(a, 0, i, jp, k) - gbar(a, 0, i, jm, k)) * a.cy -
                       (gbar(a, 1, ip, j, k) - gbar(a, 1, im, j, k)) * a.cx;
         S = txx * (T(2) * ur0 * n0) + tyy * (T(2) * ur1 * n1) + tzz * (T(2) * ur2 * n2) +
@@ -182,10 +198,10 @@ __device__ inline T band_record(const BandArgs<T>& a, int kind, long r) {
         P1 = tyy * (T(2) * n1) + txy * n0;
         P2 = tzz * (T(2) * n2);
     } else {
-        const T txz = (a.g_tau[4] ? a.g_tau[4][q] : T(0)) -
+        const T txz = gtau<T, HAS_GT>(a, 4, q) -
                       (gbar(a, 2, ip, j, k) - gbar(a, 2, im, j, k)) * a.cx +
                       (gbar(a, 0, i, j, k - 1) - gbar(a, 0, i, j, k)) * a.cz;
-        const T tyz = (a.g_tau[5] ? a.g_tau[5][q] : T(0)) -
+        const T tyz = gtau<T, HAS_GT>(a, 5, q) -
                       (gbar(a, 2, i, jp, k) - gbar(a, 2, i, jm, k)) * a.cy +
                       (gbar(a, 1, i, j, k - 1) - gbar(a, 1, i, j, k)) * a.cz;
         S = txz * (ur0 * n2 + n0 * ur2) + tyz * (ur1 * n2 + n1 * ur2);
@@ -217,7 +233,7 @@ __device__ inline T band_record(const BandArgs<T>& a, int kind, long r) {
 // One thread per band node: its uv record, then its w record; the log z0
 // cotangent of the node is 0 (the dense pass) + the uv record's + the w
 // record's, in that order.
-template <typename T, bool HAS_LZ>
+template <typename T, bool HAS_LZ, bool HAS_GT>
 __global__ void __launch_bounds__(256) k_vjp_band(BandArgs<T> a) {
     const long b = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= a.nb) return;
@@ -225,11 +241,11 @@ __global__ void __launch_bounds__(256) k_vjp_band(BandArgs<T> a) {
     T gl = T(0);
     int q = 0;
     if (ruv >= 0) {
-        gl = gl + band_record<T, HAS_LZ>(a, IBM_GRID_UV, ruv);
+        gl = gl + band_record<T, HAS_LZ, HAS_GT>(a, IBM_GRID_UV, ruv);
         q = a.recs[0].q[ruv];
     }
     if (rw >= 0) {
-        gl = gl + band_record<T, HAS_LZ>(a, IBM_GRID_W, rw);
+        gl = gl + band_record<T, HAS_LZ, HAS_GT>(a, IBM_GRID_W, rw);
         q = a.recs[1].q[rw];
     }
     if (HAS_LZ && a.glz) a.glz[q] = gl;
@@ -430,7 +446,11 @@ int vjp_t(ibm_ctx* c, const T* u, const T* v, const T* w, double z0, const T* lo
     a.v = v;
     a.w = w;
     a.log_z0 = log_z0;
-    for (int i = 0; i < 6; ++i) a.g_tau[i] = g_tau ? (const T*)g_tau[i] : nullptr;
+    a.gt_mask = 0;
+    for (int i = 0; i < 6; ++i) {
+        a.g_tau[i] = g_tau ? (const T*)g_tau[i] : nullptr;
+        if (a.g_tau[i]) a.gt_mask |= 1u << i;
+    }
     for (int i = 0; i < 3; ++i) {
         a.g_div[i] = (const T*)g_div[i];
         a.gdrag[i] = g_drag[i];
@@ -459,10 +479,19 @@ int vjp_t(ibm_ctx* c, const T* u, const T* v, const T* w, double z0, const T* lo
     a.nb = c->adj.nb;
     a.nuv = nuv;
     if (a.nb) {
-        if (log_z0)
-            hipLaunchKernelGGL((k_vjp_band<T, true>), dim3(nblk(a.nb, 256)), dim3(256), 0, s, a);
-        else
-            hipLaunchKernelGGL((k_vjp_band<T, false>), dim3(nblk(a.nb, 256)), dim3(256), 0, s, a);
+        const dim3 gb(nblk(a.nb, 256));
+        if (a.gt_mask) {
+            for (int i = 0; i < 6; ++i)
+                if (!a.g_tau[i]) a.g_tau[i] = a.g_div[0];   // read, never used
+            if (log_z0)
+                hipLaunchKernelGGL((k_vjp_band<T, true, true>), gb, dim3(256), 0, s, a);
+            else
+                hipLaunchKernelGGL((k_vjp_band<T, false, true>), gb, dim3(256), 0, s, a);
+        } else if (log_z0) {
+            hipLaunchKernelGGL((k_vjp_band<T, true, false>), gb, dim3(256), 0, s, a);
+        } else {
+            hipLaunchKernelGGL((k_vjp_band<T, false, false>), gb, dim3(256), 0, s, a);
+        }
     }
     GatherArgs<T> ga;
     ga.ntot = ntot;

@@ -80,6 +80,15 @@ def test_vjp_f64_matches_oracle(ora):
     errs = [normwise(a.cpu().numpy(), b) for a, b in zip((gu, gv, gw, glz), ref)]
     _say(f"normwise errors gu gv gw glog_z0: {errs}")
     assert max(errs) <= 1e-11, errs
+    # some stress cotangents given, the others NULL (= 0): one of each node set missing
+    part = [g if i not in (1, 4) else None for i, g in enumerate(g_tau)]
+    gu, gv, gw, glz = st.ctx.vjp(u, v, w, [T(a) for a in g_div], [T(a) for a in g_us], g_drag,
+                                 log_z0=lz,
+                                 g_tau=[None if a is None else T(a) for a in part])
+    ref = ora.stage_vjp(wl, part, g_div, g_us, g_drag)
+    errs = [normwise(a.cpu().numpy(), b) for a, b in zip((gu, gv, gw, glz), ref)]
+    _say(f"g_tau[1], g_tau[4] NULL: {errs}")
+    assert max(errs) <= 1e-11, errs
     # scalar z0, no log z0 field and no stress cotangent
     wl2 = configs.cube(32, 16, 16)
     st2 = Stage(wl2, "f64")
