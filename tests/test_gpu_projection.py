@@ -69,6 +69,11 @@ def _project(g, vel, dt, dtype, in_place=False):
                                             ((8, 16, 4), (1.0, 1.0, 1.0), "f32"),
                                             ((256, 8, 5), (0.9, 1.1, 1.0), "f32"),
                                             ((512, 4, 3), (1.0, 1.0, 1.0), "f64"),
+                                            # an odd number of x rows (ny = 1): the
+                                            # last row pair has one row, and teams
+                                            # past the end read clamped rows
+                                            ((64, 1, 5), (1.0, 1.0, 1.0), "f32"),
+                                            ((512, 1, 7), (1.0, 1.0, 1.3), "f64"),
                                             # the longest transforms each type takes
                                             ((2048, 4, 3), (1.0, 1.0, 1.0), "f32"),
                                             ((4, 2048, 3), (1.0, 1.0, 1.0), "f32"),
